@@ -1,0 +1,86 @@
+"""Checks of the seeded problem generator (no VV10 arithmetic here)."""
+import numpy as np
+import pytest
+
+from paper_2208_14639_amd import inputs
+
+
+def test_deterministic_by_seed():
+    a = inputs.make_problem(2, 20, 5)
+    b = inputs.make_problem(2, 20, 5)
+    c = inputs.make_problem(2, 20, 6)
+    assert np.array_equal(a.coords, b.coords) and np.array_equal(a.rho_x, b.rho_x)
+    assert not np.array_equal(a.coords, c.coords)
+
+
+def test_shapes_and_ordering(small_dimer):
+    p = small_dimer
+    assert p.n_grid == 360 and p.n_pert == 18
+    assert p.rho_x.shape == (18, 360) and p.grad_rho_x.shape == (18, 360, 3)
+    assert np.all(np.diff(p.atom_of) >= 0)
+    assert np.all(p.weights > 0) and np.all(p.rho > 0)
+    r = np.linalg.norm(p.coords - p.mol.R[p.atom_of], axis=1)
+    assert np.all(r >= inputs.R_MIN * (1 - 1e-12)) and np.all(r <= inputs.R_MAX * (1 + 1e-12))
+
+
+def test_water_geometry():
+    rng = np.random.default_rng(3)
+    m = inputs.water_cluster(6, rng)
+    ang = inputs.BOHR_PER_ANGSTROM
+    for k in range(6):
+        O, H1, H2 = m.R[3 * k:3 * k + 3]
+        assert abs(np.linalg.norm(H1 - O) - 0.96 * ang) < 1e-12
+        cosang = np.dot(H1 - O, H2 - O) / np.linalg.norm(H1 - O) / np.linalg.norm(H2 - O)
+        assert abs(np.degrees(np.arccos(cosang)) - 104.5) < 1e-9
+    Os = m.R[0::3]
+    d = np.linalg.norm(Os[:, None] - Os[None], axis=2) + np.eye(6) * 100
+    assert d.min() >= 2.6 * ang - 1e-9
+
+
+def test_weights_integrate_density():
+    """Monte-Carlo estimate of the electron count: sum_i w_i rho_i ~ 20 for a dimer."""
+    p = inputs.make_workload("water_dimer", with_derivatives=False)
+    n_el = float(np.dot(p.weights, p.rho))
+    assert 10.0 < n_el < 30.0
+
+
+def test_gradient_matches_fd(small_dimer):
+    p = small_dimer
+    h = 1e-5
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = h
+        rp, _, _ = inputs.model_density(p.mol, p.coords + e)
+        rm, _, _ = inputs.model_density(p.mol, p.coords - e)
+        fd = (rp - rm) / (2 * h)
+        assert np.max(np.abs(fd - p.grad_rho[:, a]) / (np.abs(p.grad_rho[:, a]) + p.rho)) < 1e-6
+
+
+def test_nuclear_derivatives_match_fd(small_dimer):
+    """rho^x and (grad rho)^x are total derivatives with the grid moving with its owner."""
+    p = small_dimer
+    h = 1e-5
+    for x in (0, 4, 8, 13, 17):
+        A, a = divmod(x, 3)
+        qp = inputs.displaced(p, A, a, h)
+        qm = inputs.displaced(p, A, a, -h)
+        fd = (qp.rho - qm.rho) / (2 * h)
+        scale = np.abs(p.rho_x[x]) + p.rho
+        assert np.max(np.abs(fd - p.rho_x[x]) / scale) < 1e-6
+        fdg = (qp.grad_rho - qm.grad_rho) / (2 * h)
+        scale = np.abs(p.grad_rho_x[x]) + p.rho[:, None]
+        assert np.max(np.abs(fdg - p.grad_rho_x[x]) / scale) < 1e-5
+
+
+def test_translational_invariance_of_derivatives(small_dimer):
+    p = small_dimer
+    s = p.rho_x.reshape(p.n_atom, 3, -1).sum(axis=0)
+    assert np.max(np.abs(s)) < 1e-10 * np.max(np.abs(p.rho_x))
+    sg = p.grad_rho_x.reshape(p.n_atom, 3, p.n_grid, 3).sum(axis=0)
+    assert np.max(np.abs(sg)) < 1e-10 * np.max(np.abs(p.grad_rho_x))
+
+
+@pytest.mark.parametrize("name,n,P", [("water_dimer", 4200, 18), ("water_hexamer", 27000, 54)])
+def test_workload_sizes(name, n, P):
+    p = inputs.make_workload(name, with_derivatives=False)
+    assert p.n_grid == n and p.n_pert == P

@@ -1,0 +1,369 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Every check here is independent of the oracle's own code path: closed forms
+derived by hand, the uniform-density condition that defines beta, brute force
+on tiny inputs, finite differences of lower-order oracle outputs, and exact
+invariances (symmetry, translational invariance).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2208_14639_amd import inputs
+
+B6, C01 = 6.0, 0.01
+
+
+def fd(f, h):
+    return (f(h) - f(-h)) / (2 * h)
+
+
+def richardson(f, h):
+    """Central difference with one Richardson step (error O(h^4))."""
+    return (4 * fd(f, h / 2) - fd(f, h)) / 3
+
+
+def _ep(p, rho=None, gam=None, coords=None):
+    g = oracle.gamma(p.grad_rho) if gam is None else gam
+    return oracle.energy_potential(p.coords if coords is None else coords, p.weights,
+                                   p.rho if rho is None else rho, g, p.b, p.C)
+
+
+# --------------------------------------------------------------------------
+# Per-point quantities: kappa, omega, beta (Section II.A)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("b", [5.9, 6.0, 6.3])
+@pytest.mark.parametrize("rho", [1e-3, 0.1, 3.0])
+def test_beta_uniform_gas_closed_form(b, rho):
+    """beta makes the energy vanish for uniform density.  With gamma = 0,
+    int Phi d^3R = -(3 pi^2/16)(kappa omega)^{-3/2} (hand integral of
+    -3/(4 g^3), g = omega R^2 + kappa), so beta = (3 pi^2/32) rho (kappa omega)^{-3/2}
+    must hold for every rho.  Pins omega's rho-dependence, kappa and beta together."""
+    q = oracle.point(b, C01, rho, 0.0)
+    want = 3 * math.pi ** 2 / 32 * rho * (q["kappa"] * q["omega"]) ** -1.5
+    assert abs(oracle.beta(b) - want) < 1e-14 * want
+
+
+def test_beta_value_b6():
+    # (1/32)(3/36)^{3/4} evaluated independently.
+    assert abs(oracle.beta(6.0) - 0.0048469003078234355) < 1e-17
+
+
+def test_kappa_special_values():
+    # kappa = b (3 pi/2) (rho/9 pi)^{1/6}: at rho = 9 pi it is 3 pi b/2, and it scales as rho^{1/6}.
+    q = oracle.point(6.0, C01, 9 * math.pi, 0.0)
+    assert abs(q["kappa"] - 9 * math.pi) < 1e-13
+    k1 = oracle.point(6.0, C01, 0.01, 0.0)["kappa"]
+    k64 = oracle.point(6.0, C01, 0.64, 0.0)["kappa"]
+    assert abs(k64 / k1 - 2.0) < 1e-14
+
+
+@pytest.mark.parametrize("zeta", [0.7, 1.0, 2.0])
+@pytest.mark.parametrize("rho", [1e-6, 0.02, 5.0])
+def test_omega_for_exponential_density(zeta, rho):
+    """For rho ~ exp(-2 zeta r), |grad rho|/rho = 2 zeta everywhere, so the
+    gradient part of omega^2 is C (2 zeta)^4 independent of rho."""
+    gam = (2 * zeta * rho) ** 2
+    q = oracle.point(B6, C01, rho, gam)
+    assert abs(q["omega"] ** 2 - 4 * math.pi * rho / 3 - C01 * (2 * zeta) ** 4) < 1e-12 * q["omega"] ** 2
+
+
+def test_point_partials_fd():
+    """First and second partials of omega and kappa against finite differences."""
+    for rho, gam in [(0.3, 0.05), (2e-4, 1e-7), (4.0, 30.0)]:
+        q = oracle.point(B6, C01, rho, gam)
+        hr, hg = 1e-4 * rho, 1e-4 * gam
+        d = lambda key, dr, dg: (oracle.point(B6, C01, rho + dr, gam + dg)[key]
+                                 - oracle.point(B6, C01, rho - dr, gam - dg)[key])
+        assert abs(d("omega", hr, 0) / (2 * hr) - q["omega_r"]) < 1e-6 * abs(q["omega_r"]) + 1e-12
+        assert abs(d("omega", 0, hg) / (2 * hg) - q["omega_g"]) < 1e-6 * abs(q["omega_g"])
+        assert abs(d("kappa", hr, 0) / (2 * hr) - q["kappa_r"]) < 1e-6 * abs(q["kappa_r"])
+        assert abs(d("omega_r", hr, 0) / (2 * hr) - q["omega_rr"]) < 1e-5 * abs(q["omega_rr"])
+        assert abs(d("omega_r", 0, hg) / (2 * hg) - q["omega_rg"]) < 1e-5 * abs(q["omega_rg"])
+        assert abs(d("omega_g", 0, hg) / (2 * hg) - q["omega_gg"]) < 1e-5 * abs(q["omega_gg"])
+        assert abs(d("kappa_r", hr, 0) / (2 * hr) - q["kappa_rr"]) < 1e-6 * abs(q["kappa_rr"])
+
+
+# --------------------------------------------------------------------------
+# Energy double sum (Section II.A quadrature form)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("rho", [1e-3, 0.1, 3.0])
+def test_uniform_gas_pair_sum(rho):
+    """A point at the centre of a radially resolved uniform gas: the inner sum
+    E_0 must reproduce rho int Phi = -2 beta, i.e. f^0 = rho(beta + E_0/2) = 0."""
+    q = oracle.point(B6, C01, rho, 0.0)
+    L = math.sqrt(q["kappa"] / q["omega"])   # length scale where omega R^2 = kappa
+    t, wt = np.polynomial.legendre.leggauss(400)
+    t = 0.5 * (t + 1)
+    wt = 0.5 * wt
+    R = L * t / (1 - t)
+    dR = L / (1 - t) ** 2 * wt
+    rng = np.random.default_rng(0)
+    u = rng.standard_normal((R.size, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    coords = np.vstack([np.zeros(3), R[:, None] * u])
+    w = np.concatenate([[0.0], 4 * math.pi * R ** 2 * dR])
+    n = w.size
+    ints = oracle.pair_integrals(coords, w, np.full(n, rho), np.zeros(n), B6, C01)
+    beta = oracle.beta(B6)
+    assert abs(ints[0, 0] + 2 * beta) < 1e-11 * beta
+
+
+def test_single_point_closed_form():
+    """N = 1: Phi_ii = -3/(4 kappa^3), E = w rho beta - (3/8) w^2 rho^2 / kappa^3."""
+    rho, gam, w = 0.37, 0.02, 0.8
+    e, fr, fg = oracle.energy_potential(np.zeros((1, 3)), [w], [rho], [gam], B6, C01)
+    k = oracle.point(B6, C01, rho, gam)["kappa"]
+    want = w * rho * oracle.beta(B6) - 3.0 / 8.0 * w * w * rho * rho / k ** 3
+    assert abs(e - want) < 1e-15 * abs(want)
+
+
+def test_two_identical_points_closed_form():
+    """Two points with the same rho, gamma, w at distance R: E = 2 w rho beta
+    + w^2 rho^2 (Phi_self + Phi_12), Phi_12 = -3/(4 (omega R^2 + kappa)^3)."""
+    rho, gam, w, R = 0.2, 0.01, 0.5, 1.7
+    coords = np.array([[0.0, 0.0, 0.0], [0.0, R, 0.0]])
+    e, _, _ = oracle.energy_potential(coords, [w, w], [rho, rho], [gam, gam], B6, C01)
+    q = oracle.point(B6, C01, rho, gam)
+    g = q["omega"] * R * R + q["kappa"]
+    want = 2 * w * rho * oracle.beta(B6) + w * w * rho * rho * (-3 / (4 * q["kappa"] ** 3) - 3 / (4 * g ** 3))
+    assert abs(e - want) < 1e-15 * abs(want)
+
+
+def test_brute_force_energy_tiny():
+    """Brute-force pair enumeration for 3 points with different rho, gamma."""
+    rng = np.random.default_rng(1)
+    coords = rng.normal(size=(3, 3))
+    w = rng.uniform(0.1, 1.0, 3)
+    rho = rng.uniform(0.01, 2.0, 3)
+    gam = rng.uniform(0.0, 0.5, 3)
+    pts = [oracle.point(B6, C01, r, g) for r, g in zip(rho, gam)]
+    tot = 0.0
+    for i in range(3):
+        inner = 0.0
+        for j in range(3):
+            R2 = float(np.sum((coords[i] - coords[j]) ** 2))
+            gi = pts[i]["omega"] * R2 + pts[i]["kappa"]
+            gj = pts[j]["omega"] * R2 + pts[j]["kappa"]
+            inner += w[j] * rho[j] * (-1.5 / (gi * gj * (gi + gj)))
+        tot += w[i] * rho[i] * (oracle.beta(B6) + 0.5 * inner)
+    e, _, _ = oracle.energy_potential(coords, w, rho, gam, B6, C01)
+    assert abs(e - tot) < 1e-14 * abs(tot)
+
+
+# --------------------------------------------------------------------------
+# Potential and second-derivative matrices (Sections II.A, II.B)
+# --------------------------------------------------------------------------
+
+def test_potential_is_energy_derivative(small_dimer):
+    """w_i f^rho_i = dE/d rho_i and w_i f^gamma_i = dE/d gamma_i (directional FD)."""
+    p = small_dimer
+    g = oracle.gamma(p.grad_rho)
+    e0, fr, fg = _ep(p)
+    rng = np.random.default_rng(0)
+    for _ in range(3):
+        v = rng.uniform(-1, 1, p.n_grid)
+        d = richardson(lambda h: _ep(p, rho=p.rho * (1 + h * v))[0], 1e-3)
+        want = np.sum(p.weights * fr * p.rho * v)
+        assert abs(d - want) < 1e-9 * np.sum(np.abs(p.weights * fr * p.rho))
+        d = richardson(lambda h: _ep(p, gam=g * (1 + h * v))[0], 1e-3)
+        want = np.sum(p.weights * fg * g * v)
+        assert abs(d - want) < 1e-9 * np.sum(np.abs(p.weights * fg * g))
+
+
+def test_potential_elementwise_fd(small_dimer):
+    p = small_dimer
+    g = oracle.gamma(p.grad_rho)
+    e0, fr, fg = _ep(p)
+    h = 1e-2
+    for i in (0, 17, 123, 250, 359):
+        onehot = np.zeros(p.n_grid)
+        onehot[i] = 1.0
+        # rounding floor of a central difference of E with step h*rho_i
+        d = richardson(lambda t: _ep(p, rho=p.rho * (1 + t * onehot))[0], h) / p.rho[i]
+        floor = 1e-14 * abs(e0) / (h * p.rho[i])
+        assert abs(d - p.weights[i] * fr[i]) < 1e-7 * abs(p.weights[i] * fr[i]) + floor
+        d = richardson(lambda t: _ep(p, gam=g * (1 + t * onehot))[0], h) / g[i]
+        floor = 1e-14 * abs(e0) / (h * g[i])
+        assert abs(d - p.weights[i] * fg[i]) < 1e-6 * abs(p.weights[i] * fg[i]) + floor
+
+
+def test_second_matrices_fd(small_dimer):
+    """d f^rho_i / d rho_j = w_j f^{rho rho}_ij, d f^gamma_i / d rho_j = w_j f^{gamma rho}_ij,
+    d f^rho_i / d gamma_j = w_j f^{rho gamma}_ij, d f^gamma_i / d gamma_j = w_j f^{gamma gamma}_ij,
+    checked on full columns j (diagonal element with its delta term included)."""
+    p = small_dimer
+    g = oracle.gamma(p.grad_rho)
+    frr, fgr, frg, fgg = oracle.second_matrices(p.coords, p.weights, p.rho, g, p.b, p.C)
+    _, fr0, fg0 = _ep(p)
+    for j in (3, 77, 200, 301):
+        onehot = np.zeros(p.n_grid)
+        onehot[j] = 1.0
+        pr = lambda h: np.concatenate(_ep(p, rho=p.rho * (1 + h * onehot))[1:])
+        pg = lambda h: np.concatenate(_ep(p, gam=g * (1 + h * onehot))[1:])
+        dr = richardson(pr, 2e-3) / p.rho[j]
+        dg = richardson(pg, 2e-3) / g[j]
+        n = p.n_grid
+        # FD noise floor ~ 1e-12 |f_i| / h; physical tolerance 1e-6 relative
+        floor_r = 1e-10 * np.abs(fr0) / (p.rho[j] * 2e-3) * p.rho[j]
+        floor_g = 1e-10 * np.abs(fg0) / (p.rho[j] * 2e-3) * p.rho[j]
+        for got, want, floor in ((dr[:n], p.weights[j] * frr[:, j], floor_r),
+                                 (dr[n:], p.weights[j] * fgr[:, j], floor_g)):
+            assert np.all(np.abs(got - want) <= 1e-6 * np.abs(want) + floor)
+        floor_r = 1e-10 * np.abs(fr0) / (g[j] * 2e-3) * g[j]
+        floor_g = 1e-10 * np.abs(fg0) / (g[j] * 2e-3) * g[j]
+        for got, want, floor in ((dg[:n], p.weights[j] * frg[:, j], floor_r),
+                                 (dg[n:], p.weights[j] * fgg[:, j], floor_g)):
+            assert np.all(np.abs(got - want) <= 1e-6 * np.abs(want) + floor)
+        # the diagonal element carries the delta_ij/w_i term: checked tightly
+        assert abs(dr[j] - p.weights[j] * frr[j, j]) < 1e-6 * abs(p.weights[j] * frr[j, j])
+
+
+def test_second_matrices_symmetry(small_dimer):
+    p = small_dimer
+    g = oracle.gamma(p.grad_rho)
+    frr, fgr, frg, fgg = oracle.second_matrices(p.coords, p.weights, p.rho, g, p.b, p.C)
+    assert np.max(np.abs(frr - frr.T)) <= 1e-14 * np.max(np.abs(frr))
+    assert np.max(np.abs(fgg - fgg.T)) <= 1e-14 * np.max(np.abs(fgg))
+    assert np.max(np.abs(frg - fgr.T)) <= 1e-14 * np.max(np.abs(frg))
+
+
+def test_response_rows_match_matrices(tiny_problem):
+    p = tiny_problem
+    g, gx = oracle.problem_inputs(p)
+    frr, fgr, frg, fgg = oracle.second_matrices(p.coords, p.weights, p.rho, g, p.b, p.C)
+    Yr, Yg = oracle.response_rows(0, p.n_grid, p.coords, p.weights, p.rho, g, p.b, p.C, p.rho_x, gx)
+    w = p.weights
+    Yr2 = (frr @ (w * p.rho_x).T + frg @ (w * gx).T).T
+    Yg2 = (fgr @ (w * p.rho_x).T + fgg @ (w * gx).T).T
+    assert np.max(np.abs(Yr - Yr2)) <= 1e-12 * np.max(np.abs(Yr2))
+    assert np.max(np.abs(Yg - Yg2)) <= 1e-12 * np.max(np.abs(Yg2))
+
+
+# --------------------------------------------------------------------------
+# Grid-position intermediates and nuclear derivatives (Sections II.A, II.B)
+# --------------------------------------------------------------------------
+
+def test_grid_vectors_are_position_derivatives(small_dimer):
+    """E^{Bgr}_i, U^{Bgr}_i, W^{Bgr}_i = d(E_i, U_i, W_i)/dX_B when only atom B's
+    grid points move (rho, gamma held); for i in B this checks the
+    translational-invariance fill."""
+    p = small_dimer
+    g = oracle.gamma(p.grad_rho)
+    Eg, Ug, Wg = oracle.grid_vectors(p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b, p.C)
+    for B in (0, 2, 4):
+        for a in range(3):
+            def ints(h):
+                c = p.coords.copy()
+                c[p.atom_of == B, a] += h
+                return oracle.pair_integrals(c, p.weights, p.rho, g, p.b, p.C)[:3]
+            d = richardson(ints, 1e-3)
+            for k, ref in enumerate((Eg, Ug, Wg)):
+                want = ref[:, B, a]
+                assert np.max(np.abs(d[k] - want)) < 1e-8 * np.max(np.abs(want))
+
+
+def test_grid_D_is_derivative_of_own_slot(small_dimer):
+    """For i in A and B != A, D^B_i = d E^{Agr}_i / dX_B (own-atom slot)."""
+    p = small_dimer
+    g = oracle.gamma(p.grad_rho)
+    for i in (5, 130, 290):
+        A = int(p.atom_of[i])
+        for B in {(A + 1) % p.n_atom, (A + 3) % p.n_atom}:
+            D = oracle.grid_D(i, B, p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b, p.C)
+            for a in range(3):
+                def own(h):
+                    c = p.coords.copy()
+                    c[p.atom_of == B, a] += h
+                    return oracle.grid_vectors(p.atom_of, p.n_atom, c, p.weights, p.rho, g,
+                                               p.b, p.C)[0][i, A]
+                d = richardson(own, 1e-3)
+                assert np.max(np.abs(d - D[:, a])) < 1e-8 * np.max(np.abs(D))
+
+
+def test_gradient_fd(small_dimer):
+    """Analytic gradient (E_G + E_gr) against central FD of E with the grid
+    moving rigidly with its atoms; and sum_A E^A = 0."""
+    p = small_dimer
+    g, gx = oracle.problem_inputs(p)
+    G = oracle.gradient(p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b, p.C, p.rho_x, gx)
+    for x in range(p.n_pert):
+        A, a = divmod(x, 3)
+        d = richardson(lambda h: _ep(inputs.displaced(p, A, a, h))[0], 1e-3)
+        assert abs(d - G[x]) < 1e-9 * np.max(np.abs(G))
+    assert np.max(np.abs(G.reshape(-1, 3).sum(0))) < 1e-13
+
+
+def test_gradient_second_form_reading(small_dimer):
+    """E^A_gr equals sum_{i in A} w_i rho_i E^{Agr}_i (the grid-vector form)."""
+    p = small_dimer
+    g, gx = oracle.problem_inputs(p)
+    _, parts = oracle.gradient(p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b, p.C,
+                               p.rho_x, gx, parts=True)
+    Eg, _, _ = oracle.grid_vectors(p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b, p.C)
+    a = p.weights * p.rho
+    alt = np.array([np.sum(a[p.atom_of == A] * Eg[p.atom_of == A, A, c])
+                    for A in range(p.n_atom) for c in range(3)])
+    assert np.max(np.abs(alt - parts[1])) < 1e-13 * np.max(np.abs(alt))
+
+
+def _frozen_gradient(p, q, gx):
+    """Gradient at the displaced problem q with rho^x, gamma^x frozen at p:
+    its derivative is the Hessian without the rho^{AB}, gamma^{AB} term."""
+    gq = oracle.gamma(q.grad_rho)
+    return oracle.gradient(q.atom_of, q.n_atom, q.coords, q.weights, q.rho, gq, q.b, q.C,
+                           p.rho_x, gx)
+
+
+def test_hessian_terms_fd(small_dimer):
+    p = small_dimer
+    g, gx = oracle.problem_inputs(p)
+    H, info = oracle.hessian_terms(p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b,
+                                   p.C, p.rho_x, gx)
+    scale = np.max(np.abs(H))
+    for y in range(p.n_pert):
+        B, b = divmod(y, 3)
+        d = richardson(lambda h: _frozen_gradient(p, inputs.displaced(p, B, b, h), gx), 1e-3)
+        assert np.max(np.abs(d - H[:, y])) < 1e-9 * scale
+    assert info["asym"] < 1e-12 * scale
+
+
+def test_hessian_invariances(small_dimer):
+    p = small_dimer
+    g, gx = oracle.problem_inputs(p)
+    H, info = oracle.hessian_terms(p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b,
+                                   p.C, p.rho_x, gx, parts=True)
+    P = p.n_pert
+    assert np.array_equal(H, H.T)
+    GG, Ggr, grgr = info["parts"]
+    assert np.max(np.abs(GG - GG.T)) < 1e-13 * np.max(np.abs(GG))
+    assert np.max(np.abs(grgr - grgr.T)) < 1e-13 * np.max(np.abs(grgr))
+    # sum over atoms B of H[(A,a),(B,b)] vanishes for every (A,a), b
+    s = H.reshape(P, p.n_atom, 3).sum(axis=1)
+    assert np.max(np.abs(s)) < 1e-12 * np.max(np.abs(H))
+    s = grgr.reshape(P, p.n_atom, 3).sum(axis=1)
+    assert np.max(np.abs(s)) < 1e-13 * np.max(np.abs(grgr))
+
+
+def test_hessian_resp_outputs(tiny_problem):
+    p = tiny_problem
+    g, gx = oracle.problem_inputs(p)
+    H, info = oracle.hessian_terms(p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b,
+                                   p.C, p.rho_x, gx, resp=True, parts=True)
+    Yr, Yg = info["resp"]
+    GG = info["parts"][0]
+    w = p.weights
+    GG2 = (w * p.rho_x) @ Yr.T + (w * gx) @ Yg.T
+    assert np.max(np.abs(GG - GG2)) < 1e-13 * np.max(np.abs(GG))
+
+
+def test_unsorted_grid_rejected(tiny_problem):
+    p = tiny_problem
+    g, gx = oracle.problem_inputs(p)
+    ao = p.atom_of.copy()[::-1].copy()
+    with pytest.raises(ValueError):
+        oracle.hessian_terms(ao, p.n_atom, p.coords, p.weights, p.rho, g, p.b, p.C, p.rho_x, gx)
