@@ -1,0 +1,153 @@
+/*
+ * vv10.h -- C ABI of the MI355X VV10 double-grid engine.
+ *
+ * The library evaluates, on one GPU, the O(N_grid^2) double sums of the VV10
+ * nonlocal correlation kernel
+ *     Phi_ij = -3 / (2 g g' (g + g')),  g = omega_i R_ij^2 + kappa_i,
+ *     g' = omega_j R_ij^2 + kappa_j
+ * that give the VV10 energy, its grid-level potential and the nuclear
+ * Hessian grid terms (Liang, Feng, Liu & Head-Gordon, arXiv 2208.14639,
+ * Section II).  Atomic units throughout.
+ *
+ * Conventions shared by every entry point:
+ *  - Every array argument is a DEVICE pointer, FP64 (int32 for atom_of),
+ *    row-major, owned by the caller.  The library reads inputs only during
+ *    the call that receives them and packs what it keeps into memory the
+ *    plan owns.
+ *  - Every call is asynchronous on the plan's HIP stream (the stream given
+ *    to vv10_prepare), except vv10_prepare, which synchronises that stream
+ *    once to read back its validation result.  Outputs are valid once the
+ *    caller has synchronised the stream.
+ *  - Errors are status codes; nothing throws across the ABI.  A call that
+ *    returns VV10_E_ARG, VV10_E_STATE, VV10_E_DENSITY, VV10_E_GRID_ORDER or
+ *    VV10_E_OOM has written no output.  After VV10_E_HIP (a failed launch or
+ *    runtime call) the outputs are undefined and the plan refuses further
+ *    work (VV10_E_STATE).  Any plan, failed or not, is safe to destroy.
+ *  - A plan is used from one host thread and one stream at a time; distinct
+ *    plans may run concurrently on distinct streams.
+ *  - All inner sums run over every grid point, the self pair j = i included.
+ *  - Quadrature weights are taken as independent of nuclear positions (they
+ *    move rigidly with their owner atom), so every weight-derivative term of
+ *    the paper's gradient and nine-term Hessian split is zero and absent.
+ */
+#ifndef VV10_H
+#define VV10_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    VV10_OK = 0,
+    VV10_E_ARG = -1,        /* bad size, null pointer, atom index out of range, n_pert != 3 n_atom */
+    VV10_E_DENSITY = -2,    /* some rho <= 0, or a non-finite rho, grad rho, weight or coordinate */
+    VV10_E_GRID_ORDER = -3, /* atom_of is not nondecreasing */
+    VV10_E_OOM = -4,        /* device allocation failed */
+    VV10_E_HIP = -5,        /* a HIP runtime call failed */
+    VV10_E_STATE = -6       /* call out of order (e.g. a destroyed or failed plan) */
+} vv10_status;
+
+/* Arithmetic of the O(N^2) parts.  Per-point preparation, every
+ * cross-tile accumulation, the energy and Hessian reductions and the
+ * symmetrisation are FP64 in all modes. */
+typedef enum {
+    VV10_FP64 = 0,          /* all pair arithmetic and the contraction in FP64 */
+    VV10_MIXED_FP32 = 1,    /* pair arithmetic FP32; contraction on FP32 MFMA */
+    VV10_MIXED_BF16X3 = 2   /* pair arithmetic FP32; contraction as split-BF16 (hi*hi + hi*lo + lo*hi) MFMA */
+} vv10_precision;
+
+/* VV10 parameters b and C (Section II.A: kappa = b (3 pi/2)(rho/9pi)^{1/6},
+ * omega = sqrt(C gamma^2/rho^4 + 4 pi rho/3), beta = (1/32)(3/b^2)^{3/4}). */
+typedef struct {
+    double b;
+    double C;
+} vv10_params;
+
+typedef struct vv10_plan vv10_plan; /* opaque; owns its device workspace */
+
+/*
+ * vv10_prepare -- validate and pack one grid (Section II.A, per-point
+ * intermediates omega, kappa and their first and second partials).
+ *
+ *  params    b, C.
+ *  n_grid    N >= 1 grid points.  n_atom >= 1 atoms.
+ *  coords    [N][3] point positions (bohr).
+ *  weights   [N] quadrature weights (> 0 not required, finite).
+ *  atom_of   [N] owner atom of each point, 0 <= atom_of[i] < n_atom, nondecreasing
+ *            (points grouped by atom; the grid moves rigidly with its atom).
+ *  rho       [N] density, every value > 0 and finite.
+ *  grad_rho  [N][3] density gradient.
+ *  prec      arithmetic mode for the O(N^2) work of later calls.
+ *  stream    HIP stream every later call of this plan runs on (0 = null stream).
+ *  out       receives the plan; set to NULL on error.
+ * Errors: VV10_E_ARG, VV10_E_DENSITY, VV10_E_GRID_ORDER, VV10_E_OOM, VV10_E_HIP.
+ * Synchronises `stream` once to read its validation flag.
+ */
+vv10_status vv10_prepare(const vv10_params *params, int64_t n_grid, int32_t n_atom,
+                         const double *coords, const double *weights,
+                         const int32_t *atom_of, const double *rho,
+                         const double *grad_rho, vv10_precision prec,
+                         hipStream_t stream, vv10_plan **out);
+
+/*
+ * vv10_energy_potential -- VV10 energy and grid-level potential
+ * (Section II.A):
+ *   E_i = sum_j w_j rho_j Phi_ij,
+ *   U_i = -sum_j w_j rho_j Phi_ij (1/(g+g') + 1/g),
+ *   W_i = -sum_j w_j rho_j Phi_ij R_ij^2 (1/(g+g') + 1/g),
+ *   energy  = sum_i w_i rho_i (beta + E_i/2),
+ *   f_rho_i = beta + E_i + rho_i (dkappa/drho U_i + domega/drho W_i),
+ *   f_gamma_i = rho_i domega/dgamma W_i
+ * (so dE/drho_i = w_i f_rho_i and dE/dgamma_i = w_i f_gamma_i).
+ *  energy   [1] device scalar.  f_rho, f_gamma [N]; either may be NULL.
+ * Errors: VV10_E_ARG (energy NULL), VV10_E_STATE, VV10_E_HIP.
+ */
+vv10_status vv10_energy_potential(vv10_plan *plan, double *energy, double *f_rho,
+                                  double *f_gamma);
+
+/*
+ * vv10_hessian_terms -- nuclear-Hessian grid terms for all 3 n_atom
+ * perturbations at once (Section II.B, nine-term split with the weight
+ * terms zero):
+ *   hess = E_{G,G} + E_{G,gr} + E_{G,gr}^T + E_{gr,gr}
+ * where E_{G,G} excludes sum_i w_i (f^rho_i rho^{AB}_i + f^gamma_i gamma^{AB}_i)
+ * (that term needs second density derivatives, which belong to the caller).
+ *
+ *  n_pert      must equal 3 n_atom; perturbation x = 3 A + alpha moves
+ *              nucleus A along axis alpha.
+ *  rho_x       [n_pert][N] total derivative of rho at each point when the
+ *              nucleus moves and the point moves with its owner atom.
+ *  grad_rho_x  [n_pert][N][3] the same for grad rho; gamma^x = 2 grad rho . grad rho^x.
+ *  hess        [n_pert][n_pert] output, symmetrised as (H + H^T)/2.
+ *  grad        [n_pert] or NULL: nuclear gradient E_G + E_gr (Section II.A).
+ *  resp_rho    [n_pert][N] or NULL: sum_j w_j (f^{rho rho}_ij rho^x_j + f^{rho gamma}_ij gamma^x_j).
+ *  resp_gamma  [n_pert][N] or NULL: sum_j w_j (f^{gamma rho}_ij rho^x_j + f^{gamma gamma}_ij gamma^x_j).
+ * Errors: VV10_E_ARG, VV10_E_OOM (workspace), VV10_E_STATE, VV10_E_HIP.
+ */
+vv10_status vv10_hessian_terms(vv10_plan *plan, int32_t n_pert, const double *rho_x,
+                               const double *grad_rho_x, double *hess, double *grad,
+                               double *resp_rho, double *resp_gamma);
+
+/* Device bytes a plan for this size holds once vv10_hessian_terms has run
+ * (an upper bound; vv10_energy_potential alone needs less). */
+size_t vv10_footprint_bytes(int64_t n_grid, int32_t n_atom, vv10_precision prec);
+
+/* Destroy a plan and free its device memory (NULL is accepted).  Waits for
+ * the plan's stream to finish the plan's work first. */
+void vv10_destroy(vv10_plan *plan);
+
+/* Static description of a status code. */
+const char *vv10_status_string(vv10_status s);
+
+/* Library build identifier (compile-time arch and version string). */
+const char *vv10_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VV10_H */

@@ -1,0 +1,203 @@
+// Per-point preparation (Section II.A of the paper: omega, kappa and the
+// first and second partial derivatives that the potential and the
+// second-derivative matrices need) and perturbation packing (Section II.B:
+// rho^x, gamma^x of the 3 N_atom nuclear perturbations).
+//
+// Both kernels are O(N) or O(N P) and bound by HBM bandwidth; everything
+// here is FP64.
+#include "dev_common.h"
+#include "vv10_internal.h"
+
+namespace vv10 {
+
+namespace {
+
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+// Fill an int32 array with a value (used instead of a memset so that the
+// launch sequence contains kernels only).
+__global__ void k_fill_i32(int32_t *a, int64_t n, int32_t v) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+// Partial sums of the coordinates for the centroid shift (fixed order).
+__global__ __launch_bounds__(256) void k_coord_partials(int64_t n, const double *coords,
+                                                        double *part) {
+    __shared__ double s[3][256];
+    double a[3] = {0, 0, 0};
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        for (int k = 0; k < 3; ++k) a[k] += coords[3 * i + k];
+    for (int k = 0; k < 3; ++k) s[k][threadIdx.x] = a[k];
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off)
+            for (int k = 0; k < 3; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) part[blockIdx.x * 3 + threadIdx.x] = s[threadIdx.x][0];
+}
+
+__global__ void k_coord_centroid(int nblk, int64_t n, double *part) {
+    if (threadIdx.x < 3) {
+        double t = 0.0;
+        for (int b = 0; b < nblk; ++b) t += part[3 * b + threadIdx.x];
+        part[3 * nblk + threadIdx.x] = t / (double)n;
+    }
+}
+
+// One thread per padded point.  Pad rows get benign values (omega = kappa = 1,
+// zero weight) so that they contribute exact zeros to every sum.
+__global__ __launch_bounds__(256) void k_prep(
+    int64_t n, int64_t npad, int32_t n_atom, double b, double C,
+    const double *__restrict__ coords, const double *__restrict__ w,
+    const int32_t *__restrict__ atom_of, const double *__restrict__ rho,
+    const double *__restrict__ grad, const double *__restrict__ centroid,
+    double4 *__restrict__ P0, double4 *__restrict__ P1, float4 *__restrict__ P0f,
+    float4 *__restrict__ P1f, double *__restrict__ F, int32_t *__restrict__ ao_out,
+    int32_t *__restrict__ flag) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= npad) return;
+    if (i >= n) {
+        P0[i] = make_double4(0.0, 0.0, 0.0, 1.0);
+        P1[i] = make_double4(1.0, 0.0, 0.0, 0.0);
+        P0f[i] = make_float4(0.f, 0.f, 0.f, 1.f);
+        P1f[i] = make_float4(1.f, 0.f, 0.f, 0.f);
+        for (int f = 0; f < NF; ++f) F[f * npad + i] = 0.0;
+        ao_out[i] = n_atom;
+        return;
+    }
+    const double r = rho[i], wi = w[i];
+    const double gx = grad[3 * i], gy = grad[3 * i + 1], gz = grad[3 * i + 2];
+    const double x = coords[3 * i] - centroid[0];
+    const double y = coords[3 * i + 1] - centroid[1];
+    const double z = coords[3 * i + 2] - centroid[2];
+    const int32_t A = atom_of[i];
+    int32_t bad = 0;
+    if (!(r > 0.0) || !isfinite(r) || !isfinite(wi) || !isfinite(gx) || !isfinite(gy) ||
+        !isfinite(gz) || !isfinite(x) || !isfinite(y) || !isfinite(z))
+        bad |= 1;
+    if (A < 0 || A >= n_atom) bad |= 4;
+    else if (i > 0 && atom_of[i - 1] > A) bad |= 2;
+    if (bad) {
+        atomicOr(flag, bad);
+        return;
+    }
+    // first point of atom A records the segment start
+    if (i == 0 || atom_of[i - 1] != A) flag[1 + A] = (int32_t)i;
+
+    const double gam = gx * gx + gy * gy + gz * gz;
+    const double ir = 1.0 / r;
+    const double q = gam * ir * ir;                 // gamma / rho^2
+    const double S = C * q * q + (4.0 * kPi / 3.0) * r;   // omega^2
+    const double om = sqrt(S);
+    const double ka = b * 1.5 * kPi * pow(r / (9.0 * kPi), 1.0 / 6.0);
+    // derivatives of S = omega^2
+    const double Sr = (4.0 * kPi / 3.0) - 4.0 * C * q * q * ir;
+    const double Sg = 2.0 * C * q * ir * ir;
+    const double Srr = 20.0 * C * q * q * ir * ir;
+    const double Srg = -8.0 * C * q * ir * ir * ir;
+    const double Sgg = 2.0 * C * ir * ir * ir * ir;
+    const double iom = 1.0 / om;
+    const double omr = 0.5 * Sr * iom, omg = 0.5 * Sg * iom;
+    const double omrr = (0.5 * Srr - omr * omr) * iom;
+    const double omrg = (0.5 * Srg - omr * omg) * iom;
+    const double omgg = (0.5 * Sgg - omg * omg) * iom;
+    const double kar = ka * ir / 6.0;
+    const double karr = -5.0 * ka * ir * ir / 36.0;
+    const double a = wi * r, c = r * kar;
+
+    P0[i] = make_double4(x, y, z, om);
+    P1[i] = make_double4(ka, a, c, 0.0);
+    P0f[i] = make_float4((float)x, (float)y, (float)z, (float)om);
+    P1f[i] = make_float4((float)ka, (float)a, (float)c, 0.f);
+    F[F_W * npad + i] = wi;
+    F[F_RHO * npad + i] = r;
+    F[F_GX * npad + i] = gx;
+    F[F_GY * npad + i] = gy;
+    F[F_GZ * npad + i] = gz;
+    F[F_OMR * npad + i] = omr;
+    F[F_OMG * npad + i] = omg;
+    F[F_KAR * npad + i] = kar;
+    F[F_OMRR * npad + i] = omrr;
+    F[F_OMRG * npad + i] = omrg;
+    F[F_OMGG * npad + i] = omgg;
+    F[F_KARR * npad + i] = karr;
+    F[F_FR * npad + i] = 0.0;
+    F[F_FG * npad + i] = 0.0;
+    ao_out[i] = A;
+}
+
+// Perturbation packing: for every point i and perturbation x,
+//   gamma^x = 2 grad rho . grad rho^x,
+//   X[i][0][x] = w rho^x                       (p channel)
+//   X[i][1][x] = w rho (omega_r rho^x + omega_g gamma^x)   (q channel)
+//   L[i][0][x] = rho^x, L[i][1][x] = gamma^x.
+// A 32 x 32 (point x perturbation) tile is staged through LDS so that both
+// the [P][N] reads and the [N][2][Pp] writes are coalesced.
+constexpr int TT = 32;
+__global__ __launch_bounds__(256) void k_pert_prep(
+    int64_t n, int64_t npad, int32_t P, int32_t Pp, const double *__restrict__ rho_x,
+    const double *__restrict__ grad_rho_x, const double *__restrict__ F,
+    double *__restrict__ X, double *__restrict__ L) {
+    __shared__ double sr[TT][TT + 1];
+    __shared__ double sg[TT][TT + 1];
+    const int64_t i0 = (int64_t)blockIdx.x * TT;
+    const int x0 = blockIdx.y * TT;
+    const int tx = threadIdx.x % TT, ty = threadIdx.x / TT;   // 32 x 8
+    // load: thread (tx, ty) reads point i0 + tx of perturbations x0 + ty + 8k
+    for (int k = 0; k < TT; k += 8) {
+        const int x = x0 + ty + k;
+        const int64_t i = i0 + tx;
+        double rx = 0.0, gxv = 0.0;
+        if (x < P && i < n) {
+            rx = rho_x[(int64_t)x * n + i];
+            const double *gp = grad_rho_x + ((int64_t)x * n + i) * 3;
+            gxv = 2.0 * (F[F_GX * npad + i] * gp[0] + F[F_GY * npad + i] * gp[1] +
+                         F[F_GZ * npad + i] * gp[2]);
+        }
+        sr[ty + k][tx] = rx;
+        sg[ty + k][tx] = gxv;
+    }
+    __syncthreads();
+    // store: thread (tx, ty) writes perturbation x0 + tx of points i0 + ty + 8k
+    for (int k = 0; k < TT; k += 8) {
+        const int64_t i = i0 + ty + k;
+        const int x = x0 + tx;
+        if (i >= npad || x >= Pp) continue;
+        const double rx = sr[tx][ty + k], gxv = sg[tx][ty + k];
+        const double wi = F[F_W * npad + i], r = F[F_RHO * npad + i];
+        const double p = wi * rx;
+        const double qv = wi * r * (F[F_OMR * npad + i] * rx + F[F_OMG * npad + i] * gxv);
+        X[(i * 2 + 0) * Pp + x] = p;
+        X[(i * 2 + 1) * Pp + x] = qv;
+        L[(i * 2 + 0) * Pp + x] = rx;
+        L[(i * 2 + 1) * Pp + x] = gxv;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_prepare(vv10_plan *p, const double *coords, const double *w,
+                          const int32_t *atom_of, const double *rho,
+                          const double *grad_rho) {
+    const int nb_part = 64;
+    k_fill_i32<<<(p->n_atom + 2 + 255) / 256, 256, 0, p->stream>>>(p->flag, p->n_atom + 2, -1);
+    k_fill_i32<<<1, 1, 0, p->stream>>>(p->flag, 1, 0);
+    k_coord_partials<<<nb_part, 256, 0, p->stream>>>(p->n, coords, p->red);
+    k_coord_centroid<<<1, 64, 0, p->stream>>>(nb_part, p->n, p->red);
+    k_prep<<<(unsigned)(p->npad / 256), 256, 0, p->stream>>>(
+        p->n, p->npad, p->n_atom, p->prm.b, p->prm.C, coords, w, atom_of, rho, grad_rho,
+        p->red + 3 * nb_part, p->P0, p->P1, p->P0f, p->P1f, p->F, p->atom_of, p->flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_pert_prep(vv10_plan *p, const double *rho_x, const double *grad_rho_x) {
+    const Workspace &ws = p->ws;
+    dim3 grid((unsigned)((p->npad + TT - 1) / TT), (unsigned)((ws.Pp + TT - 1) / TT));
+    k_pert_prep<<<grid, 256, 0, p->stream>>>(p->n, p->npad, ws.P, ws.Pp, rho_x, grad_rho_x,
+                                             p->F, ws.X, ws.L);
+    return hipGetLastError();
+}
+
+}  // namespace vv10

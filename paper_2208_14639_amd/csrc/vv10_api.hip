@@ -1,0 +1,344 @@
+// Host side of the C ABI declared in include/vv10.h: argument validation,
+// plan and workspace ownership, launch sequencing and error mapping.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "vv10_internal.h"
+
+using vv10::Workspace;
+
+namespace vv10 {
+
+void plan_workspace_shape(int64_t npad, int32_t n_atom, int32_t ntiles, int num_cu,
+                          vv10_precision prec, Workspace &ws) {
+    (void)prec;
+    ws.P = 3 * n_atom;
+    const int ncb_total = (ws.P + 15) / 16;
+    ws.ngroups = (ncb_total + 7) / 8;
+    ws.ncb = (ncb_total + ws.ngroups - 1) / ws.ngroups;
+    ws.Pp = 16 * ws.ncb * ws.ngroups;
+
+    // j splits of the contraction: keep the last round of workgroups full
+    // (two resident 256-thread workgroups per CU).
+    const int64_t units = (npad / 64) * ws.ngroups;
+    const int64_t slots = 2LL * num_cu;
+    double best = -1.0;
+    ws.jsplit = 1;
+    for (int S = 1; S <= 8; ++S) {
+        if (npad / S < 256) break;
+        const int64_t u = units * S;
+        const double eff = (double)u / (double)(((u + slots - 1) / slots) * slots);
+        const double score = eff - 0.01 * (S - 1);
+        if (score > best + 1e-12) {
+            best = score;
+            ws.jsplit = S;
+        }
+    }
+    const int tiles = (ws.Pp + 63) / 64;
+    ws.gsplit = (int)std::max<int64_t>(1, std::min<int64_t>((1024 + tiles * tiles - 1) / (tiles * tiles),
+                                                             std::max<int64_t>(1, npad / 64)));
+    ws.bgroups = std::max(1, std::min<int>(n_atom, (8192 + std::max(ntiles, 1) - 1) / std::max(ntiles, 1)));
+}
+
+size_t workspace_bytes(int64_t npad, int32_t n_atom, int32_t ntiles, const Workspace &ws) {
+    const size_t ch = (size_t)npad * 2 * ws.Pp * sizeof(double);
+    size_t b = 3 * ch + (size_t)ws.jsplit * ch;
+    b += (size_t)ntiles * n_atom * 9 * sizeof(double);
+    b += (size_t)ws.gsplit * ws.Pp * ws.Pp * sizeof(double);
+    b += (size_t)ws.P * ws.P * sizeof(double);
+    b += (size_t)256 * ws.Pp * sizeof(double);
+    return b;
+}
+
+}  // namespace vv10
+
+namespace {
+
+constexpr int kCentroidBlocks = 64;
+
+size_t reduction_doubles(int64_t npad) {
+    return std::max<size_t>((size_t)(npad / 256) + 2, 3 * kCentroidBlocks + 3);
+}
+
+size_t base_bytes(int64_t npad, int32_t n_atom, int64_t ntiles_bound) {
+    size_t b = 2 * (size_t)npad * sizeof(double4) + 2 * (size_t)npad * sizeof(float4);
+    b += (size_t)vv10::NF * npad * sizeof(double) + (size_t)vv10::NI * npad * sizeof(double);
+    b += (size_t)npad * sizeof(int32_t) + (size_t)(n_atom + 1) * sizeof(int64_t);
+    b += (size_t)(3 * ntiles_bound + n_atom + 1) * sizeof(int32_t);
+    b += reduction_doubles(npad) * sizeof(double) + (size_t)(n_atom + 2) * sizeof(int32_t);
+    return b;
+}
+
+template <typename T>
+hipError_t dalloc(T **p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T));
+}
+
+void dfree(void *ptr) {
+    if (ptr) (void)hipFree(ptr);
+}
+
+void free_workspace(Workspace &ws) {
+    dfree(ws.X);
+    dfree(ws.L);
+    dfree(ws.Y);
+    dfree(ws.Z);
+    dfree(ws.Dpart);
+    dfree(ws.Hpart);
+    dfree(ws.Hgr);
+    dfree(ws.gpart);
+    ws = Workspace{};
+}
+
+void free_plan(vv10_plan *p) {
+    if (!p) return;
+    free_workspace(p->ws);
+    dfree(p->P0);
+    dfree(p->P1);
+    dfree(p->P0f);
+    dfree(p->P1f);
+    dfree(p->F);
+    dfree(p->I);
+    dfree(p->atom_of);
+    dfree(p->d_seg);
+    dfree(p->d_tile_i0);
+    dfree(p->d_tile_n);
+    dfree(p->d_tile_atom);
+    dfree(p->d_tile_first);
+    dfree(p->red);
+    dfree(p->flag);
+    delete p;
+}
+
+vv10_status hip_status(hipError_t e) {
+    if (e == hipSuccess) return VV10_OK;
+    if (e == hipErrorOutOfMemory) return VV10_E_OOM;
+    return VV10_E_HIP;
+}
+
+// Test hook: VV10_FAIL_ALLOC=<n> makes the n-th workspace allocation of the
+// process report out-of-memory (used to exercise the error path on the host).
+bool injected_alloc_failure() {
+    static int countdown = [] {
+        const char *s = std::getenv("VV10_FAIL_ALLOC");
+        return s ? std::atoi(s) : 0;
+    }();
+    if (countdown <= 0) return false;
+    return --countdown == 0;
+}
+
+vv10_status ensure_workspace(vv10_plan *p) {
+    if (p->ws.X) return VV10_OK;
+    Workspace ws;
+    vv10::plan_workspace_shape(p->npad, p->n_atom, p->ntiles, p->num_cu, p->prec, ws);
+    if (injected_alloc_failure()) return VV10_E_OOM;
+    const size_t ch = (size_t)p->npad * 2 * ws.Pp;
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = dalloc(&ws.X, ch);
+    if (e == hipSuccess) e = dalloc(&ws.L, ch);
+    if (e == hipSuccess) e = dalloc(&ws.Y, ch * ws.jsplit);
+    if (e == hipSuccess) e = dalloc(&ws.Z, ch);
+    if (e == hipSuccess) e = dalloc(&ws.Dpart, (size_t)p->ntiles * p->n_atom * 9);
+    if (e == hipSuccess) e = dalloc(&ws.Hpart, (size_t)ws.gsplit * ws.Pp * ws.Pp);
+    if (e == hipSuccess) e = dalloc(&ws.Hgr, (size_t)ws.P * ws.P);
+    if (e == hipSuccess) e = dalloc(&ws.gpart, (size_t)256 * ws.Pp);
+    if (e != hipSuccess) {
+        free_workspace(ws);
+        (void)hipGetLastError();
+        return hip_status(e);
+    }
+    ws.bytes = vv10::workspace_bytes(p->npad, p->n_atom, p->ntiles, ws);
+    p->ws = ws;
+    return VV10_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *vv10_status_string(vv10_status s) {
+    switch (s) {
+        case VV10_OK: return "ok";
+        case VV10_E_ARG: return "invalid argument";
+        case VV10_E_DENSITY: return "density not positive or input not finite";
+        case VV10_E_GRID_ORDER: return "atom_of is not nondecreasing";
+        case VV10_E_OOM: return "device allocation failed";
+        case VV10_E_HIP: return "HIP runtime error";
+        case VV10_E_STATE: return "plan in invalid state";
+    }
+    return "unknown status";
+}
+
+const char *vv10_version(void) { return "vv10-mi355x 0.1 (gfx950)"; }
+
+size_t vv10_footprint_bytes(int64_t n_grid, int32_t n_atom, vv10_precision prec) {
+    if (n_grid < 1 || n_atom < 1) return 0;
+    const int64_t npad = ((n_grid + vv10::kPad - 1) / vv10::kPad) * vv10::kPad;
+    const int64_t ntiles = (n_grid + vv10::kGridTile - 1) / vv10::kGridTile + n_atom;
+    Workspace ws;
+    vv10::plan_workspace_shape(npad, n_atom, (int32_t)ntiles, 256, prec, ws);
+    ws.jsplit = 8;   // upper bound over devices
+    return base_bytes(npad, n_atom, ntiles) + vv10::workspace_bytes(npad, n_atom, (int32_t)ntiles, ws);
+}
+
+vv10_status vv10_prepare(const vv10_params *params, int64_t n_grid, int32_t n_atom,
+                         const double *coords, const double *weights, const int32_t *atom_of,
+                         const double *rho, const double *grad_rho, vv10_precision prec,
+                         hipStream_t stream, vv10_plan **out) {
+    if (!out) return VV10_E_ARG;
+    *out = nullptr;
+    if (!params || !coords || !weights || !atom_of || !rho || !grad_rho) return VV10_E_ARG;
+    if (n_grid < 1 || n_atom < 1 || n_grid > (int64_t)INT32_MAX - vv10::kPad) return VV10_E_ARG;
+    if (!(params->b > 0.0) || !std::isfinite(params->b) || !(params->C >= 0.0) ||
+        !std::isfinite(params->C))
+        return VV10_E_ARG;
+    if (prec != VV10_FP64 && prec != VV10_MIXED_FP32 && prec != VV10_MIXED_BF16X3) return VV10_E_ARG;
+    // The mixed contraction kernels are not part of this build yet.
+    if (prec != VV10_FP64) return VV10_E_ARG;
+
+    vv10_plan *p = new (std::nothrow) vv10_plan();
+    if (!p) return VV10_E_OOM;
+    p->prm = *params;
+    p->beta = std::pow(3.0 / (params->b * params->b), 0.75) / 32.0;
+    p->n = n_grid;
+    p->npad = ((n_grid + vv10::kPad - 1) / vv10::kPad) * vv10::kPad;
+    p->n_atom = n_atom;
+    p->prec = prec;
+    p->stream = stream;
+    hipError_t e = hipGetDevice(&p->device);
+    if (e == hipSuccess) {
+        int cu = 0;
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && cu > 0)
+            p->num_cu = cu;
+    }
+    const int64_t npad = p->npad;
+    if (e == hipSuccess) e = dalloc(&p->P0, npad);
+    if (e == hipSuccess) e = dalloc(&p->P1, npad);
+    if (e == hipSuccess) e = dalloc(&p->P0f, npad);
+    if (e == hipSuccess) e = dalloc(&p->P1f, npad);
+    if (e == hipSuccess) e = dalloc(&p->F, (size_t)vv10::NF * npad);
+    if (e == hipSuccess) e = dalloc(&p->I, (size_t)vv10::NI * npad);
+    if (e == hipSuccess) e = dalloc(&p->atom_of, npad);
+    if (e == hipSuccess) e = dalloc(&p->d_seg, (size_t)n_atom + 1);
+    if (e == hipSuccess) e = dalloc(&p->red, reduction_doubles(npad));
+    if (e == hipSuccess) e = dalloc(&p->flag, (size_t)n_atom + 2);
+    if (e != hipSuccess) {
+        vv10_status st = hip_status(e);
+        (void)hipGetLastError();
+        free_plan(p);
+        return st;
+    }
+    e = vv10::launch_prepare(p, coords, weights, atom_of, rho, grad_rho);
+    std::vector<int32_t> flag((size_t)n_atom + 2);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(flag.data(), p->flag, flag.size() * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        free_plan(p);
+        return VV10_E_HIP;
+    }
+    if (flag[0] != 0) {
+        free_plan(p);
+        if (flag[0] & 4) return VV10_E_ARG;
+        if (flag[0] & 1) return VV10_E_DENSITY;
+        return VV10_E_GRID_ORDER;
+    }
+    // atom segments (empty atoms get zero-length segments)
+    p->seg.assign((size_t)n_atom + 1, 0);
+    p->seg[n_atom] = n_grid;
+    for (int32_t A = n_atom - 1; A >= 0; --A)
+        p->seg[A] = flag[1 + A] >= 0 ? flag[1 + A] : p->seg[A + 1];
+    // grid-term tiles: kGridTile consecutive points of one atom
+    p->tile_first.assign((size_t)n_atom + 1, 0);
+    for (int32_t A = 0; A < n_atom; ++A) {
+        p->tile_first[A] = (int32_t)p->tile_i0.size();
+        for (int64_t i0 = p->seg[A]; i0 < p->seg[A + 1]; i0 += vv10::kGridTile) {
+            p->tile_i0.push_back((int32_t)i0);
+            p->tile_n.push_back((int32_t)std::min<int64_t>(vv10::kGridTile, p->seg[A + 1] - i0));
+            p->tile_atom.push_back(A);
+        }
+    }
+    p->ntiles = (int32_t)p->tile_i0.size();
+    p->tile_first[n_atom] = p->ntiles;
+    if (e == hipSuccess) e = dalloc(&p->d_tile_i0, (size_t)p->ntiles);
+    if (e == hipSuccess) e = dalloc(&p->d_tile_n, (size_t)p->ntiles);
+    if (e == hipSuccess) e = dalloc(&p->d_tile_atom, (size_t)p->ntiles);
+    if (e == hipSuccess) e = dalloc(&p->d_tile_first, (size_t)n_atom + 1);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p->d_seg, p->seg.data(), p->seg.size() * sizeof(int64_t),
+                           hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p->d_tile_i0, p->tile_i0.data(), p->tile_i0.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p->d_tile_n, p->tile_n.data(), p->tile_n.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p->d_tile_atom, p->tile_atom.data(), p->tile_atom.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p->d_tile_first, p->tile_first.data(),
+                           p->tile_first.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream);
+    // the host vectors are read by the copies above: wait before returning
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        vv10_status st = hip_status(e);
+        (void)hipGetLastError();
+        free_plan(p);
+        return st;
+    }
+    p->base_bytes = base_bytes(npad, n_atom, p->ntiles);
+    *out = p;
+    return VV10_OK;
+}
+
+vv10_status vv10_energy_potential(vv10_plan *p, double *energy, double *f_rho, double *f_gamma) {
+    if (!p) return VV10_E_STATE;
+    if (p->failed) return VV10_E_STATE;
+    if (!energy) return VV10_E_ARG;
+    hipError_t e = vv10::launch_pair_integrals(p, false);
+    if (e == hipSuccess) e = vv10::launch_potential(p, energy, f_rho, f_gamma);
+    if (e != hipSuccess) {
+        p->failed = true;
+        (void)hipGetLastError();
+        return VV10_E_HIP;
+    }
+    return VV10_OK;
+}
+
+vv10_status vv10_hessian_terms(vv10_plan *p, int32_t n_pert, const double *rho_x,
+                               const double *grad_rho_x, double *hess, double *grad,
+                               double *resp_rho, double *resp_gamma) {
+    if (!p) return VV10_E_STATE;
+    if (p->failed) return VV10_E_STATE;
+    if (n_pert != 3 * p->n_atom || !rho_x || !grad_rho_x || !hess) return VV10_E_ARG;
+    vv10_status st = ensure_workspace(p);
+    if (st != VV10_OK) return st;
+    hipError_t e = vv10::launch_pair_integrals(p, true);
+    if (e == hipSuccess) e = vv10::launch_potential(p, nullptr, nullptr, nullptr);
+    if (e == hipSuccess) e = vv10::launch_pert_prep(p, rho_x, grad_rho_x);
+    if (e == hipSuccess) e = vv10::launch_contract(p);
+    if (e == hipSuccess) e = vv10::launch_grid_terms(p);
+    if (e == hipSuccess) e = vv10::launch_assemble(p, hess, grad, resp_rho, resp_gamma);
+    if (e != hipSuccess) {
+        p->failed = true;
+        (void)hipGetLastError();
+        return VV10_E_HIP;
+    }
+    return VV10_OK;
+}
+
+void vv10_destroy(vv10_plan *p) {
+    if (!p) return;
+    (void)hipStreamSynchronize(p->stream);
+    free_plan(p);
+}
+
+}  // extern "C"

@@ -1,0 +1,107 @@
+// Internal declarations of the VV10 HIP library: the plan, its device
+// layout and the kernel launchers.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "../../include/vv10.h"
+
+namespace vv10 {
+
+// Rows of the per-point FP64 table F[NF][npad] (structure of arrays).
+enum Field {
+    F_W = 0,     // quadrature weight
+    F_RHO,       // density
+    F_GX, F_GY, F_GZ,  // density gradient
+    F_OMR,       // d omega / d rho
+    F_OMG,       // d omega / d gamma
+    F_KAR,       // d kappa / d rho
+    F_OMRR,      // d2 omega / d rho2
+    F_OMRG,      // d2 omega / d rho d gamma
+    F_OMGG,      // d2 omega / d gamma2
+    F_KARR,      // d2 kappa / d rho2
+    F_FR,        // potential f^rho (filled by the pair-integral finalisation)
+    F_FG,        // potential f^gamma
+    NF
+};
+
+// Rows of the pair-integral table I[6][npad].
+enum Integral { I_E = 0, I_U, I_W, I_A, I_B, I_C, NI };
+
+constexpr int kPad = 256;        // npad is a multiple of this
+constexpr int kGridTile = 64;    // i points per grid-term tile (one wave)
+
+struct Workspace {
+    int32_t P = 0, Pp = 0;       // perturbations and padded column count
+    int32_t ncb = 0, ngroups = 0;  // 16-column blocks per contraction group, groups
+    int32_t jsplit = 1;          // j splits of the contraction
+    int32_t gsplit = 1;          // splits of the assembly GEMM
+    int32_t bgroups = 1;         // atom groups of the grid-term kernel
+    double *X = nullptr;         // [npad][2][Pp] (p, q) channels
+    double *L = nullptr;         // [npad][2][Pp] (rho^x, gamma^x)
+    double *Y = nullptr;         // [jsplit][npad][2][Pp] contraction, then R in place
+    double *Z = nullptr;         // [npad][2][Pp] grid-position channels
+    double *Dpart = nullptr;     // [ntiles][n_atom][9] tile sums of a_i D^B_i (6) and a_i E^{Bgr}_i (3)
+    double *Hpart = nullptr;     // [gsplit][Pp][Pp]
+    double *Hgr = nullptr;       // [P][P] E_{gr,gr}
+    double *gpart = nullptr;     // [ngrad][Pp] gradient partials
+    size_t bytes = 0;
+};
+
+}  // namespace vv10
+
+struct vv10_plan {
+    vv10_params prm{};
+    double beta = 0.0;
+    int64_t n = 0, npad = 0;
+    int32_t n_atom = 0;
+    vv10_precision prec = VV10_FP64;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int num_cu = 256;
+    bool failed = false;
+
+    std::vector<int64_t> seg;       // host: atom segments, seg[A]..seg[A+1]
+    std::vector<int32_t> tile_i0, tile_n, tile_atom, tile_first;  // grid-term tiles
+    int32_t ntiles = 0;
+
+    // device memory owned by the plan
+    double4 *P0 = nullptr;   // [npad] (x, y, z, omega), coordinates shifted by the grid centroid
+    double4 *P1 = nullptr;   // [npad] (kappa, a = w rho, c = rho dkappa/drho, 0)
+    float4 *P0f = nullptr;   // FP32 copies for the mixed modes
+    float4 *P1f = nullptr;
+    double *F = nullptr;     // [NF][npad]
+    double *I = nullptr;     // [6][npad]
+    int32_t *atom_of = nullptr;   // [npad], padding rows hold n_atom
+    int64_t *d_seg = nullptr;     // [n_atom + 1]
+    int32_t *d_tile_i0 = nullptr, *d_tile_n = nullptr, *d_tile_atom = nullptr, *d_tile_first = nullptr;
+    double *red = nullptr;   // reduction scratch
+    int32_t *flag = nullptr; // [1 + n_atom + 1] validation flag and segment starts
+    size_t base_bytes = 0;
+
+    vv10::Workspace ws;
+};
+
+namespace vv10 {
+
+// Kernel launchers (each enqueues on plan->stream and returns hipGetLastError()).
+hipError_t launch_prepare(vv10_plan *p, const double *coords, const double *w,
+                          const int32_t *atom_of, const double *rho,
+                          const double *grad_rho);
+hipError_t launch_pair_integrals(vv10_plan *p, bool hessian_mode);
+hipError_t launch_potential(vv10_plan *p, double *energy, double *f_rho, double *f_gamma);
+hipError_t launch_pert_prep(vv10_plan *p, const double *rho_x, const double *grad_rho_x);
+hipError_t launch_contract(vv10_plan *p);
+hipError_t launch_grid_terms(vv10_plan *p);
+hipError_t launch_assemble(vv10_plan *p, double *hess, double *grad, double *resp_rho,
+                           double *resp_gamma);
+
+// Layout decisions shared by the host code.
+void plan_workspace_shape(int64_t npad, int32_t n_atom, int32_t ntiles, int num_cu,
+                          vv10_precision prec, Workspace &ws);
+size_t workspace_bytes(int64_t npad, int32_t n_atom, int32_t ntiles, const Workspace &ws);
+
+}  // namespace vv10

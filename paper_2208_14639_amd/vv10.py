@@ -1,0 +1,211 @@
+"""Python binding of the VV10 C ABI (include/vv10.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library ``libvv10.so``.  Functions keep the C names; array arguments are
+torch tensors on the GPU (or raw device addresses as ints) and are passed
+as plain pointers.  PyTorch is used for device memory and streams only.
+
+The library is loaded from this directory; if it is missing the import of
+any entry point raises -- there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvv10.so")
+
+VV10_OK = 0
+VV10_E_ARG = -1
+VV10_E_DENSITY = -2
+VV10_E_GRID_ORDER = -3
+VV10_E_OOM = -4
+VV10_E_HIP = -5
+VV10_E_STATE = -6
+
+VV10_FP64 = 0
+VV10_MIXED_FP32 = 1
+VV10_MIXED_BF16X3 = 2
+PRECISIONS = {"fp64": VV10_FP64, "fp32": VV10_MIXED_FP32, "bf16x3": VV10_MIXED_BF16X3}
+
+ENTRY_POINTS = ("vv10_prepare", "vv10_energy_potential", "vv10_hessian_terms",
+                "vv10_footprint_bytes", "vv10_destroy", "vv10_status_string", "vv10_version")
+
+
+class vv10_params(ctypes.Structure):
+    _fields_ = [("b", ctypes.c_double), ("C", ctypes.c_double)]
+
+
+class VV10Error(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {vv10_status_string(status)} ({status})")
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libvv10.so (raises OSError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise OSError(f"{LIB_PATH} is missing: build it with paper_2208_14639_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i64, i32, st = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int
+    lib.vv10_prepare.restype = st
+    lib.vv10_prepare.argtypes = [ctypes.POINTER(vv10_params), i64, i32, P, P, P, P, P, st, P,
+                                 ctypes.POINTER(P)]
+    lib.vv10_energy_potential.restype = st
+    lib.vv10_energy_potential.argtypes = [P, P, P, P]
+    lib.vv10_hessian_terms.restype = st
+    lib.vv10_hessian_terms.argtypes = [P, i32, P, P, P, P, P, P]
+    lib.vv10_footprint_bytes.restype = ctypes.c_size_t
+    lib.vv10_footprint_bytes.argtypes = [i64, i32, st]
+    lib.vv10_destroy.restype = None
+    lib.vv10_destroy.argtypes = [P]
+    lib.vv10_status_string.restype = ctypes.c_char_p
+    lib.vv10_status_string.argtypes = [st]
+    lib.vv10_version.restype = ctypes.c_char_p
+    lib.vv10_version.argtypes = []
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def vv10_status_string(status: int) -> str:
+    return load().vv10_status_string(status).decode()
+
+
+def vv10_version() -> str:
+    return load().vv10_version().decode()
+
+
+def vv10_footprint_bytes(n_grid: int, n_atom: int, prec: int = VV10_FP64) -> int:
+    return int(load().vv10_footprint_bytes(n_grid, n_atom, prec))
+
+
+def vv10_prepare(b: float, C: float, n_grid: int, n_atom: int, coords, weights, atom_of, rho,
+                 grad_rho, prec: int = VV10_FP64, stream=None) -> int:
+    """Returns the plan handle (an int); raises VV10Error on failure."""
+    lib = load()
+    prm = vv10_params(b, C)
+    out = ctypes.c_void_p()
+    st = lib.vv10_prepare(ctypes.byref(prm), n_grid, n_atom, _ptr(coords), _ptr(weights),
+                          _ptr(atom_of), _ptr(rho), _ptr(grad_rho), prec, _stream(stream),
+                          ctypes.byref(out))
+    if st != VV10_OK:
+        raise VV10Error(st, "vv10_prepare")
+    return out.value
+
+
+def vv10_energy_potential(plan: int, energy, f_rho=None, f_gamma=None) -> None:
+    st = load().vv10_energy_potential(plan, _ptr(energy), _ptr(f_rho), _ptr(f_gamma))
+    if st != VV10_OK:
+        raise VV10Error(st, "vv10_energy_potential")
+
+
+def vv10_hessian_terms(plan: int, n_pert: int, rho_x, grad_rho_x, hess, grad=None,
+                       resp_rho=None, resp_gamma=None) -> None:
+    st = load().vv10_hessian_terms(plan, n_pert, _ptr(rho_x), _ptr(grad_rho_x), _ptr(hess),
+                                   _ptr(grad), _ptr(resp_rho), _ptr(resp_gamma))
+    if st != VV10_OK:
+        raise VV10Error(st, "vv10_hessian_terms")
+
+
+def vv10_destroy(plan: int) -> None:
+    if plan:
+        load().vv10_destroy(plan)
+
+
+class Plan:
+    """A prepared grid on the current device (owns a vv10_plan).
+
+    ``problem`` is anything with coords, weights, atom_of, rho, grad_rho,
+    n_grid, n_atom, b, C (e.g. inputs.Problem); arrays are copied to the
+    device as FP64/int32 tensors."""
+
+    def __init__(self, problem, prec="fp64", device="cuda", stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.prec = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+        self.n = int(problem.n_grid)
+        self.n_atom = int(problem.n_atom)
+        d = self._dev
+        self.coords = d(problem.coords)
+        self.weights = d(problem.weights)
+        self.atom_of = torch.as_tensor(problem.atom_of, dtype=torch.int32).to(self.device).contiguous()
+        self.rho = d(problem.rho)
+        self.grad_rho = d(problem.grad_rho)
+        self.stream = stream
+        self.handle = vv10_prepare(problem.b, problem.C, self.n, self.n_atom, self.coords,
+                                   self.weights, self.atom_of, self.rho, self.grad_rho,
+                                   self.prec, stream)
+
+    def _dev(self, a):
+        return self.torch.as_tensor(a, dtype=self.torch.float64).to(self.device).contiguous()
+
+    def energy_potential(self):
+        t = self.torch
+        e = t.empty(1, dtype=t.float64, device=self.device)
+        fr = t.empty(self.n, dtype=t.float64, device=self.device)
+        fg = t.empty(self.n, dtype=t.float64, device=self.device)
+        vv10_energy_potential(self.handle, e, fr, fg)
+        return e, fr, fg
+
+    def hessian_terms(self, rho_x, grad_rho_x, grad=False, resp=False):
+        t = self.torch
+        P = 3 * self.n_atom
+        rx = rho_x if isinstance(rho_x, t.Tensor) and rho_x.is_cuda else self._dev(rho_x)
+        gx = grad_rho_x if isinstance(grad_rho_x, t.Tensor) and grad_rho_x.is_cuda else self._dev(grad_rho_x)
+        H = t.empty((P, P), dtype=t.float64, device=self.device)
+        g = t.empty(P, dtype=t.float64, device=self.device) if grad else None
+        rr = t.empty((P, self.n), dtype=t.float64, device=self.device) if resp else None
+        rg = t.empty((P, self.n), dtype=t.float64, device=self.device) if resp else None
+        vv10_hessian_terms(self.handle, P, rx, gx, H, g, rr, rg)
+        out = {"hess": H}
+        if grad:
+            out["grad"] = g
+        if resp:
+            out["resp_rho"], out["resp_gamma"] = rr, rg
+        return out
+
+    def close(self):
+        if self.handle:
+            vv10_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
