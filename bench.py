@@ -1,0 +1,231 @@
+#!/usr/bin/env python3
+"""Benchmark of the VV10 Hessian-term engine on one MI355X.
+
+One step is one pass of the whole hot path over one synthetic molecule
+already resident in HBM: vv10_prepare (per-point prep) ->
+vv10_energy_potential (pair integrals, potential, energy) ->
+vv10_hessian_terms (pair integrals in Hessian mode, perturbation packing,
+MFMA contraction, grid-position terms, assembly) -> vv10_destroy.
+
+Metric: grid-pair x perturbation per second, N^2 P / t_step, with N^2 the
+ordered pairs (self pairs included) and P = 3 N_atom.
+
+Prints one JSON line with the metric, a roofline entry for the dominant
+kernel (the perturbation contraction, timed with HIP events recorded by the
+library on the plan's stream) and a CPU baseline (the FP64 oracle on the
+host, rank 0 only).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAKS_TFLOPS = {"mfma_f64": 78.6, "mfma_f32": 157.3, "mfma_bf16": 2500.0, "valu_f32": 157.3,
+                "valu_f64": 78.6}
+HBM_GBS = 8000.0
+# algorithmic work per unit
+FLOPS_PER_PAIR_PERT = 8          # contraction: 4 FMAs per pair and perturbation
+FLOPS_PER_PAIR_INTEGRALS = 38    # E, U, W (26) + A, B, C (12)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_sha(rels):
+    h = hashlib.sha256()
+    for rel in rels:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_key, workload, prec):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernel source changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f).get(f"{kernel_key}:{workload}:{prec}")
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_sha") != source_sha(rec["sources"]):
+        return None
+    return rec["bytes_per_launch"]
+
+
+def cpu_baseline(p, budget_s=30.0):
+    """FP64 oracle on the host.  Full workload when it fits the budget, else
+    the dominant O(N^2 P) step (response rows) on a row sample."""
+    import oracle
+    g, gx = oracle.problem_inputs(p)
+    n, P = p.n_grid, p.n_pert
+    est_rate = 3e9 * oracle.num_threads() / 8      # pair*pert/s, measured order of magnitude
+    if n * n * P / est_rate <= budget_s:
+        t0 = time.perf_counter()
+        H, _ = oracle.hessian_terms(p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b, p.C,
+                                    p.rho_x, gx)
+        e0, fr0, fg0 = oracle.energy_potential(p.coords, p.weights, p.rho, g, p.b, p.C)
+        dt = time.perf_counter() - t0
+        return dict(value=n * n * P / dt, unit="pair*pert/s", cores=oracle.num_threads(),
+                    kind="oracle", seconds=dt,
+                    sample=f"whole workload: energy, potential and Hessian terms, N={n}, P={P}"), \
+            dict(H=H, E=e0, f_rho=fr0, f_gamma=fg0)
+    # row sample: calibrate on 16 rows, then size to ~10 s
+    t0 = time.perf_counter()
+    oracle.response_rows(0, 16, p.coords, p.weights, p.rho, g, p.b, p.C, p.rho_x, gx)
+    t16 = time.perf_counter() - t0
+    k = max(16, min(n, int(16 * 10.0 / max(t16, 1e-3))))
+    t0 = time.perf_counter()
+    oracle.response_rows(0, k, p.coords, p.weights, p.rho, g, p.b, p.C, p.rho_x, gx)
+    dt = time.perf_counter() - t0
+    return dict(value=k * n * P / dt, unit="pair*pert/s", cores=oracle.num_threads(),
+                kind="oracle", seconds=dt,
+                sample=f"response rows 0..{k} of N={n}, P={P} (dominant N^2 P step incl. one "
+                       f"full pair-integral pass)"), None
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="water_hexamer",
+                    choices=["water_dimer", "water_hexamer", "water_20mer"])
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one device copy of 256 MiB first (HBM counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this engine runs on one GPU; multi-GPU runs are not supported "
+              "(see DESIGN.md for how the path would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2208_14639_amd import inputs, vv10
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    vv10.load()
+    prec = vv10.PRECISIONS[args.prec]
+
+    p = inputs.make_workload(args.workload)
+    n, na, P = p.n_grid, p.n_atom, p.n_pert
+    log(f"workload {args.workload}: N={n} atoms={na} P={P} prec={args.prec}")
+    f64 = lambda a: torch.as_tensor(a, dtype=torch.float64).to(dev).contiguous()
+    coords, w, rho, grad = f64(p.coords), f64(p.weights), f64(p.rho), f64(p.grad_rho)
+    atom_of = torch.as_tensor(p.atom_of, dtype=torch.int32).to(dev).contiguous()
+    rho_x, grad_x = f64(p.rho_x), f64(p.grad_rho_x)
+    energy = torch.empty(1, dtype=torch.float64, device=dev)
+    f_rho = torch.empty(n, dtype=torch.float64, device=dev)
+    f_gamma = torch.empty(n, dtype=torch.float64, device=dev)
+    hess = torch.empty((P, P), dtype=torch.float64, device=dev)
+    gradient = torch.empty(P, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream().cuda_stream
+
+    if args.copy_calibration:
+        a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)   # 256 MiB
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    def step():
+        h = vv10.vv10_prepare(p.b, p.C, n, na, coords, w, atom_of, rho, grad, prec, stream)
+        try:
+            vv10.vv10_set_timing(h, True)
+            vv10.vv10_energy_potential(h, energy, f_rho, f_gamma)
+            st_e = vv10.vv10_stage_times(h)
+            vv10.vv10_hessian_terms(h, P, rho_x, grad_x, hess, gradient, None, None)
+            st = vv10.vv10_stage_times(h)
+        finally:
+            vv10.vv10_destroy(h)
+        st["pair_energy"] = st_e["pair"]
+        st["potential_energy"] = st_e["potential"]
+        return st
+
+    for k in range(args.warmup):
+        step()
+        log(f"warmup {k + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    stages = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        stages.append(step())
+        log(f"step {k + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dt = (t1 - t0) / args.steps
+    stage_ms = {k: float(np.mean([s[k] for s in stages])) for k in stages[0]}
+    pair_pert = float(n) * n * P
+    value = pair_pert / dt
+
+    t_con = stage_ms["contract"] * 1e-3
+    mfma_key = {"fp64": "mfma_f64", "fp32": "mfma_f32", "bf16x3": "mfma_bf16"}[args.prec]
+    achieved = FLOPS_PER_PAIR_PERT * pair_pert / t_con / 1e12
+    traffic = measured_traffic("contract", args.workload, args.prec)
+    roofline = dict(bound="mfma", kernel=f"k_contract_{args.prec}", achieved=achieved,
+                    peak=PEAKS_TFLOPS[mfma_key], unit="TFLOP/s",
+                    frac=achieved / PEAKS_TFLOPS[mfma_key], traffic=traffic)
+    pair_rate = float(n) * n / (stage_ms["pair_energy"] * 1e-3)
+
+    out = {
+        "metric": "VV10 Hessian grid-pair*perturbation/s",
+        "value": value,
+        "unit": "pair*pert/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f32+f64"}[args.prec],
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n_grid": n, "n_atom": na, "n_pert": P,
+                   "precision": args.prec, "b": p.b, "C": p.C, "seed": p.seed},
+        "roofline": roofline,
+        "stage_ms": stage_ms,
+        "pair_kernel": {"pairs_per_s": pair_rate,
+                        "valu_tflops": 26 * n * n / (stage_ms["pair_energy"] * 1e-3) / 1e12},
+        "footprint_bytes": vv10.vv10_footprint_bytes(n, na, prec),
+    }
+
+    # results of the last step, checked against the oracle when it ran in full
+    H = hess.cpu().numpy()
+    out["checks"] = {"hess_symmetric": bool(np.array_equal(H, H.T)),
+                     "hess_row_sum_rel": float(np.max(np.abs(H.reshape(P, na, 3).sum(axis=1)))
+                                               / np.max(np.abs(H)))}
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) running ...")
+        cb, ref = cpu_baseline(p)
+        out["cpu_baseline"] = cb
+        if ref is not None:
+            out["errors_vs_oracle"] = {
+                "energy_rel": abs(energy.item() - ref["E"]) / abs(ref["E"]),
+                "f_rho_normwise": float(np.max(np.abs(f_rho.cpu().numpy() - ref["f_rho"]))
+                                        / np.max(np.abs(ref["f_rho"]))),
+                "f_gamma_normwise": float(np.max(np.abs(f_gamma.cpu().numpy() - ref["f_gamma"]))
+                                          / np.max(np.abs(ref["f_gamma"]))),
+                "hess_normwise": float(np.max(np.abs(H - ref["H"])) / np.max(np.abs(ref["H"]))),
+                "hess_max_abs": float(np.max(np.abs(H - ref["H"]))),
+            }
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -133,6 +133,29 @@ vv10_status vv10_hessian_terms(vv10_plan *plan, int32_t n_pert, const double *rh
                                const double *grad_rho_x, double *hess, double *grad,
                                double *resp_rho, double *resp_gamma);
 
+/* Stages of the library's launch sequence, for vv10_stage_times. */
+typedef enum {
+    VV10_STAGE_PAIR = 0,      /* pair integrals E, U, W (and A, B, C in a Hessian call) */
+    VV10_STAGE_POTENTIAL = 1, /* f^rho, f^gamma and the energy reduction */
+    VV10_STAGE_PERT_PREP = 2, /* packing of the perturbation channels */
+    VV10_STAGE_CONTRACT = 3,  /* perturbation-batched contraction (MFMA) */
+    VV10_STAGE_GRID = 4,      /* grid-position intermediates */
+    VV10_STAGE_ASSEMBLE = 5,  /* Hessian assembly (and gradient) */
+    VV10_NUM_STAGES = 6
+} vv10_stage;
+
+/* Enable (1) or disable (0) per-stage timing: while enabled, every call
+ * records a HIP event pair on the plan's stream around each stage it runs.
+ * Errors: VV10_E_STATE (NULL plan), VV10_E_HIP (event creation failed). */
+vv10_status vv10_set_timing(vv10_plan *plan, int32_t enable);
+
+/* Device time in milliseconds of each stage's most recent run, from the
+ * events above; ms has VV10_NUM_STAGES entries (HOST memory), stages never
+ * run report 0.  Waits for the recorded events to complete.
+ * Errors: VV10_E_STATE (NULL plan or timing never enabled), VV10_E_ARG
+ * (ms NULL), VV10_E_HIP. */
+vv10_status vv10_stage_times(vv10_plan *plan, double *ms);
+
 /* Device bytes a plan for this size holds once vv10_hessian_terms has run
  * (an upper bound; vv10_energy_potential alone needs less). */
 size_t vv10_footprint_bytes(int64_t n_grid, int32_t n_atom, vv10_precision prec);

@@ -1,6 +1,7 @@
 // Hessian assembly (Section II.B, nine-term split with the weight terms
 // zero).  All FP64.
 //
+// 0. k_sum_splits adds the partial contractions of the j splits.
 // 1. k_resp, per point i and perturbation x:
 //      Yr = Y_p + rho omega_r Y_q + loc_rho,   Yg = rho omega_g Y_q + loc_gamma
 //    (the paper's inner sums sum_j w_j (f^{rho rho}_ij rho^x_j + f^{rho gamma}_ij gamma^x_j)
@@ -28,6 +29,15 @@
 namespace vv10 {
 
 namespace {
+
+// Y[0] += Y[1] + ... + Y[S-1] over the j splits of the contraction, in split order.
+__global__ __launch_bounds__(256) void k_sum_splits(int64_t len, int S, double *__restrict__ Y) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= len) return;
+    double a = Y[k];
+    for (int s = 1; s < S; ++s) a += Y[s * len + k];
+    Y[k] = a;
+}
 
 __global__ __launch_bounds__(256) void k_resp(
     int64_t n, int64_t npad, int32_t P, int32_t Pp, int32_t n_atom,
@@ -227,6 +237,10 @@ hipError_t launch_assemble(vv10_plan *p, double *hess, double *grad, double *res
                            double *resp_gamma) {
     const Workspace &ws = p->ws;
     const int64_t n = p->n;
+    if (ws.jsplit > 1) {
+        const int64_t len = p->npad * 2 * ws.Pp;
+        k_sum_splits<<<(unsigned)((len + 255) / 256), 256, 0, p->stream>>>(len, ws.jsplit, ws.Y);
+    }
     {
         dim3 grid((unsigned)((n + 3) / 4), (unsigned)((ws.Pp + 63) / 64));
         k_resp<<<grid, 256, 0, p->stream>>>(n, p->npad, ws.P, ws.Pp, p->n_atom, p->atom_of, p->F,

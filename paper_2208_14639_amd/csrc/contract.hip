@@ -114,15 +114,6 @@ __global__ __launch_bounds__(256, 2) void k_contract_f64(
         }
 }
 
-// Y[0] += Y[1] + ... + Y[S-1], in split order.
-__global__ __launch_bounds__(256) void k_sum_splits(int64_t len, int S, double *__restrict__ Y) {
-    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (k >= len) return;
-    double a = Y[k];
-    for (int s = 1; s < S; ++s) a += Y[s * len + k];
-    Y[k] = a;
-}
-
 template <int NCB>
 hipError_t run_f64(vv10_plan *p) {
     const Workspace &ws = p->ws;
@@ -151,12 +142,6 @@ hipError_t launch_contract(vv10_plan *p) {
         }
     } else {
         return hipErrorInvalidValue;   // mixed contraction: see contract_mixed.hip
-    }
-    if (e != hipSuccess) return e;
-    if (ws.jsplit > 1) {
-        const int64_t len = p->npad * 2 * ws.Pp;
-        k_sum_splits<<<(unsigned)((len + 255) / 256), 256, 0, p->stream>>>(len, ws.jsplit, ws.Y);
-        e = hipGetLastError();
     }
     return e;
 }

@@ -97,6 +97,8 @@ void free_workspace(Workspace &ws) {
 
 void free_plan(vv10_plan *p) {
     if (!p) return;
+    for (auto &ev : p->ev)
+        if (ev) (void)hipEventDestroy(ev);
     free_workspace(p->ws);
     dfree(p->P0);
     dfree(p->P1);
@@ -155,6 +157,17 @@ vv10_status ensure_workspace(vv10_plan *p) {
     ws.bytes = vv10::workspace_bytes(p->npad, p->n_atom, p->ntiles, ws);
     p->ws = ws;
     return VV10_OK;
+}
+
+// Run one stage, bracketed by timing events when timing is enabled.
+template <typename Fn>
+hipError_t stage(vv10_plan *p, int k, Fn &&fn) {
+    hipError_t e = hipSuccess;
+    if (p->timing) e = hipEventRecord(p->ev[2 * k], p->stream);
+    if (e == hipSuccess) e = fn();
+    if (e == hipSuccess && p->timing) e = hipEventRecord(p->ev[2 * k + 1], p->stream);
+    if (e == hipSuccess && p->timing) p->ran[k] = true;
+    return e;
 }
 
 }  // namespace
@@ -303,8 +316,9 @@ vv10_status vv10_energy_potential(vv10_plan *p, double *energy, double *f_rho, d
     if (!p) return VV10_E_STATE;
     if (p->failed) return VV10_E_STATE;
     if (!energy) return VV10_E_ARG;
-    hipError_t e = vv10::launch_pair_integrals(p, false);
-    if (e == hipSuccess) e = vv10::launch_potential(p, energy, f_rho, f_gamma);
+    hipError_t e = stage(p, VV10_STAGE_PAIR, [&] { return vv10::launch_pair_integrals(p, false); });
+    if (e == hipSuccess)
+        e = stage(p, VV10_STAGE_POTENTIAL, [&] { return vv10::launch_potential(p, energy, f_rho, f_gamma); });
     if (e != hipSuccess) {
         p->failed = true;
         (void)hipGetLastError();
@@ -321,16 +335,51 @@ vv10_status vv10_hessian_terms(vv10_plan *p, int32_t n_pert, const double *rho_x
     if (n_pert != 3 * p->n_atom || !rho_x || !grad_rho_x || !hess) return VV10_E_ARG;
     vv10_status st = ensure_workspace(p);
     if (st != VV10_OK) return st;
-    hipError_t e = vv10::launch_pair_integrals(p, true);
-    if (e == hipSuccess) e = vv10::launch_potential(p, nullptr, nullptr, nullptr);
-    if (e == hipSuccess) e = vv10::launch_pert_prep(p, rho_x, grad_rho_x);
-    if (e == hipSuccess) e = vv10::launch_contract(p);
-    if (e == hipSuccess) e = vv10::launch_grid_terms(p);
-    if (e == hipSuccess) e = vv10::launch_assemble(p, hess, grad, resp_rho, resp_gamma);
+    hipError_t e = stage(p, VV10_STAGE_PAIR, [&] { return vv10::launch_pair_integrals(p, true); });
+    if (e == hipSuccess)
+        e = stage(p, VV10_STAGE_POTENTIAL, [&] { return vv10::launch_potential(p, nullptr, nullptr, nullptr); });
+    if (e == hipSuccess)
+        e = stage(p, VV10_STAGE_PERT_PREP, [&] { return vv10::launch_pert_prep(p, rho_x, grad_rho_x); });
+    if (e == hipSuccess) e = stage(p, VV10_STAGE_CONTRACT, [&] { return vv10::launch_contract(p); });
+    if (e == hipSuccess) e = stage(p, VV10_STAGE_GRID, [&] { return vv10::launch_grid_terms(p); });
+    if (e == hipSuccess)
+        e = stage(p, VV10_STAGE_ASSEMBLE,
+                  [&] { return vv10::launch_assemble(p, hess, grad, resp_rho, resp_gamma); });
     if (e != hipSuccess) {
         p->failed = true;
         (void)hipGetLastError();
         return VV10_E_HIP;
+    }
+    return VV10_OK;
+}
+
+vv10_status vv10_set_timing(vv10_plan *p, int32_t enable) {
+    if (!p) return VV10_E_STATE;
+    if (enable && !p->ev[0]) {
+        for (auto &ev : p->ev) {
+            if (hipEventCreate(&ev) != hipSuccess) {
+                (void)hipGetLastError();
+                return VV10_E_HIP;
+            }
+        }
+    }
+    p->timing = enable != 0;
+    return VV10_OK;
+}
+
+vv10_status vv10_stage_times(vv10_plan *p, double *ms) {
+    if (!p || !p->ev[0]) return VV10_E_STATE;
+    if (!ms) return VV10_E_ARG;
+    for (int k = 0; k < VV10_NUM_STAGES; ++k) {
+        ms[k] = 0.0;
+        if (!p->ran[k]) continue;
+        float t = 0.f;
+        if (hipEventSynchronize(p->ev[2 * k + 1]) != hipSuccess ||
+            hipEventElapsedTime(&t, p->ev[2 * k], p->ev[2 * k + 1]) != hipSuccess) {
+            (void)hipGetLastError();
+            return VV10_E_HIP;
+        }
+        ms[k] = t;
     }
     return VV10_OK;
 }

@@ -82,6 +82,11 @@ struct vv10_plan {
     int32_t *flag = nullptr; // [1 + n_atom + 1] validation flag and segment starts
     size_t base_bytes = 0;
 
+    // per-stage timing (vv10_set_timing)
+    bool timing = false;
+    hipEvent_t ev[2 * VV10_NUM_STAGES] = {};
+    bool ran[VV10_NUM_STAGES] = {};
+
     vv10::Workspace ws;
 };
 

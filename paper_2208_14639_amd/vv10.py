@@ -29,8 +29,7 @@ VV10_MIXED_FP32 = 1
 VV10_MIXED_BF16X3 = 2
 PRECISIONS = {"fp64": VV10_FP64, "fp32": VV10_MIXED_FP32, "bf16x3": VV10_MIXED_BF16X3}
 
-ENTRY_POINTS = ("vv10_prepare", "vv10_energy_potential", "vv10_hessian_terms",
-                "vv10_footprint_bytes", "vv10_destroy", "vv10_status_string", "vv10_version")
+STAGES = ("pair", "potential", "pert_prep", "contract", "grid", "assemble")
 
 
 class vv10_params(ctypes.Structure):
@@ -70,6 +69,10 @@ def load() -> ctypes.CDLL:
     lib.vv10_status_string.argtypes = [st]
     lib.vv10_version.restype = ctypes.c_char_p
     lib.vv10_version.argtypes = []
+    lib.vv10_set_timing.restype = st
+    lib.vv10_set_timing.argtypes = [P, i32]
+    lib.vv10_stage_times.restype = st
+    lib.vv10_stage_times.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
     _lib = lib
     return lib
 
@@ -133,6 +136,21 @@ def vv10_hessian_terms(plan: int, n_pert: int, rho_x, grad_rho_x, hess, grad=Non
                                    _ptr(grad), _ptr(resp_rho), _ptr(resp_gamma))
     if st != VV10_OK:
         raise VV10Error(st, "vv10_hessian_terms")
+
+
+def vv10_set_timing(plan: int, enable: bool = True) -> None:
+    st = load().vv10_set_timing(plan, 1 if enable else 0)
+    if st != VV10_OK:
+        raise VV10Error(st, "vv10_set_timing")
+
+
+def vv10_stage_times(plan: int) -> dict:
+    """Milliseconds per stage of the most recent runs (host dict)."""
+    buf = (ctypes.c_double * len(STAGES))()
+    st = load().vv10_stage_times(plan, buf)
+    if st != VV10_OK:
+        raise VV10Error(st, "vv10_stage_times")
+    return dict(zip(STAGES, list(buf)))
 
 
 def vv10_destroy(plan: int) -> None:
