@@ -30,12 +30,15 @@ namespace vv10 {
 
 namespace {
 
-// Y[0] += Y[1] + ... + Y[S-1] over the j splits of the contraction, in split order.
-__global__ __launch_bounds__(256) void k_sum_splits(int64_t len, int S, double *__restrict__ Y) {
+// Y = Ypart[0] + ... + Ypart[S-1] over the j splits of the contraction, in
+// split order and in FP64 (the partials are FP64 or FP32).
+template <typename T>
+__global__ __launch_bounds__(256) void k_sum_splits(int64_t len, int S, const T *__restrict__ Yp,
+                                                    double *__restrict__ Y) {
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (k >= len) return;
-    double a = Y[k];
-    for (int s = 1; s < S; ++s) a += Y[s * len + k];
+    double a = (double)Yp[k];
+    for (int s = 1; s < S; ++s) a += (double)Yp[s * len + k];
     Y[k] = a;
 }
 
@@ -237,9 +240,15 @@ hipError_t launch_assemble(vv10_plan *p, double *hess, double *grad, double *res
                            double *resp_gamma) {
     const Workspace &ws = p->ws;
     const int64_t n = p->n;
-    if (ws.jsplit > 1) {
+    {
         const int64_t len = p->npad * 2 * ws.Pp;
-        k_sum_splits<<<(unsigned)((len + 255) / 256), 256, 0, p->stream>>>(len, ws.jsplit, ws.Y);
+        const unsigned nb = (unsigned)((len + 255) / 256);
+        if (p->prec != VV10_FP64)
+            k_sum_splits<float><<<nb, 256, 0, p->stream>>>(len, ws.jsplit,
+                                                           static_cast<const float *>(ws.Ypart), ws.Y);
+        else if (ws.Ypart != ws.Y)
+            k_sum_splits<double><<<nb, 256, 0, p->stream>>>(len, ws.jsplit,
+                                                            static_cast<const double *>(ws.Ypart), ws.Y);
     }
     {
         dim3 grid((unsigned)((n + 3) / 4), (unsigned)((ws.Pp + 63) / 64));

@@ -16,12 +16,25 @@
 // without the delta_ij local terms, which the assembly adds.
 //
 // This is a dense (2N x 2N) x (2N x P) product whose left operand is never
-// stored: each 16 x 4 block of (i, j) pairs is formed once in registers, one
-// pair per lane in the MFMA A-operand layout, and fed to four
-// v_mfma_f64_16x16x4 per 16 perturbation columns (K_pp X_p, K_pq X_q into
-// Y_p; K_qp X_p, K_qq X_q into Y_q).  X chunks are staged in LDS and shared
-// by the four waves of a workgroup; every wave owns 16 outer points and all
-// columns of its column group, with FP64 accumulators in registers.
+// stored: every (i, j) pair is formed once, in registers, directly in the
+// MFMA A-operand layout.  X chunks are staged in LDS and shared by the four
+// waves of a workgroup; every wave owns 16 outer points and all columns of
+// its column group, with accumulators in registers.  Three arithmetic modes:
+//
+//  FP64:   one pair per lane per 16 x 4 block, four v_mfma_f64_16x16x4 per
+//          16 columns (K_pp X_p, K_pq X_q into Y_p; K_qp X_p, K_qq X_q into Y_q).
+//  FP32:   the same scheme with v_mfma_f32_16x16x4 and FP32 pair arithmetic.
+//  BF16X3: four pairs per lane per 16 x 16 block; the MFMA K index runs over
+//          (j, channel), k = 2 (j mod 16) + c, so one v_mfma_f32_16x16x32_bf16
+//          contracts K_pp, K_pq (or K_qp, K_qq) of 16 j with both channels of X.
+//          Each operand is split as v = hi + lo with hi = bf16(v),
+//          lo = bf16(v - hi), and three products hi*hi + hi*lo + lo*hi are
+//          accumulated (relative error about 2^-16 per product).
+//
+// The mixed modes accumulate one j-split in FP32 and write FP32 partials,
+// which the assembly sums over splits in FP64.
+#include <type_traits>
+
 #include "dev_common.h"
 #include "vv10_internal.h"
 
@@ -114,36 +127,279 @@ __global__ __launch_bounds__(256, 2) void k_contract_f64(
         }
 }
 
+// ---------------------------------------------------------------------------
+// FP32 MFMA
+// ---------------------------------------------------------------------------
 template <int NCB>
-hipError_t run_f64(vv10_plan *p) {
+__global__ __launch_bounds__(256, 2) void k_contract_f32(
+    int64_t npad, int64_t jlen, int32_t Pp, const float4 *__restrict__ P0,
+    const float4 *__restrict__ P1, const float *__restrict__ X, float *__restrict__ Yout) {
+    constexpr int NC = NCB * 16;
+    __shared__ float4 sA[kJC], sB[kJC];
+    __shared__ __attribute__((aligned(16))) float sX[kJC * 2 * NC];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m = lane & 15, kq = lane >> 4;
+    const int64_t ibase = (int64_t)blockIdx.x * 64 + wave * 16;
+    const int col0 = blockIdx.y * NC;
+    const int64_t jbeg = (int64_t)blockIdx.z * jlen;
+    const int64_t jend = min(npad, jbeg + jlen);
+    const float4 a0 = P0[ibase + m], a1 = P1[ibase + m];
+    const float ci = a1.z;
+    v4f accp[NCB], accq[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+        accp[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
+        accq[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
+    }
+    for (int64_t j0 = jbeg; j0 < jend; j0 += kJC) {
+        __syncthreads();
+        if (tid < kJC) {
+            sA[tid] = P0[j0 + tid];
+            sB[tid] = P1[j0 + tid];
+        }
+        constexpr int H4 = NC / 4;
+        for (int e = tid; e < kJC * 2 * H4; e += 256) {
+            const int row = e / H4, cc = e - row * H4;
+            const float4 v = *reinterpret_cast<const float4 *>(X + (j0 * 2 + row) * Pp + col0 + 4 * cc);
+            *reinterpret_cast<float4 *>(sX + row * NC + 4 * cc) = v;
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int jj = 0; jj < kJC; jj += 4) {
+            const int jl = jj + kq;
+            const float4 b0 = sA[jl], b1 = sB[jl];
+            const float dx = a0.x - b0.x, dy = a0.y - b0.y, dz = a0.z - b0.z;
+            const float R2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+            const float g = __builtin_fmaf(a0.w, R2, a1.x);
+            const float gp = __builtin_fmaf(b0.w, R2, b1.x);
+            const float s = g + gp, t = g * gp;
+            const float r = rcp32(t * s);
+            const float phi = -1.5f * r;
+            const float sr = s * r;
+            const float ig = gp * sr, igp = g * sr, is = t * r;
+            const float Pg = -phi * (ig + is);
+            const float Pgp = -phi * (igp + is);
+            const float Pgg = 2.f * phi * __builtin_fmaf(ig, igp, is * is);
+            const float cj = b1.z;
+            const float u = __builtin_fmaf(ci, Pgg, Pgp);
+            const float kpp = __builtin_fmaf(cj, u, __builtin_fmaf(ci, Pg, phi));
+            const float kpq = R2 * u;
+            const float kqp = R2 * __builtin_fmaf(cj, Pgg, Pg);
+            const float kqq = R2 * R2 * Pgg;
+            const float *xr = sX + (jl * 2) * NC + m;
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                const float xp = xr[cb * 16];
+                accp[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(kpp, xp, accp[cb], 0, 0, 0);
+                accq[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(kqp, xp, accq[cb], 0, 0, 0);
+            }
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                const float xq = xr[NC + cb * 16];
+                accp[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(kpq, xq, accp[cb], 0, 0, 0);
+                accq[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(kqq, xq, accq[cb], 0, 0, 0);
+            }
+        }
+    }
+    // D layout of the FP32 MFMAs (measured on gfx950): item r of lane l holds
+    // row 4 (l/16) + r, column l%16
+    float *Yb = Yout + (int64_t)blockIdx.z * npad * 2 * Pp;
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t row = ibase + 4 * kq + r;
+            Yb[(row * 2 + 0) * Pp + col0 + cb * 16 + m] = accp[cb][r];
+            Yb[(row * 2 + 1) * Pp + col0 + cb * 16 + m] = accq[cb][r];
+        }
+}
+
+// ---------------------------------------------------------------------------
+// split-BF16 MFMA
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ void split_bf16(float v, __bf16 &hi, __bf16 &lo) {
+    hi = (__bf16)v;
+    lo = (__bf16)(v - (float)hi);
+}
+
+constexpr int kJB = 2;    // 16-point j blocks per LDS stage
+
+template <int NCB>
+__global__ __launch_bounds__(256, 2) void k_contract_bf16x3(
+    int64_t npad, int64_t jlen, int32_t Pp, const float4 *__restrict__ P0,
+    const float4 *__restrict__ P1, const bf16x8 *__restrict__ Xhi,
+    const bf16x8 *__restrict__ Xlo, float *__restrict__ Yout) {
+    constexpr int NC = NCB * 16;
+    constexpr int JC = 16 * kJB;
+    __shared__ float4 sA[JC], sB[JC];
+    __shared__ bf16x8 sH[kJB * NC * 4], sL[kJB * NC * 4];   // [jblock][col][g]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m = lane & 15, g = lane >> 4;
+    const int64_t ibase = (int64_t)blockIdx.x * 64 + wave * 16;
+    const int col0 = blockIdx.y * NC;
+    const int64_t jbeg = (int64_t)blockIdx.z * jlen;
+    const int64_t jend = min(npad, jbeg + jlen);
+    const float4 a0 = P0[ibase + m], a1 = P1[ibase + m];
+    const float ci = a1.z;
+    v4f accp[NCB], accq[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+        accp[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
+        accq[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
+    }
+    for (int64_t j0 = jbeg; j0 < jend; j0 += JC) {
+        __syncthreads();
+        if (tid < JC) {
+            sA[tid] = P0[j0 + tid];
+            sB[tid] = P1[j0 + tid];
+        }
+        // units of 8 bf16: global [jblock][Pp][4], LDS [jblock][NC][4]
+        for (int e = tid; e < kJB * NC * 4; e += 256) {
+            const int jb = e / (NC * 4), rem = e - jb * NC * 4;
+            const int64_t src = ((j0 / 16 + jb) * Pp + col0) * 4 + rem;
+            sH[e] = Xhi[src];
+            sL[e] = Xlo[src];
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int jb = 0; jb < kJB; ++jb) {
+            bf16x8 aph, apl, aqh, aql;
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                const int jl = 16 * jb + 4 * g + jj;
+                const float4 b0 = sA[jl], b1 = sB[jl];
+                const float dx = a0.x - b0.x, dy = a0.y - b0.y, dz = a0.z - b0.z;
+                const float R2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+                const float gg = __builtin_fmaf(a0.w, R2, a1.x);
+                const float gp = __builtin_fmaf(b0.w, R2, b1.x);
+                const float s = gg + gp, t = gg * gp;
+                const float r = rcp32(t * s);
+                const float phi = -1.5f * r;
+                const float sr = s * r;
+                const float ig = gp * sr, igp = gg * sr, is = t * r;
+                const float Pg = -phi * (ig + is);
+                const float Pgp = -phi * (igp + is);
+                const float Pgg = 2.f * phi * __builtin_fmaf(ig, igp, is * is);
+                const float cj = b1.z;
+                const float u = __builtin_fmaf(ci, Pgg, Pgp);
+                const float kpp = __builtin_fmaf(cj, u, __builtin_fmaf(ci, Pg, phi));
+                const float kpq = R2 * u;
+                const float kqp = R2 * __builtin_fmaf(cj, Pgg, Pg);
+                const float kqq = R2 * R2 * Pgg;
+                __bf16 h, l;
+                split_bf16(kpp, h, l); aph[2 * jj] = h; apl[2 * jj] = l;
+                split_bf16(kpq, h, l); aph[2 * jj + 1] = h; apl[2 * jj + 1] = l;
+                split_bf16(kqp, h, l); aqh[2 * jj] = h; aql[2 * jj] = l;
+                split_bf16(kqq, h, l); aqh[2 * jj + 1] = h; aql[2 * jj + 1] = l;
+            }
+            const bf16x8 *hp = sH + (jb * NC + m) * 4 + g;
+            const bf16x8 *lp = sL + (jb * NC + m) * 4 + g;
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                const bf16x8 bh = hp[cb * 64];
+                accp[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aph, bh, accp[cb], 0, 0, 0);
+                accq[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aqh, bh, accq[cb], 0, 0, 0);
+            }
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                const bf16x8 bl = lp[cb * 64];
+                accp[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aph, bl, accp[cb], 0, 0, 0);
+                accq[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aqh, bl, accq[cb], 0, 0, 0);
+            }
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                const bf16x8 bh = hp[cb * 64];
+                accp[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(apl, bh, accp[cb], 0, 0, 0);
+                accq[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aql, bh, accq[cb], 0, 0, 0);
+            }
+        }
+    }
+    float *Yb = Yout + (int64_t)blockIdx.z * npad * 2 * Pp;
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t row = ibase + 4 * g + r;
+            Yb[(row * 2 + 0) * Pp + col0 + cb * 16 + m] = accp[cb][r];
+            Yb[(row * 2 + 1) * Pp + col0 + cb * 16 + m] = accq[cb][r];
+        }
+}
+
+template <int NCB>
+hipError_t run(vv10_plan *p) {
     const Workspace &ws = p->ws;
-    const int64_t jlen = ((p->npad / ws.jsplit + kJC - 1) / kJC) * kJC;
     dim3 grid((unsigned)(p->npad / 64), (unsigned)ws.ngroups, (unsigned)ws.jsplit);
-    k_contract_f64<NCB><<<grid, 256, 0, p->stream>>>(p->npad, jlen, ws.Pp, p->P0, p->P1, ws.X, ws.Y);
+    if (p->prec == VV10_FP64) {
+        if constexpr (NCB <= 8)
+            k_contract_f64<NCB><<<grid, 256, 0, p->stream>>>(
+                p->npad, ws.jlen, ws.Pp, p->P0, p->P1, static_cast<const double *>(ws.X),
+                static_cast<double *>(ws.Ypart));
+        else
+            return hipErrorInvalidValue;
+    } else if (p->prec == VV10_MIXED_FP32) {
+        k_contract_f32<NCB><<<grid, 256, 0, p->stream>>>(
+            p->npad, ws.jlen, ws.Pp, p->P0f, p->P1f, static_cast<const float *>(ws.X),
+            static_cast<float *>(ws.Ypart));
+    } else {
+        const bf16x8 *xh = static_cast<const bf16x8 *>(ws.X);
+        const bf16x8 *xl = xh + (size_t)p->npad * ws.Pp * 2 / 8;
+        k_contract_bf16x3<NCB><<<grid, 256, 0, p->stream>>>(
+            p->npad, ws.jlen, ws.Pp, p->P0f, p->P1f, xh, xl, static_cast<float *>(ws.Ypart));
+    }
     return hipGetLastError();
+}
+
+template <int NCB>
+int occupancy(vv10_precision prec) {
+    int nb = 0;
+    hipError_t e;
+    if (prec == VV10_FP64) {
+        if constexpr (NCB <= 8)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_contract_f64<NCB>, 256, 0);
+        else
+            return 0;
+    } else if (prec == VV10_MIXED_FP32) {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_contract_f32<NCB>, 256, 0);
+    } else {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_contract_bf16x3<NCB>, 256, 0);
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return nb;
+}
+
+template <typename F>
+auto dispatch_ncb(int ncb, F &&f) -> decltype(f(std::integral_constant<int, 1>{})) {
+    switch (ncb) {
+        case 1: return f(std::integral_constant<int, 1>{});
+        case 2: return f(std::integral_constant<int, 2>{});
+        case 3: return f(std::integral_constant<int, 3>{});
+        case 4: return f(std::integral_constant<int, 4>{});
+        case 5: return f(std::integral_constant<int, 5>{});
+        case 6: return f(std::integral_constant<int, 6>{});
+        case 7: return f(std::integral_constant<int, 7>{});
+        case 8: return f(std::integral_constant<int, 8>{});
+        case 9: return f(std::integral_constant<int, 9>{});
+        case 10: return f(std::integral_constant<int, 10>{});
+        case 11: return f(std::integral_constant<int, 11>{});
+        case 12: return f(std::integral_constant<int, 12>{});
+        default: return decltype(f(std::integral_constant<int, 1>{})){};
+    }
 }
 
 }  // namespace
 
+int contract_blocks_per_cu(vv10_precision prec, int ncb) {
+    return dispatch_ncb(ncb, [&](auto c) { return occupancy<decltype(c)::value>(prec); });
+}
+
 hipError_t launch_contract(vv10_plan *p) {
-    const Workspace &ws = p->ws;
-    hipError_t e = hipErrorInvalidValue;
-    if (p->prec == VV10_FP64) {
-        switch (ws.ncb) {
-            case 1: e = run_f64<1>(p); break;
-            case 2: e = run_f64<2>(p); break;
-            case 3: e = run_f64<3>(p); break;
-            case 4: e = run_f64<4>(p); break;
-            case 5: e = run_f64<5>(p); break;
-            case 6: e = run_f64<6>(p); break;
-            case 7: e = run_f64<7>(p); break;
-            case 8: e = run_f64<8>(p); break;
-            default: return hipErrorInvalidValue;
-        }
-    } else {
-        return hipErrorInvalidValue;   // mixed contraction: see contract_mixed.hip
-    }
-    return e;
+    if (p->ws.ncb < 1 || p->ws.ncb > max_ncb(p->prec)) return hipErrorInvalidValue;
+    return dispatch_ncb(p->ws.ncb, [&](auto c) { return run<decltype(c)::value>(p); });
 }
 
 }  // namespace vv10

@@ -20,6 +20,9 @@
 //
 // One wave per (tile of 64 outer points, group of atoms B); tiles never
 // straddle atoms, so the D sums are plain wave reductions in a fixed order.
+// FP64 mode evaluates and accumulates in FP64; the mixed modes evaluate each
+// pair in FP32, accumulate one 64-point chunk in FP32 and add the chunk sums
+// into FP64 accumulators.
 #include "dev_common.h"
 #include "vv10_internal.h"
 
@@ -29,24 +32,26 @@ namespace {
 
 constexpr int TG = kGridTile;
 
-__global__ __launch_bounds__(64) void k_grid_f64(
+template <typename T, typename T4>
+__global__ __launch_bounds__(64) void k_grid(
     int32_t n_atom, int32_t Pp, int32_t bgroups, const int64_t *__restrict__ seg,
     const int32_t *__restrict__ tile_i0, const int32_t *__restrict__ tile_n,
-    const int32_t *__restrict__ tile_atom, const double4 *__restrict__ P0,
-    const double4 *__restrict__ P1, double *__restrict__ Z, double *__restrict__ Dpart) {
-    __shared__ double4 sA[TG], sB[TG];
+    const int32_t *__restrict__ tile_atom, const T4 *__restrict__ P0,
+    const T4 *__restrict__ P1, double *__restrict__ Z, double *__restrict__ Dpart) {
+    __shared__ T4 sA[TG], sB[TG];
     const int t = blockIdx.x, grp = blockIdx.y, lane = threadIdx.x;
     const int A = tile_atom[t];
     const int nt = tile_n[t];
     const bool live = lane < nt;
     const int64_t i = (int64_t)tile_i0[t] + (live ? lane : 0);
-    const double4 a0 = P0[i], a1 = P1[i];
-    const double ai = live ? a1.y : 0.0, ci = a1.z, oi = a0.w;
+    const T4 a0 = P0[i], a1 = P1[i];
+    const double ai = live ? (double)a1.y : 0.0, ci = (double)a1.z;
+    const T oi = a0.w;
     for (int B = grp; B < n_atom; B += bgroups) {
         if (B == A) continue;
         const int64_t jb = seg[B], je = seg[B + 1];
-        double ex = 0, ey = 0, ez = 0, ux = 0, uy = 0, uz = 0, vx = 0, vy = 0, vz = 0;
-        double dxx = 0, dyy = 0, dzz = 0, dxy = 0, dxz = 0, dyz = 0;
+        // [0..2] e d, [3..5] u d, [6..8] v d, [9..14] D (xx, yy, zz, xy, xz, yz)
+        double acc[15] = {};
         for (int64_t j0 = jb; j0 < je; j0 += TG) {
             __syncthreads();
             const int64_t j = j0 + lane;
@@ -54,50 +59,55 @@ __global__ __launch_bounds__(64) void k_grid_f64(
             sB[lane] = P1[j < je ? j : jb];
             __syncthreads();
             const int cnt = (int)min((int64_t)TG, je - j0);
+            T c[15] = {};
             for (int jj = 0; jj < cnt; ++jj) {
-                const double4 b0 = sA[jj], b1 = sB[jj];
-                const double dx = b0.x - a0.x, dy = b0.y - a0.y, dz = b0.z - a0.z;
-                const double R2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
-                const double g = __builtin_fma(oi, R2, a1.x);
-                const double gp = __builtin_fma(b0.w, R2, b1.x);
-                const double s = g + gp, tt = g * gp;
-                const double r = rcp64(tt * s);
-                const double pa = -1.5 * b1.y * r;       // a_j Phi_ij
-                const double ig = gp * s * r, igp = g * s * r, is = tt * r;
-                const double Ti = oi * ig, Tj = b0.w * igp, Ts = (oi + b0.w) * is;
-                const double T = Ti + Tj + Ts;
-                const double h = ig + is;
-                const double TQ = __builtin_fma(T, h, __builtin_fma(Ti, ig, Ts * is));
-                const double e = -2.0 * pa * T;
-                const double u = 2.0 * pa * TQ;
-                const double v = 2.0 * pa * __builtin_fma(R2, TQ, -h);
-                const double S = __builtin_fma(T, T, __builtin_fma(Ti, Ti, __builtin_fma(Tj, Tj, Ts * Ts)));
-                const double dd = -4.0 * pa * S;       // coefficient of d d^T
-                const double di = -e;                  // coefficient of I (= 2 a_j Phi T)
-                ex = __builtin_fma(e, dx, ex); ey = __builtin_fma(e, dy, ey); ez = __builtin_fma(e, dz, ez);
-                ux = __builtin_fma(u, dx, ux); uy = __builtin_fma(u, dy, uy); uz = __builtin_fma(u, dz, uz);
-                vx = __builtin_fma(v, dx, vx); vy = __builtin_fma(v, dy, vy); vz = __builtin_fma(v, dz, vz);
-                const double ddx = dd * dx, ddy = dd * dy;
-                dxx += __builtin_fma(ddx, dx, di);
-                dyy += __builtin_fma(ddy, dy, di);
-                dzz += __builtin_fma(dd * dz, dz, di);
-                dxy = __builtin_fma(ddx, dy, dxy);
-                dxz = __builtin_fma(ddx, dz, dxz);
-                dyz = __builtin_fma(ddy, dz, dyz);
+                const T4 b0 = sA[jj], b1 = sB[jj];
+                const T dx = b0.x - a0.x, dy = b0.y - a0.y, dz = b0.z - a0.z;
+                const T R2 = dx * dx + dy * dy + dz * dz;
+                const T g = oi * R2 + a1.x;
+                const T gp = b0.w * R2 + b1.x;
+                const T s = g + gp, tt = g * gp;
+                T r;
+                if constexpr (sizeof(T) == 8) r = rcp64(tt * s); else r = rcp32(tt * s);
+                const T pa = T(-1.5) * b1.y * r;         // a_j Phi_ij
+                const T sr = s * r;
+                const T ig = gp * sr, igp = g * sr, is = tt * r;
+                const T Ti = oi * ig, Tj = b0.w * igp, Ts = (oi + b0.w) * is;
+                const T T_ = Ti + Tj + Ts;
+                const T h = ig + is;
+                const T TQ = T_ * h + Ti * ig + Ts * is;
+                const T e = T(-2) * pa * T_;
+                const T u = T(2) * pa * TQ;
+                const T v = T(2) * pa * (R2 * TQ - h);
+                const T S = T_ * T_ + Ti * Ti + Tj * Tj + Ts * Ts;
+                const T dd = T(-4) * pa * S;            // coefficient of d d^T
+                const T di = -e;                        // coefficient of I (= 2 a_j Phi T)
+                c[0] += e * dx; c[1] += e * dy; c[2] += e * dz;
+                c[3] += u * dx; c[4] += u * dy; c[5] += u * dz;
+                c[6] += v * dx; c[7] += v * dy; c[8] += v * dz;
+                const T ddx = dd * dx, ddy = dd * dy;
+                c[9] += ddx * dx + di;
+                c[10] += ddy * dy + di;
+                c[11] += dd * dz * dz + di;
+                c[12] += ddx * dy;
+                c[13] += ddx * dz;
+                c[14] += ddy * dz;
             }
+#pragma unroll
+            for (int k = 0; k < 15; ++k) acc[k] += (double)c[k];
         }
         if (live) {
             double *z0 = Z + (i * 2 + 0) * Pp + 3 * B;
             double *z1 = Z + (i * 2 + 1) * Pp + 3 * B;
-            z0[0] = __builtin_fma(ci, ux, ex);
-            z0[1] = __builtin_fma(ci, uy, ey);
-            z0[2] = __builtin_fma(ci, uz, ez);
-            z1[0] = vx;
-            z1[1] = vy;
-            z1[2] = vz;
+            z0[0] = acc[0] + ci * acc[3];
+            z0[1] = acc[1] + ci * acc[4];
+            z0[2] = acc[2] + ci * acc[5];
+            z1[0] = acc[6];
+            z1[1] = acc[7];
+            z1[2] = acc[8];
         }
-        const double red[9] = {ai * dxx, ai * dyy, ai * dzz, ai * dxy, ai * dxz, ai * dyz,
-                               ai * ex, ai * ey, ai * ez};
+        const double red[9] = {ai * acc[9], ai * acc[10], ai * acc[11], ai * acc[12], ai * acc[13],
+                               ai * acc[14], ai * acc[0], ai * acc[1], ai * acc[2]};
         double *dp = Dpart + ((int64_t)t * n_atom + B) * 9;
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
@@ -111,11 +121,15 @@ __global__ __launch_bounds__(64) void k_grid_f64(
 
 hipError_t launch_grid_terms(vv10_plan *p) {
     const Workspace &ws = p->ws;
-    if (p->prec != VV10_FP64) return hipErrorInvalidValue;
     dim3 grid((unsigned)p->ntiles, (unsigned)ws.bgroups);
-    k_grid_f64<<<grid, TG, 0, p->stream>>>(p->n_atom, ws.Pp, ws.bgroups, p->d_seg, p->d_tile_i0,
-                                          p->d_tile_n, p->d_tile_atom, p->P0, p->P1, ws.Z,
-                                          ws.Dpart);
+    if (p->prec == VV10_FP64)
+        k_grid<double, double4><<<grid, TG, 0, p->stream>>>(p->n_atom, ws.Pp, ws.bgroups, p->d_seg,
+                                                           p->d_tile_i0, p->d_tile_n, p->d_tile_atom,
+                                                           p->P0, p->P1, ws.Z, ws.Dpart);
+    else
+        k_grid<float, float4><<<grid, TG, 0, p->stream>>>(p->n_atom, ws.Pp, ws.bgroups, p->d_seg,
+                                                         p->d_tile_i0, p->d_tile_n, p->d_tile_atom,
+                                                         p->P0f, p->P1f, ws.Z, ws.Dpart);
     return hipGetLastError();
 }
 

@@ -130,16 +130,19 @@ __global__ __launch_bounds__(256) void k_prep(
 
 // Perturbation packing: for every point i and perturbation x,
 //   gamma^x = 2 grad rho . grad rho^x,
-//   X[i][0][x] = w rho^x                       (p channel)
-//   X[i][1][x] = w rho (omega_r rho^x + omega_g gamma^x)   (q channel)
-//   L[i][0][x] = rho^x, L[i][1][x] = gamma^x.
-// A 32 x 32 (point x perturbation) tile is staged through LDS so that both
-// the [P][N] reads and the [N][2][Pp] writes are coalesced.
+//   p = w rho^x,  q = w rho (omega_r rho^x + omega_g gamma^x)   (the two channels)
+//   L[i][0][x] = rho^x, L[i][1][x] = gamma^x  (FP64, for the assembly).
+// The channels are stored as the contraction of the plan's mode reads them:
+//   FP64 / FP32: X[i][c][x];
+//   BF16X3: hi = bf16(v), lo = bf16(v - hi), each as [i/16][x][2 (i mod 16) + c].
+// A 32 x 32 (point x perturbation) tile is staged through LDS so that the
+// [P][N] reads are coalesced.
 constexpr int TT = 32;
+template <int MODE>
 __global__ __launch_bounds__(256) void k_pert_prep(
     int64_t n, int64_t npad, int32_t P, int32_t Pp, const double *__restrict__ rho_x,
     const double *__restrict__ grad_rho_x, const double *__restrict__ F,
-    double *__restrict__ X, double *__restrict__ L) {
+    void *__restrict__ Xv, double *__restrict__ L) {
     __shared__ double sr[TT][TT + 1];
     __shared__ double sg[TT][TT + 1];
     const int64_t i0 = (int64_t)blockIdx.x * TT;
@@ -169,8 +172,24 @@ __global__ __launch_bounds__(256) void k_pert_prep(
         const double wi = F[F_W * npad + i], r = F[F_RHO * npad + i];
         const double p = wi * rx;
         const double qv = wi * r * (F[F_OMR * npad + i] * rx + F[F_OMG * npad + i] * gxv);
-        X[(i * 2 + 0) * Pp + x] = p;
-        X[(i * 2 + 1) * Pp + x] = qv;
+        if (MODE == VV10_FP64) {
+            double *X = static_cast<double *>(Xv);
+            X[(i * 2 + 0) * Pp + x] = p;
+            X[(i * 2 + 1) * Pp + x] = qv;
+        } else if (MODE == VV10_MIXED_FP32) {
+            float *X = static_cast<float *>(Xv);
+            X[(i * 2 + 0) * Pp + x] = (float)p;
+            X[(i * 2 + 1) * Pp + x] = (float)qv;
+        } else {
+            __bf16 *Xh = static_cast<__bf16 *>(Xv);
+            __bf16 *Xl = Xh + npad * 2 * Pp;
+            const int64_t o = ((i / 16) * Pp + x) * 32 + 2 * (i % 16);
+            const __bf16 ph = (__bf16)(float)p, qh = (__bf16)(float)qv;
+            Xh[o] = ph;
+            Xh[o + 1] = qh;
+            Xl[o] = (__bf16)(float)(p - (double)(float)ph);
+            Xl[o + 1] = (__bf16)(float)(qv - (double)(float)qh);
+        }
         L[(i * 2 + 0) * Pp + x] = rx;
         L[(i * 2 + 1) * Pp + x] = gxv;
     }
@@ -195,8 +214,15 @@ hipError_t launch_prepare(vv10_plan *p, const double *coords, const double *w,
 hipError_t launch_pert_prep(vv10_plan *p, const double *rho_x, const double *grad_rho_x) {
     const Workspace &ws = p->ws;
     dim3 grid((unsigned)((p->npad + TT - 1) / TT), (unsigned)((ws.Pp + TT - 1) / TT));
-    k_pert_prep<<<grid, 256, 0, p->stream>>>(p->n, p->npad, ws.P, ws.Pp, rho_x, grad_rho_x,
-                                             p->F, ws.X, ws.L);
+    if (p->prec == VV10_FP64)
+        k_pert_prep<VV10_FP64><<<grid, 256, 0, p->stream>>>(p->n, p->npad, ws.P, ws.Pp, rho_x,
+                                                            grad_rho_x, p->F, ws.X, ws.L);
+    else if (p->prec == VV10_MIXED_FP32)
+        k_pert_prep<VV10_MIXED_FP32><<<grid, 256, 0, p->stream>>>(p->n, p->npad, ws.P, ws.Pp, rho_x,
+                                                                  grad_rho_x, p->F, ws.X, ws.L);
+    else
+        k_pert_prep<VV10_MIXED_BF16X3><<<grid, 256, 0, p->stream>>>(p->n, p->npad, ws.P, ws.Pp, rho_x,
+                                                                    grad_rho_x, p->F, ws.X, ws.L);
     return hipGetLastError();
 }
 

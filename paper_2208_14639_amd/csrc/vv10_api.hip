@@ -14,38 +14,48 @@ namespace vv10 {
 
 void plan_workspace_shape(int64_t npad, int32_t n_atom, int32_t ntiles, int num_cu,
                           vv10_precision prec, Workspace &ws) {
-    (void)prec;
     ws.P = 3 * n_atom;
     const int ncb_total = (ws.P + 15) / 16;
-    ws.ngroups = (ncb_total + 7) / 8;
+    const int cap = max_ncb(prec);
+    ws.ngroups = (ncb_total + cap - 1) / cap;
     ws.ncb = (ncb_total + ws.ngroups - 1) / ws.ngroups;
     ws.Pp = 16 * ws.ncb * ws.ngroups;
 
-    // j splits of the contraction: keep the last round of workgroups full
-    // (two resident 256-thread workgroups per CU).
+    // j splits of the contraction: fill the last round of resident
+    // workgroups; the mixed modes accumulate one split in FP32, so they
+    // also cap a split at 16384 points.
+    int per_cu = contract_blocks_per_cu(prec, ws.ncb);
+    if (per_cu <= 0) per_cu = 2;
     const int64_t units = (npad / 64) * ws.ngroups;
-    const int64_t slots = 2LL * num_cu;
+    const int64_t slots = (int64_t)per_cu * num_cu;
+    const int min_split = prec == VV10_FP64 ? 1 : (int)((npad + 16383) / 16384);
     double best = -1.0;
-    ws.jsplit = 1;
-    for (int S = 1; S <= 8; ++S) {
-        if (npad / S < 256) break;
+    ws.jsplit = min_split;
+    for (int S = min_split; S <= min_split + 15; ++S) {
+        if (S > 1 && npad / S < 256) break;
         const int64_t u = units * S;
         const double eff = (double)u / (double)(((u + slots - 1) / slots) * slots);
-        const double score = eff - 0.01 * (S - 1);
+        const double score = eff - 0.01 * (S - min_split);
         if (score > best + 1e-12) {
             best = score;
             ws.jsplit = S;
         }
     }
+    ws.jlen = ((npad / ws.jsplit + 31) / 32) * 32;
+    while ((ws.jsplit - 1) * ws.jlen >= npad) --ws.jsplit;   // no empty split
     const int tiles = (ws.Pp + 63) / 64;
     ws.gsplit = (int)std::max<int64_t>(1, std::min<int64_t>((1024 + tiles * tiles - 1) / (tiles * tiles),
                                                              std::max<int64_t>(1, npad / 64)));
     ws.bgroups = std::max(1, std::min<int>(n_atom, (8192 + std::max(ntiles, 1) - 1) / std::max(ntiles, 1)));
 }
 
-size_t workspace_bytes(int64_t npad, int32_t n_atom, int32_t ntiles, const Workspace &ws) {
-    const size_t ch = (size_t)npad * 2 * ws.Pp * sizeof(double);
-    size_t b = 3 * ch + (size_t)ws.jsplit * ch;
+size_t workspace_bytes(int64_t npad, int32_t n_atom, int32_t ntiles, vv10_precision prec,
+                       const Workspace &ws) {
+    const size_t ch = (size_t)npad * 2 * ws.Pp;
+    size_t b = 3 * ch * sizeof(double);                       // L, Y, Z
+    b += ch * (prec == VV10_FP64 ? 8 : 4);                    // X (FP64, FP32, or BF16 hi + lo)
+    const bool alias = prec == VV10_FP64 && ws.jsplit == 1;   // partials written straight into Y
+    if (!alias) b += (size_t)ws.jsplit * ch * partial_elem(prec);
     b += (size_t)ntiles * n_atom * 9 * sizeof(double);
     b += (size_t)ws.gsplit * ws.Pp * ws.Pp * sizeof(double);
     b += (size_t)ws.P * ws.P * sizeof(double);
@@ -86,6 +96,7 @@ void dfree(void *ptr) {
 void free_workspace(Workspace &ws) {
     dfree(ws.X);
     dfree(ws.L);
+    if (ws.Ypart != ws.Y) dfree(ws.Ypart);
     dfree(ws.Y);
     dfree(ws.Z);
     dfree(ws.Dpart);
@@ -141,9 +152,19 @@ vv10_status ensure_workspace(vv10_plan *p) {
     if (injected_alloc_failure()) return VV10_E_OOM;
     const size_t ch = (size_t)p->npad * 2 * ws.Pp;
     hipError_t e = hipSuccess;
-    if (e == hipSuccess) e = dalloc(&ws.X, ch);
+    char *xb = nullptr, *yp = nullptr;
+    if (e == hipSuccess) e = dalloc(&xb, ch * (p->prec == VV10_FP64 ? 8 : 4));
+    ws.X = xb;
     if (e == hipSuccess) e = dalloc(&ws.L, ch);
-    if (e == hipSuccess) e = dalloc(&ws.Y, ch * ws.jsplit);
+    if (e == hipSuccess) e = dalloc(&ws.Y, ch);
+    if (e == hipSuccess) {
+        if (p->prec == VV10_FP64 && ws.jsplit == 1) {
+            ws.Ypart = ws.Y;
+        } else {
+            e = dalloc(&yp, ch * ws.jsplit * vv10::partial_elem(p->prec));
+            ws.Ypart = yp;
+        }
+    }
     if (e == hipSuccess) e = dalloc(&ws.Z, ch);
     if (e == hipSuccess) e = dalloc(&ws.Dpart, (size_t)p->ntiles * p->n_atom * 9);
     if (e == hipSuccess) e = dalloc(&ws.Hpart, (size_t)ws.gsplit * ws.Pp * ws.Pp);
@@ -154,7 +175,7 @@ vv10_status ensure_workspace(vv10_plan *p) {
         (void)hipGetLastError();
         return hip_status(e);
     }
-    ws.bytes = vv10::workspace_bytes(p->npad, p->n_atom, p->ntiles, ws);
+    ws.bytes = vv10::workspace_bytes(p->npad, p->n_atom, p->ntiles, p->prec, ws);
     p->ws = ws;
     return VV10_OK;
 }
@@ -195,8 +216,9 @@ size_t vv10_footprint_bytes(int64_t n_grid, int32_t n_atom, vv10_precision prec)
     const int64_t ntiles = (n_grid + vv10::kGridTile - 1) / vv10::kGridTile + n_atom;
     Workspace ws;
     vv10::plan_workspace_shape(npad, n_atom, (int32_t)ntiles, 256, prec, ws);
-    ws.jsplit = 8;   // upper bound over devices
-    return base_bytes(npad, n_atom, ntiles) + vv10::workspace_bytes(npad, n_atom, (int32_t)ntiles, ws);
+    ws.jsplit = std::max(ws.jsplit, 16);   // upper bound over devices and occupancies
+    return base_bytes(npad, n_atom, ntiles) +
+           vv10::workspace_bytes(npad, n_atom, (int32_t)ntiles, prec, ws);
 }
 
 vv10_status vv10_prepare(const vv10_params *params, int64_t n_grid, int32_t n_atom,
@@ -211,8 +233,6 @@ vv10_status vv10_prepare(const vv10_params *params, int64_t n_grid, int32_t n_at
         !std::isfinite(params->C))
         return VV10_E_ARG;
     if (prec != VV10_FP64 && prec != VV10_MIXED_FP32 && prec != VV10_MIXED_BF16X3) return VV10_E_ARG;
-    // The mixed contraction kernels are not part of this build yet.
-    if (prec != VV10_FP64) return VV10_E_ARG;
 
     vv10_plan *p = new (std::nothrow) vv10_plan();
     if (!p) return VV10_E_OOM;

@@ -38,11 +38,14 @@ struct Workspace {
     int32_t P = 0, Pp = 0;       // perturbations and padded column count
     int32_t ncb = 0, ngroups = 0;  // 16-column blocks per contraction group, groups
     int32_t jsplit = 1;          // j splits of the contraction
+    int64_t jlen = 0;            // j points per split (multiple of 32)
     int32_t gsplit = 1;          // splits of the assembly GEMM
     int32_t bgroups = 1;         // atom groups of the grid-term kernel
-    double *X = nullptr;         // [npad][2][Pp] (p, q) channels
+    void *X = nullptr;           // (p, q) channels: FP64 or FP32 [npad][2][Pp];
+                                 // BF16X3: hi then lo, each [npad/16][Pp][32] bf16
     double *L = nullptr;         // [npad][2][Pp] (rho^x, gamma^x)
-    double *Y = nullptr;         // [jsplit][npad][2][Pp] contraction, then R in place
+    void *Ypart = nullptr;       // [jsplit][npad][2][Pp] contraction partials (FP64 or FP32)
+    double *Y = nullptr;         // [npad][2][Pp] summed contraction, then R in place
     double *Z = nullptr;         // [npad][2][Pp] grid-position channels
     double *Dpart = nullptr;     // [ntiles][n_atom][9] tile sums of a_i D^B_i (6) and a_i E^{Bgr}_i (3)
     double *Hpart = nullptr;     // [gsplit][Pp][Pp]
@@ -107,6 +110,13 @@ hipError_t launch_assemble(vv10_plan *p, double *hess, double *grad, double *res
 // Layout decisions shared by the host code.
 void plan_workspace_shape(int64_t npad, int32_t n_atom, int32_t ntiles, int num_cu,
                           vv10_precision prec, Workspace &ws);
-size_t workspace_bytes(int64_t npad, int32_t n_atom, int32_t ntiles, const Workspace &ws);
+size_t workspace_bytes(int64_t npad, int32_t n_atom, int32_t ntiles, vv10_precision prec,
+                       const Workspace &ws);
+// Resident workgroups per CU of the contraction kernel for this shape (0 if unknown).
+int contract_blocks_per_cu(vv10_precision prec, int ncb);
+// Max 16-column blocks per contraction workgroup.
+inline int max_ncb(vv10_precision prec) { return prec == VV10_FP64 ? 8 : 12; }
+// Bytes of one element of the contraction partials / operand.
+inline size_t partial_elem(vv10_precision prec) { return prec == VV10_FP64 ? 8 : 4; }
 
 }  // namespace vv10

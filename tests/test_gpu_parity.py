@@ -92,3 +92,59 @@ def test_translational_invariance_fp64(torch):
         assert np.max(np.abs(s)) < 1e-10 * np.max(np.abs(H))
         g = out["grad"].cpu().numpy().reshape(-1, 3).sum(axis=0)
         assert np.max(np.abs(g)) < 1e-10 * np.max(np.abs(out["grad"].cpu().numpy()))
+
+
+# ---------------------------------------------------------------------------
+# Mixed precision: FP32 pair arithmetic, FP32 or split-BF16 MFMA contraction,
+# FP64 accumulation across tiles.  Bounds: energy <= 1e-6 relative, every
+# Hessian element <= 1e-5 au absolute; potential and gradient <= 1e-5
+# normwise; response rows <= 1e-5 (FP32) and 5e-5 (split-BF16, whose
+# operands carry about 2^-16 relative error each and whose small rows do not
+# average it out) normwise.
+# ---------------------------------------------------------------------------
+MIXED = ["fp32", "bf16x3"]
+E_REL, H_ABS, V_NORM = 1e-6, 1e-5, 1e-5
+RESP_NORM = {"fp32": 1e-5, "bf16x3": 5e-5}
+
+
+@pytest.mark.parametrize("prec", MIXED)
+@pytest.mark.parametrize("case", CASES)
+def test_mixed_precision_bounds(torch, case, prec):
+    _say("mixed", prec, case)
+    p = problem(*case)
+    with _plan(torch, case, prec) as pl:
+        e, fr, fg = pl.energy_potential()
+        out = pl.hessian_terms(p.rho_x, p.grad_rho_x, grad=True, resp=True)
+        torch.cuda.synchronize()
+    e0, fr0, fg0 = oracle_energy(*case)
+    H0, G0, (Yr0, Yg0) = oracle_hessian(*case)
+    H = out["hess"].cpu().numpy()
+    errs = dict(
+        energy_rel=relerr(e.item(), e0),
+        f_rho=normwise(fr.cpu().numpy(), fr0),
+        f_gamma=normwise(fg.cpu().numpy(), fg0),
+        grad=normwise(out["grad"].cpu().numpy(), G0),
+        resp_rho=normwise(out["resp_rho"].cpu().numpy(), Yr0),
+        resp_gamma=normwise(out["resp_gamma"].cpu().numpy(), Yg0),
+        hess_max_abs=float(np.max(np.abs(H - H0))),
+        hess_normwise=normwise(H, H0),
+    )
+    _say("  errors", errs)
+    assert errs["energy_rel"] <= E_REL
+    assert errs["hess_max_abs"] <= H_ABS
+    for k in ("f_rho", "f_gamma", "grad"):
+        assert errs[k] <= V_NORM, (k, errs[k])
+    for k in ("resp_rho", "resp_gamma"):
+        assert errs[k] <= RESP_NORM[prec], (k, errs[k])
+    assert np.array_equal(H, H.T)
+
+
+@pytest.mark.parametrize("prec", MIXED)
+def test_mixed_deterministic(torch, prec):
+    case = CASES[2]
+    p = problem(*case)
+    with _plan(torch, case, prec) as pl:
+        a = pl.hessian_terms(p.rho_x, p.grad_rho_x, grad=True)
+        b = pl.hessian_terms(p.rho_x, p.grad_rho_x, grad=True)
+        torch.cuda.synchronize()
+        assert torch.equal(a["hess"], b["hess"]) and torch.equal(a["grad"], b["grad"])
