@@ -135,11 +135,12 @@ vv10_status vv10_hessian_terms(vv10_plan *plan, int32_t n_pert, const double *rh
 
 /* Stages of the library's launch sequence, for vv10_stage_times. */
 typedef enum {
-    VV10_STAGE_PAIR = 0,      /* pair integrals E, U, W (and A, B, C in a Hessian call) */
+    VV10_STAGE_PAIR = 0,      /* pair integrals E, U, W of vv10_energy_potential */
     VV10_STAGE_POTENTIAL = 1, /* f^rho, f^gamma and the energy reduction */
     VV10_STAGE_PERT_PREP = 2, /* packing of the perturbation channels */
     VV10_STAGE_CONTRACT = 3,  /* perturbation-batched contraction (MFMA) */
-    VV10_STAGE_GRID = 4,      /* grid-position intermediates */
+    VV10_STAGE_GRID = 4,      /* grid-position intermediates fused with the pair
+                                 integrals E, U, W, A, B, C of vv10_hessian_terms */
     VV10_STAGE_ASSEMBLE = 5,  /* Hessian assembly (and gradient) */
     VV10_NUM_STAGES = 6
 } vv10_stage;

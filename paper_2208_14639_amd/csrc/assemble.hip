@@ -18,8 +18,8 @@
 //      R = w (Yr + 2 Zr, Yg + 2 Zg)   written over Y.
 // 2. k_gemm: Hpart[s] = sum over a slice of points of L_i^T R_i, L = (rho^x, gamma^x),
 //    so that sum_s Hpart[s] = E_GG + 2 E_{G,gr} (E_GG without the rho^{AB} term).
-// 3. k_grgr: E_{gr,gr} from the tile sums of a_i D^B_i; diagonal blocks by
-//    translational invariance.
+// 3. k_dsum, k_grgr: E_{gr,gr} from the tile sums of a_i D^B_i, reduced per
+//    atom pair; diagonal blocks by translational invariance.
 // 4. k_hess_final: H = sym(sum_s Hpart[s]) + sym(E_{gr,gr}), sym(M) = (M + M^T)/2.
 // 5. gradient: E_G = sum_i w_i (f^rho_i rho^x_i + f^gamma_i gamma^x_i) and
 //    E_gr = sum_{i in A} a_i E^{Agr}_i = -sum_{B != A} sum_{i in A} a_i E^{Bgr}_i.
@@ -147,17 +147,28 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t n, int64_t slice, int32_t 
         }
 }
 
-// E_{gr,gr}[(A,a)][(B,b)] = sum_{tiles t of A} Dpart[t][B][(a,b)], B != A,
-// and the diagonal blocks -sum_{B != A}.
+// DS[A][B][c] = sum over the tiles t of atom A of Dpart[t][B][c] (tile order).
+__global__ __launch_bounds__(256) void k_dsum(int32_t n_atom, const int32_t *__restrict__ tile_first,
+                                              const double *__restrict__ Dpart,
+                                              double *__restrict__ DS) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= (int64_t)n_atom * n_atom * 9) return;
+    const int A = (int)(k / (9LL * n_atom));
+    const int rem = (int)(k - (int64_t)A * 9 * n_atom);   // B * 9 + c
+    double v = 0.0;
+    for (int t = tile_first[A]; t < tile_first[A + 1]; ++t) v += Dpart[(int64_t)t * n_atom * 9 + rem];
+    DS[k] = v;
+}
+
+// E_{gr,gr}[(A,a)][(B,b)] = DS[A][B][(a,b)] for B != A, and the diagonal
+// blocks -sum_{B != A} DS[A][B][(a,b)] (translational invariance).
 __device__ __forceinline__ int sym_index(int a, int b) {
     if (a == b) return a;                 // xx, yy, zz
     const int lo = a < b ? a : b, hi = a < b ? b : a;
     return lo == 0 ? (hi == 1 ? 3 : 4) : 5;   // xy, xz, yz
 }
 
-__global__ __launch_bounds__(256) void k_grgr(int32_t n_atom, int32_t P,
-                                              const int32_t *__restrict__ tile_first,
-                                              const double *__restrict__ Dpart,
+__global__ __launch_bounds__(256) void k_grgr(int32_t n_atom, int32_t P, const double *__restrict__ DS,
                                               double *__restrict__ Hgr) {
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (k >= (int64_t)P * P) return;
@@ -166,16 +177,10 @@ __global__ __launch_bounds__(256) void k_grgr(int32_t n_atom, int32_t P,
     const int c = sym_index(a, b);
     double v = 0.0;
     if (A != B) {
-        for (int t = tile_first[A]; t < tile_first[A + 1]; ++t)
-            v += Dpart[((int64_t)t * n_atom + B) * 9 + c];
+        v = DS[((int64_t)A * n_atom + B) * 9 + c];
     } else {
-        for (int C = 0; C < n_atom; ++C) {
-            if (C == A) continue;
-            double s = 0.0;
-            for (int t = tile_first[A]; t < tile_first[A + 1]; ++t)
-                s += Dpart[((int64_t)t * n_atom + C) * 9 + c];
-            v -= s;
-        }
+        for (int C = 0; C < n_atom; ++C)
+            if (C != A) v -= DS[((int64_t)A * n_atom + C) * 9 + c];
     }
     Hgr[k] = v;
 }
@@ -213,10 +218,8 @@ __global__ __launch_bounds__(256) void k_grad_part(int64_t n, int64_t npad, int6
 }
 
 __global__ __launch_bounds__(256) void k_grad_final(int32_t n_atom, int32_t P, int32_t Pp,
-                                                    int32_t nslices,
-                                                    const int32_t *__restrict__ tile_first,
-                                                    const double *__restrict__ gpart,
-                                                    const double *__restrict__ Dpart,
+                                                    int32_t nslices, const double *__restrict__ gpart,
+                                                    const double *__restrict__ DS,
                                                     double *__restrict__ grad) {
     const int x = blockIdx.x * 256 + threadIdx.x;
     if (x >= P) return;
@@ -224,13 +227,8 @@ __global__ __launch_bounds__(256) void k_grad_final(int32_t n_atom, int32_t P, i
     for (int s = 0; s < nslices; ++s) g += gpart[(int64_t)s * Pp + x];
     const int A = x / 3, a = x % 3;
     double gr = 0.0;
-    for (int B = 0; B < n_atom; ++B) {
-        if (B == A) continue;
-        double s = 0.0;
-        for (int t = tile_first[A]; t < tile_first[A + 1]; ++t)
-            s += Dpart[((int64_t)t * n_atom + B) * 9 + 6 + a];
-        gr -= s;
-    }
+    for (int B = 0; B < n_atom; ++B)
+        if (B != A) gr -= DS[((int64_t)A * n_atom + B) * 9 + 6 + a];
     grad[x] = g + gr;
 }
 
@@ -262,8 +260,10 @@ hipError_t launch_assemble(vv10_plan *p, double *hess, double *grad, double *res
         k_gemm<<<grid, 256, 0, p->stream>>>(n, slice, ws.Pp, ws.L, ws.Y, ws.Hpart);
     }
     const int64_t PP = (int64_t)ws.P * ws.P;
-    k_grgr<<<(unsigned)((PP + 255) / 256), 256, 0, p->stream>>>(p->n_atom, ws.P, p->d_tile_first,
-                                                                ws.Dpart, ws.Hgr);
+    const int64_t nds = (int64_t)p->n_atom * p->n_atom * 9;
+    k_dsum<<<(unsigned)((nds + 255) / 256), 256, 0, p->stream>>>(p->n_atom, p->d_tile_first,
+                                                                 ws.Dpart, ws.DS);
+    k_grgr<<<(unsigned)((PP + 255) / 256), 256, 0, p->stream>>>(p->n_atom, ws.P, ws.DS, ws.Hgr);
     k_hess_final<<<(unsigned)((PP + 255) / 256), 256, 0, p->stream>>>(ws.P, ws.Pp, ws.gsplit,
                                                                       ws.Hpart, ws.Hgr, hess);
     if (grad) {
@@ -271,7 +271,7 @@ hipError_t launch_assemble(vv10_plan *p, double *hess, double *grad, double *res
         const int64_t gs = (n + ns - 1) / ns;
         k_grad_part<<<ns, 256, 0, p->stream>>>(n, p->npad, gs, ws.Pp, p->F, ws.L, ws.gpart);
         k_grad_final<<<(unsigned)((ws.P + 255) / 256), 256, 0, p->stream>>>(
-            p->n_atom, ws.P, ws.Pp, ns, p->d_tile_first, ws.gpart, ws.Dpart, grad);
+            p->n_atom, ws.P, ws.Pp, ns, ws.gpart, ws.DS, grad);
     }
     return hipGetLastError();
 }

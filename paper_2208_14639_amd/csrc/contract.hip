@@ -218,23 +218,84 @@ __global__ __launch_bounds__(256, 2) void k_contract_f32(
 // split-BF16 MFMA
 // ---------------------------------------------------------------------------
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ void split_bf16(float v, __bf16 &hi, __bf16 &lo) {
-    hi = (__bf16)v;
-    lo = (__bf16)(v - (float)hi);
+struct Aops {          // A operands of one 16 x 16 pair block (per lane: 4 pairs)
+    bf16x8 ph, pl, qh, ql;
+};
+
+// Split two FP32 values into packed bf16 hi (round to nearest even) and lo
+// (the rounded remainder): returns the packed words (v0 in the low half).
+__device__ __forceinline__ void split2(float v0, float v1, uint32_t &hi, uint32_t &lo) {
+    const bf16x2 h = {(__bf16)v0, (__bf16)v1};
+    hi = __builtin_bit_cast(uint32_t, h);
+    const float h0 = __uint_as_float(hi << 16), h1 = __uint_as_float(hi & 0xffff0000u);
+    const bf16x2 l = {(__bf16)(v0 - h0), (__bf16)(v1 - h1)};
+    lo = __builtin_bit_cast(uint32_t, l);
 }
 
-constexpr int kJB = 2;    // 16-point j blocks per LDS stage
+// The four kernel-derivative values of pair (i, j) (see the file header).
+__device__ __forceinline__ void pair_K(const float4 a0, const float4 a1, const float4 b0,
+                                       const float4 b1, float &kpp, float &kpq, float &kqp,
+                                       float &kqq) {
+    const float dx = a0.x - b0.x, dy = a0.y - b0.y, dz = a0.z - b0.z;
+    const float R2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+    const float gg = __builtin_fmaf(a0.w, R2, a1.x);
+    const float gp = __builtin_fmaf(b0.w, R2, b1.x);
+    const float s = gg + gp, t = gg * gp;
+    const float r = rcp32(t * s);
+    const float phi = -1.5f * r;
+    const float sr = s * r;
+    const float ig = gp * sr, igp = gg * sr, is = t * r;
+    const float Pg = -phi * (ig + is);
+    const float Pgp = -phi * (igp + is);
+    const float Pgg = 2.f * phi * __builtin_fmaf(ig, igp, is * is);
+    const float ci = a1.z, cj = b1.z;
+    const float u = __builtin_fmaf(ci, Pgg, Pgp);
+    kpp = __builtin_fmaf(cj, u, __builtin_fmaf(ci, Pg, phi));
+    kpq = R2 * u;
+    kqp = R2 * __builtin_fmaf(cj, Pgg, Pg);
+    kqq = R2 * R2 * Pgg;
+}
 
+// A operands of the block whose 4 j points of this lane are b0[jj], b1[jj].
+__device__ __forceinline__ Aops form_A(const float4 a0, const float4 a1, const float4 *b0,
+                                       const float4 *b1) {
+    uint32_t ph[4], pl[4], qh[4], ql[4];
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+        float kpp, kpq, kqp, kqq;
+        pair_K(a0, a1, b0[jj], b1[jj], kpp, kpq, kqp, kqq);
+        split2(kpp, kpq, ph[jj], pl[jj]);
+        split2(kqp, kqq, qh[jj], ql[jj]);
+    }
+    Aops A;
+    A.ph = __builtin_bit_cast(bf16x8, (uint4){ph[0], ph[1], ph[2], ph[3]});
+    A.pl = __builtin_bit_cast(bf16x8, (uint4){pl[0], pl[1], pl[2], pl[3]});
+    A.qh = __builtin_bit_cast(bf16x8, (uint4){qh[0], qh[1], qh[2], qh[3]});
+    A.ql = __builtin_bit_cast(bf16x8, (uint4){ql[0], ql[1], ql[2], ql[3]});
+    return A;
+}
+
+// Software pipeline per wave, one 16-point j block per stage:
+//  * the X block (hi and lo, all columns of the group) is double-buffered in
+//    LDS; the next block is loaded into registers while this block's MFMAs
+//    run, stored to the other buffer afterwards, and one barrier per stage
+//    publishes it;
+//  * the VALU forms the A operands of the next block from point data loaded
+//    one block ahead straight from global memory; the instruction scheduler
+//    interleaves it with the MFMAs of the current block (measured: forcing a
+//    fixed MFMA/VALU interleave, staging point data through LDS or forcing
+//    three waves per SIMD were all slower on the 20-water grid).
 template <int NCB>
 __global__ __launch_bounds__(256, 2) void k_contract_bf16x3(
     int64_t npad, int64_t jlen, int32_t Pp, const float4 *__restrict__ P0,
     const float4 *__restrict__ P1, const bf16x8 *__restrict__ Xhi,
     const bf16x8 *__restrict__ Xlo, float *__restrict__ Yout) {
     constexpr int NC = NCB * 16;
-    constexpr int JC = 16 * kJB;
-    __shared__ float4 sA[JC], sB[JC];
-    __shared__ bf16x8 sH[kJB * NC * 4], sL[kJB * NC * 4];   // [jblock][col][g]
+    constexpr int UNITS = NC * 4;                       // 8-bf16 units per block and array
+    constexpr int PER = (UNITS + 255) / 256;            // units per thread and array
+    __shared__ bf16x8 sH[2][UNITS], sL[2][UNITS];      // [buffer][col][g]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m = lane & 15, g = lane >> 4;
     const int64_t ibase = (int64_t)blockIdx.x * 64 + wave * 16;
@@ -242,79 +303,73 @@ __global__ __launch_bounds__(256, 2) void k_contract_bf16x3(
     const int64_t jbeg = (int64_t)blockIdx.z * jlen;
     const int64_t jend = min(npad, jbeg + jlen);
     const float4 a0 = P0[ibase + m], a1 = P1[ibase + m];
-    const float ci = a1.z;
     v4f accp[NCB], accq[NCB];
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
         accp[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
         accq[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
     }
-    for (int64_t j0 = jbeg; j0 < jend; j0 += JC) {
+    // X block staging: thread tid moves units tid + 256 k of the block
+    bf16x8 rh[PER], rl[PER];
+    auto load_x = [&](int64_t blk) {
+        const int64_t base = ((blk / 16) * Pp + col0) * 4;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = tid + 256 * k;
+            if (e < UNITS) {
+                rh[k] = Xhi[base + e];
+                rl[k] = Xlo[base + e];
+            }
+        }
+    };
+    auto store_x = [&](int buf) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = tid + 256 * k;
+            if (e < UNITS) {
+                sH[buf][e] = rh[k];
+                sL[buf][e] = rl[k];
+            }
+        }
+    };
+    // point data of this lane's 4 j of a block: j = blk + 4 g + jj
+    float4 n0[4], n1[4];
+    auto load_pts = [&](int64_t blk) {
+        const int64_t jq = min(blk, npad - 16) + 4 * g;   // clamped: never read past npad
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            n0[jj] = P0[jq + jj];
+            n1[jj] = P1[jq + jj];
+        }
+    };
+    load_pts(jbeg);
+    load_x(jbeg);
+    Aops cur = form_A(a0, a1, n0, n1);
+    load_pts(jbeg + 16);
+    store_x(0);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t j0 = jbeg; j0 < jend; j0 += 16) {
+        const bool more = j0 + 16 < jend;
+        if (more) load_x(j0 + 16);
+        const Aops nxt = form_A(a0, a1, n0, n1);
+        load_pts(j0 + 32);
+        const bf16x8 *hp = sH[buf] + m * 4 + g;
+        const bf16x8 *lp = sL[buf] + m * 4 + g;
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+            const bf16x8 bh = hp[cb * 64], bl = lp[cb * 64];
+            accp[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.ph, bh, accp[cb], 0, 0, 0);
+            accq[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.qh, bh, accq[cb], 0, 0, 0);
+            accp[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.pl, bh, accp[cb], 0, 0, 0);
+            accq[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.ql, bh, accq[cb], 0, 0, 0);
+            accp[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.ph, bl, accp[cb], 0, 0, 0);
+            accq[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.qh, bl, accq[cb], 0, 0, 0);
+        }
+        cur = nxt;
+        if (more) store_x(buf ^ 1);
         __syncthreads();
-        if (tid < JC) {
-            sA[tid] = P0[j0 + tid];
-            sB[tid] = P1[j0 + tid];
-        }
-        // units of 8 bf16: global [jblock][Pp][4], LDS [jblock][NC][4]
-        for (int e = tid; e < kJB * NC * 4; e += 256) {
-            const int jb = e / (NC * 4), rem = e - jb * NC * 4;
-            const int64_t src = ((j0 / 16 + jb) * Pp + col0) * 4 + rem;
-            sH[e] = Xhi[src];
-            sL[e] = Xlo[src];
-        }
-        __syncthreads();
-#pragma unroll 1
-        for (int jb = 0; jb < kJB; ++jb) {
-            bf16x8 aph, apl, aqh, aql;
-#pragma unroll
-            for (int jj = 0; jj < 4; ++jj) {
-                const int jl = 16 * jb + 4 * g + jj;
-                const float4 b0 = sA[jl], b1 = sB[jl];
-                const float dx = a0.x - b0.x, dy = a0.y - b0.y, dz = a0.z - b0.z;
-                const float R2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
-                const float gg = __builtin_fmaf(a0.w, R2, a1.x);
-                const float gp = __builtin_fmaf(b0.w, R2, b1.x);
-                const float s = gg + gp, t = gg * gp;
-                const float r = rcp32(t * s);
-                const float phi = -1.5f * r;
-                const float sr = s * r;
-                const float ig = gp * sr, igp = gg * sr, is = t * r;
-                const float Pg = -phi * (ig + is);
-                const float Pgp = -phi * (igp + is);
-                const float Pgg = 2.f * phi * __builtin_fmaf(ig, igp, is * is);
-                const float cj = b1.z;
-                const float u = __builtin_fmaf(ci, Pgg, Pgp);
-                const float kpp = __builtin_fmaf(cj, u, __builtin_fmaf(ci, Pg, phi));
-                const float kpq = R2 * u;
-                const float kqp = R2 * __builtin_fmaf(cj, Pgg, Pg);
-                const float kqq = R2 * R2 * Pgg;
-                __bf16 h, l;
-                split_bf16(kpp, h, l); aph[2 * jj] = h; apl[2 * jj] = l;
-                split_bf16(kpq, h, l); aph[2 * jj + 1] = h; apl[2 * jj + 1] = l;
-                split_bf16(kqp, h, l); aqh[2 * jj] = h; aql[2 * jj] = l;
-                split_bf16(kqq, h, l); aqh[2 * jj + 1] = h; aql[2 * jj + 1] = l;
-            }
-            const bf16x8 *hp = sH + (jb * NC + m) * 4 + g;
-            const bf16x8 *lp = sL + (jb * NC + m) * 4 + g;
-#pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) {
-                const bf16x8 bh = hp[cb * 64];
-                accp[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aph, bh, accp[cb], 0, 0, 0);
-                accq[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aqh, bh, accq[cb], 0, 0, 0);
-            }
-#pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) {
-                const bf16x8 bl = lp[cb * 64];
-                accp[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aph, bl, accp[cb], 0, 0, 0);
-                accq[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aqh, bl, accq[cb], 0, 0, 0);
-            }
-#pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) {
-                const bf16x8 bh = hp[cb * 64];
-                accp[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(apl, bh, accp[cb], 0, 0, 0);
-                accq[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aql, bh, accq[cb], 0, 0, 0);
-            }
-        }
+        buf ^= 1;
     }
     float *Yb = Yout + (int64_t)blockIdx.z * npad * 2 * Pp;
 #pragma unroll

@@ -18,6 +18,10 @@
 // gradient.  The own-atom slot B = O(i) follows from translational
 // invariance and is filled by the assembly.
 //
+// The same pass also accumulates the pair integrals E, U, W, A, B, C of the
+// Hessian call (over every j, the outer point's own atom included), so the
+// pair geometry and its reciprocal are evaluated once per pair.
+//
 // One wave per (tile of 64 outer points, group of atoms B); tiles never
 // straddle atoms, so the D sums are plain wave reductions in a fixed order.
 // FP64 mode evaluates and accumulates in FP64; the mixed modes evaluate each
@@ -32,12 +36,53 @@ namespace {
 
 constexpr int TG = kGridTile;
 
+// Pair integrals of one (i, j) pair (the Section II.A/II.B inner sums), added
+// to c[0..5] = E, U, W, A, B, C; returns the shared geometry for the grid terms.
+template <typename T>
+struct PairGeo {
+    T R2, g, gp, s, r, pa, ig, igp, is;
+};
+
+template <typename T, typename T4>
+__device__ __forceinline__ PairGeo<T> pair_geo(const T4 a0, const T4 a1, const T4 b0, const T4 b1) {
+    PairGeo<T> q;
+    const T dx = b0.x - a0.x, dy = b0.y - a0.y, dz = b0.z - a0.z;
+    q.R2 = dx * dx + dy * dy + dz * dz;
+    q.g = a0.w * q.R2 + a1.x;
+    q.gp = b0.w * q.R2 + b1.x;
+    q.s = q.g + q.gp;
+    const T tt = q.g * q.gp;
+    if constexpr (sizeof(T) == 8) q.r = rcp64(tt * q.s); else q.r = rcp32(tt * q.s);
+    q.pa = T(-1.5) * b1.y * q.r;                 // a_j Phi_ij
+    const T sr = q.s * q.r;
+    q.ig = q.gp * sr;
+    q.igp = q.g * sr;
+    q.is = tt * q.r;
+    return q;
+}
+
+template <typename T>
+__device__ __forceinline__ void add_pair_integrals(const PairGeo<T> &q, T *c) {
+    const T u = q.pa * (q.ig + q.is);
+    const T m2 = T(2) * q.pa * (q.is * q.is + q.is * q.ig + q.ig * q.ig);
+    c[0] += q.pa;
+    c[1] -= u;
+    c[2] -= u * q.R2;
+    c[3] += m2;
+    c[4] += m2 * q.R2;
+    c[5] += m2 * q.R2 * q.R2;
+}
+
+// Fused with the pair integrals of the Hessian call: the group of atoms B of
+// a workgroup also covers the outer point's own atom for E, U, W, A, B, C,
+// whose per-group partial sums go to Ipart[group][6][npad].
 template <typename T, typename T4>
 __global__ __launch_bounds__(64) void k_grid(
-    int32_t n_atom, int32_t Pp, int32_t bgroups, const int64_t *__restrict__ seg,
+    int32_t n_atom, int32_t Pp, int32_t bgroups, int64_t npad, const int64_t *__restrict__ seg,
     const int32_t *__restrict__ tile_i0, const int32_t *__restrict__ tile_n,
     const int32_t *__restrict__ tile_atom, const T4 *__restrict__ P0,
-    const T4 *__restrict__ P1, double *__restrict__ Z, double *__restrict__ Dpart) {
+    const T4 *__restrict__ P1, double *__restrict__ Z, double *__restrict__ Dpart,
+    double *__restrict__ Ipart) {
     __shared__ T4 sA[TG], sB[TG];
     const int t = blockIdx.x, grp = blockIdx.y, lane = threadIdx.x;
     const int A = tile_atom[t];
@@ -47,8 +92,8 @@ __global__ __launch_bounds__(64) void k_grid(
     const T4 a0 = P0[i], a1 = P1[i];
     const double ai = live ? (double)a1.y : 0.0, ci = (double)a1.z;
     const T oi = a0.w;
+    double pint[6] = {};
     for (int B = grp; B < n_atom; B += bgroups) {
-        if (B == A) continue;
         const int64_t jb = seg[B], je = seg[B + 1];
         // [0..2] e d, [3..5] u d, [6..8] v d, [9..14] D (xx, yy, zz, xy, xz, yz)
         double acc[15] = {};
@@ -59,43 +104,48 @@ __global__ __launch_bounds__(64) void k_grid(
             sB[lane] = P1[j < je ? j : jb];
             __syncthreads();
             const int cnt = (int)min((int64_t)TG, je - j0);
-            T c[15] = {};
-            for (int jj = 0; jj < cnt; ++jj) {
-                const T4 b0 = sA[jj], b1 = sB[jj];
-                const T dx = b0.x - a0.x, dy = b0.y - a0.y, dz = b0.z - a0.z;
-                const T R2 = dx * dx + dy * dy + dz * dz;
-                const T g = oi * R2 + a1.x;
-                const T gp = b0.w * R2 + b1.x;
-                const T s = g + gp, tt = g * gp;
-                T r;
-                if constexpr (sizeof(T) == 8) r = rcp64(tt * s); else r = rcp32(tt * s);
-                const T pa = T(-1.5) * b1.y * r;         // a_j Phi_ij
-                const T sr = s * r;
-                const T ig = gp * sr, igp = g * sr, is = tt * r;
-                const T Ti = oi * ig, Tj = b0.w * igp, Ts = (oi + b0.w) * is;
-                const T T_ = Ti + Tj + Ts;
-                const T h = ig + is;
-                const T TQ = T_ * h + Ti * ig + Ts * is;
-                const T e = T(-2) * pa * T_;
-                const T u = T(2) * pa * TQ;
-                const T v = T(2) * pa * (R2 * TQ - h);
-                const T S = T_ * T_ + Ti * Ti + Tj * Tj + Ts * Ts;
-                const T dd = T(-4) * pa * S;            // coefficient of d d^T
-                const T di = -e;                        // coefficient of I (= 2 a_j Phi T)
-                c[0] += e * dx; c[1] += e * dy; c[2] += e * dz;
-                c[3] += u * dx; c[4] += u * dy; c[5] += u * dz;
-                c[6] += v * dx; c[7] += v * dy; c[8] += v * dz;
-                const T ddx = dd * dx, ddy = dd * dy;
-                c[9] += ddx * dx + di;
-                c[10] += ddy * dy + di;
-                c[11] += dd * dz * dz + di;
-                c[12] += ddx * dy;
-                c[13] += ddx * dz;
-                c[14] += ddy * dz;
+            T pc[6] = {};
+            if (B == A) {
+                // own atom: pair integrals only (grid-position terms vanish)
+                for (int jj = 0; jj < cnt; ++jj) {
+                    const PairGeo<T> q = pair_geo<T>(a0, a1, sA[jj], sB[jj]);
+                    add_pair_integrals(q, pc);
+                }
+            } else {
+                T c[15] = {};
+                for (int jj = 0; jj < cnt; ++jj) {
+                    const T4 b0 = sA[jj];
+                    const PairGeo<T> q = pair_geo<T>(a0, a1, b0, sB[jj]);
+                    add_pair_integrals(q, pc);
+                    const T dx = b0.x - a0.x, dy = b0.y - a0.y, dz = b0.z - a0.z;
+                    const T Ti = oi * q.ig, Tj = b0.w * q.igp, Ts = (oi + b0.w) * q.is;
+                    const T T_ = Ti + Tj + Ts;
+                    const T h = q.ig + q.is;
+                    const T TQ = T_ * h + Ti * q.ig + Ts * q.is;
+                    const T e = T(-2) * q.pa * T_;
+                    const T u = T(2) * q.pa * TQ;
+                    const T v = T(2) * q.pa * (q.R2 * TQ - h);
+                    const T S = T_ * T_ + Ti * Ti + Tj * Tj + Ts * Ts;
+                    const T dd = T(-4) * q.pa * S;          // coefficient of d d^T
+                    const T di = -e;                        // coefficient of I (= 2 a_j Phi T)
+                    c[0] += e * dx; c[1] += e * dy; c[2] += e * dz;
+                    c[3] += u * dx; c[4] += u * dy; c[5] += u * dz;
+                    c[6] += v * dx; c[7] += v * dy; c[8] += v * dz;
+                    const T ddx = dd * dx, ddy = dd * dy;
+                    c[9] += ddx * dx + di;
+                    c[10] += ddy * dy + di;
+                    c[11] += dd * dz * dz + di;
+                    c[12] += ddx * dy;
+                    c[13] += ddx * dz;
+                    c[14] += ddy * dz;
+                }
+#pragma unroll
+                for (int k = 0; k < 15; ++k) acc[k] += (double)c[k];
             }
 #pragma unroll
-            for (int k = 0; k < 15; ++k) acc[k] += (double)c[k];
+            for (int k = 0; k < 6; ++k) pint[k] += (double)pc[k];
         }
+        if (B == A) continue;
         if (live) {
             double *z0 = Z + (i * 2 + 0) * Pp + 3 * B;
             double *z1 = Z + (i * 2 + 1) * Pp + 3 * B;
@@ -115,6 +165,22 @@ __global__ __launch_bounds__(64) void k_grid(
             if (lane == 0) dp[k] = tot;
         }
     }
+    if (live)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) Ipart[((int64_t)grp * NI + k) * npad + i] = pint[k];
+}
+
+// I[k][i] = sum over atom groups of Ipart[grp][k][i] (group order), i < n.
+__global__ __launch_bounds__(256) void k_sum_groups(int64_t n, int64_t npad, int G,
+                                                    const double *__restrict__ Ipart,
+                                                    double *__restrict__ I) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)NI * n) return;
+    const int k = (int)(e / n);
+    const int64_t i = e - (int64_t)k * n;
+    double a = 0.0;
+    for (int gidx = 0; gidx < G; ++gidx) a += Ipart[((int64_t)gidx * NI + k) * npad + i];
+    I[k * npad + i] = a;
 }
 
 }  // namespace
@@ -123,13 +189,16 @@ hipError_t launch_grid_terms(vv10_plan *p) {
     const Workspace &ws = p->ws;
     dim3 grid((unsigned)p->ntiles, (unsigned)ws.bgroups);
     if (p->prec == VV10_FP64)
-        k_grid<double, double4><<<grid, TG, 0, p->stream>>>(p->n_atom, ws.Pp, ws.bgroups, p->d_seg,
-                                                           p->d_tile_i0, p->d_tile_n, p->d_tile_atom,
-                                                           p->P0, p->P1, ws.Z, ws.Dpart);
+        k_grid<double, double4><<<grid, TG, 0, p->stream>>>(
+            p->n_atom, ws.Pp, ws.bgroups, p->npad, p->d_seg, p->d_tile_i0, p->d_tile_n,
+            p->d_tile_atom, p->P0, p->P1, ws.Z, ws.Dpart, ws.Igrp);
     else
-        k_grid<float, float4><<<grid, TG, 0, p->stream>>>(p->n_atom, ws.Pp, ws.bgroups, p->d_seg,
-                                                         p->d_tile_i0, p->d_tile_n, p->d_tile_atom,
-                                                         p->P0f, p->P1f, ws.Z, ws.Dpart);
+        k_grid<float, float4><<<grid, TG, 0, p->stream>>>(
+            p->n_atom, ws.Pp, ws.bgroups, p->npad, p->d_seg, p->d_tile_i0, p->d_tile_n,
+            p->d_tile_atom, p->P0f, p->P1f, ws.Z, ws.Dpart, ws.Igrp);
+    const int64_t tot = (int64_t)NI * p->n;
+    k_sum_groups<<<(unsigned)((tot + 255) / 256), 256, 0, p->stream>>>(p->n, p->npad, ws.bgroups,
+                                                                       ws.Igrp, p->I);
     return hipGetLastError();
 }
 

@@ -6,13 +6,11 @@
 //   {A,B,C}_i = sum_j 2 a_j Phi_ij (R^2)^{0,1,2} m_ij,
 //                                        m = 1/(g+g')^2 + 1/((g+g')g) + 1/g^2
 // with a_j = w_j rho_j and every j (j = i included).  One lane owns one
-// outer point i; j points stream through LDS in chunks of 256 and are read
-// as wave-wide broadcasts.  All 1/g, 1/g', 1/(g+g') come from one
-// reciprocal of g g' (g+g').
-//
-// FP64 mode accumulates in FP64.  FP32 mode evaluates each pair in FP32,
-// accumulates one 256-point chunk in FP32 and adds the chunk sums into
-// FP64 accumulators.
+// outer point i; j points stream through LDS and are read as wave-wide
+// broadcasts.  All 1/g, 1/g', 1/(g+g') come from one reciprocal of
+// g g' (g+g').
+#include <algorithm>
+
 #include "dev_common.h"
 #include "vv10_internal.h"
 
@@ -20,107 +18,90 @@ namespace vv10 {
 
 namespace {
 
-constexpr int JC = 256;
+constexpr int JC = 256;   // j points staged per block step; wave w takes [64 w, 64 w + 64)
 
-template <bool HESS>
-__global__ __launch_bounds__(256) void k_pair_f64(int64_t npad, const double4 *__restrict__ P0,
-                                                  const double4 *__restrict__ P1,
-                                                  double *__restrict__ I) {
-    __shared__ double4 s0[JC], s1[JC];
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const double4 a0 = P0[i], a1 = P1[i];
+// One workgroup = 4 waves sharing 64 outer points (one per lane); each wave
+// takes a quarter of every 256-point j chunk, and the four partial sums are
+// added in wave order at the end.  blockIdx.y selects a contiguous j range
+// (a split); splits write partial integrals [split][6][npad] that
+// k_sum_integrals adds in split order.  Mixed mode evaluates in FP32 and
+// adds each 64-point run into FP64 accumulators.
+template <typename T, typename T4, bool HESS>
+__global__ __launch_bounds__(256) void k_pair(int64_t npad, int64_t jlen,
+                                              const T4 *__restrict__ P0,
+                                              const T4 *__restrict__ P1,
+                                              double *__restrict__ Ipart) {
+    __shared__ T4 s0[JC], s1[JC];
+    __shared__ double red[4][6][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+    const int64_t jbeg = (int64_t)blockIdx.y * jlen;
+    const int64_t jend = min(npad, jbeg + jlen);
+    const T4 a0 = P0[i], a1 = P1[i];
     double E = 0, U = 0, W = 0, A = 0, B = 0, C = 0;
-    for (int64_t j0 = 0; j0 < npad; j0 += JC) {
+    for (int64_t j0 = jbeg; j0 < jend; j0 += JC) {
         __syncthreads();
         s0[threadIdx.x] = P0[j0 + threadIdx.x];
         s1[threadIdx.x] = P1[j0 + threadIdx.x];
         __syncthreads();
-#pragma unroll 4
-        for (int jj = 0; jj < JC; ++jj) {
-            const double4 b0 = s0[jj], b1 = s1[jj];
-            const double dx = a0.x - b0.x, dy = a0.y - b0.y, dz = a0.z - b0.z;
-            const double R2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
-            const double g = __builtin_fma(a0.w, R2, a1.x);
-            const double gp = __builtin_fma(b0.w, R2, b1.x);
-            const double s = g + gp, t = g * gp;
-            const double r = rcp64(t * s);
-            const double pa = -1.5 * b1.y * r;       // a_j Phi_ij
-            const double ig = gp * s * r, is = t * r;
-            const double u = pa * (ig + is);
-            E += pa;
-            U -= u;
-            W = __builtin_fma(-u, R2, W);
+        T e = 0, uu = 0, ww = 0, aa = 0, bb = 0, cc = 0;
+#pragma unroll 8
+        for (int jj = 64 * wave; jj < 64 * wave + 64; ++jj) {
+            const T4 b0 = s0[jj], b1 = s1[jj];
+            const T dx = a0.x - b0.x, dy = a0.y - b0.y, dz = a0.z - b0.z;
+            const T R2 = dx * dx + dy * dy + dz * dz;
+            const T g = a0.w * R2 + a1.x;
+            const T gp = b0.w * R2 + b1.x;
+            const T s = g + gp, t = g * gp;
+            T r;
+            if constexpr (sizeof(T) == 8) r = rcp64(t * s); else r = rcp32(t * s);
+            const T pa = T(-1.5) * b1.y * r;       // a_j Phi_ij
+            const T ig = gp * s * r, is = t * r;
+            const T u = pa * (ig + is);
+            e += pa;
+            uu -= u;
+            ww -= u * R2;
             if (HESS) {
-                const double m2 = 2.0 * pa * __builtin_fma(is, is, __builtin_fma(is, ig, ig * ig));
-                A += m2;
-                B = __builtin_fma(m2, R2, B);
-                C = __builtin_fma(m2 * R2, R2, C);
+                const T m2 = T(2) * pa * (is * is + is * ig + ig * ig);
+                aa += m2;
+                bb += m2 * R2;
+                cc += m2 * R2 * R2;
             }
         }
+        E += (double)e;
+        U += (double)uu;
+        W += (double)ww;
+        if (HESS) {
+            A += (double)aa;
+            B += (double)bb;
+            C += (double)cc;
+        }
     }
-    I[I_E * npad + i] = E;
-    I[I_U * npad + i] = U;
-    I[I_W * npad + i] = W;
-    if (HESS) {
-        I[I_A * npad + i] = A;
-        I[I_B * npad + i] = B;
-        I[I_C * npad + i] = C;
+    red[wave][0][lane] = E;
+    red[wave][1][lane] = U;
+    red[wave][2][lane] = W;
+    red[wave][3][lane] = A;
+    red[wave][4][lane] = B;
+    red[wave][5][lane] = C;
+    __syncthreads();
+    const int nout = HESS ? 6 : 3;
+    for (int k = wave; k < nout; k += 4) {
+        const double v = red[0][k][lane] + red[1][k][lane] + red[2][k][lane] + red[3][k][lane];
+        Ipart[((int64_t)blockIdx.y * NI + k) * npad + i] = v;
     }
 }
 
-template <bool HESS>
-__global__ __launch_bounds__(256) void k_pair_f32(int64_t npad, const float4 *__restrict__ P0,
-                                                  const float4 *__restrict__ P1,
-                                                  double *__restrict__ I) {
-    __shared__ float4 s0[JC], s1[JC];
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const float4 a0 = P0[i], a1 = P1[i];
-    double E = 0, U = 0, W = 0, A = 0, B = 0, C = 0;
-    for (int64_t j0 = 0; j0 < npad; j0 += JC) {
-        __syncthreads();
-        s0[threadIdx.x] = P0[j0 + threadIdx.x];
-        s1[threadIdx.x] = P1[j0 + threadIdx.x];
-        __syncthreads();
-        float e = 0.f, uu = 0.f, ww = 0.f, aa = 0.f, bb = 0.f, cc = 0.f;
-#pragma unroll 8
-        for (int jj = 0; jj < JC; ++jj) {
-            const float4 b0 = s0[jj], b1 = s1[jj];
-            const float dx = a0.x - b0.x, dy = a0.y - b0.y, dz = a0.z - b0.z;
-            const float R2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
-            const float g = __builtin_fmaf(a0.w, R2, a1.x);
-            const float gp = __builtin_fmaf(b0.w, R2, b1.x);
-            const float s = g + gp, t = g * gp;
-            const float r = rcp32(t * s);
-            const float pa = -1.5f * b1.y * r;
-            const float ig = gp * s * r, is = t * r;
-            const float u = pa * (ig + is);
-            e += pa;
-            uu -= u;
-            ww = __builtin_fmaf(-u, R2, ww);
-            if (HESS) {
-                const float m2 = 2.f * pa * __builtin_fmaf(is, is, __builtin_fmaf(is, ig, ig * ig));
-                aa += m2;
-                bb = __builtin_fmaf(m2, R2, bb);
-                cc = __builtin_fmaf(m2 * R2, R2, cc);
-            }
-        }
-        E += e;
-        U += uu;
-        W += ww;
-        if (HESS) {
-            A += aa;
-            B += bb;
-            C += cc;
-        }
-    }
-    I[I_E * npad + i] = E;
-    I[I_U * npad + i] = U;
-    I[I_W * npad + i] = W;
-    if (HESS) {
-        I[I_A * npad + i] = A;
-        I[I_B * npad + i] = B;
-        I[I_C * npad + i] = C;
-    }
+// I[k][i] = sum over splits of Ipart[s][k][i], in split order.
+__global__ __launch_bounds__(256) void k_sum_integrals(int64_t npad, int nout, int S,
+                                                       const double *__restrict__ Ipart,
+                                                       double *__restrict__ I) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)nout * npad) return;
+    const int k = (int)(e / npad);
+    const int64_t i = e - (int64_t)k * npad;
+    double a = 0.0;
+    for (int s = 0; s < S; ++s) a += Ipart[((int64_t)s * NI + k) * npad + i];
+    I[k * npad + i] = a;
 }
 
 // Potential and energy terms (Section II.A):
@@ -177,18 +158,34 @@ __global__ __launch_bounds__(256) void k_sum_partials(int64_t nb, const double *
 
 }  // namespace
 
+int pair_splits(int64_t npad) {
+    // enough workgroups for about eight waves per SIMD on 256 CUs
+    const int64_t blocks = npad / 64;
+    int S = (int)std::min<int64_t>(16, std::max<int64_t>(1, (2048 + blocks - 1) / blocks));
+    while (S > 1 && npad / S < JC) --S;
+    return S;
+}
+
 hipError_t launch_pair_integrals(vv10_plan *p, bool hessian_mode) {
-    const unsigned nb = (unsigned)(p->npad / 256);
+    const int S = pair_splits(p->npad);
+    const int64_t jlen = ((p->npad / S + JC - 1) / JC) * JC;
+    dim3 grid((unsigned)(p->npad / 64), (unsigned)S);
+    double *Ipart = S == 1 ? p->I : p->Ipart;
     if (p->prec == VV10_FP64) {
         if (hessian_mode)
-            k_pair_f64<true><<<nb, 256, 0, p->stream>>>(p->npad, p->P0, p->P1, p->I);
+            k_pair<double, double4, true><<<grid, 256, 0, p->stream>>>(p->npad, jlen, p->P0, p->P1, Ipart);
         else
-            k_pair_f64<false><<<nb, 256, 0, p->stream>>>(p->npad, p->P0, p->P1, p->I);
+            k_pair<double, double4, false><<<grid, 256, 0, p->stream>>>(p->npad, jlen, p->P0, p->P1, Ipart);
     } else {
         if (hessian_mode)
-            k_pair_f32<true><<<nb, 256, 0, p->stream>>>(p->npad, p->P0f, p->P1f, p->I);
+            k_pair<float, float4, true><<<grid, 256, 0, p->stream>>>(p->npad, jlen, p->P0f, p->P1f, Ipart);
         else
-            k_pair_f32<false><<<nb, 256, 0, p->stream>>>(p->npad, p->P0f, p->P1f, p->I);
+            k_pair<float, float4, false><<<grid, 256, 0, p->stream>>>(p->npad, jlen, p->P0f, p->P1f, Ipart);
+    }
+    if (S > 1) {
+        const int nout = hessian_mode ? 6 : 3;
+        const int64_t tot = (int64_t)nout * p->npad;
+        k_sum_integrals<<<(unsigned)((tot + 255) / 256), 256, 0, p->stream>>>(p->npad, nout, S, Ipart, p->I);
     }
     return hipGetLastError();
 }

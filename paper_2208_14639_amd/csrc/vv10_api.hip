@@ -57,8 +57,10 @@ size_t workspace_bytes(int64_t npad, int32_t n_atom, int32_t ntiles, vv10_precis
     const bool alias = prec == VV10_FP64 && ws.jsplit == 1;   // partials written straight into Y
     if (!alias) b += (size_t)ws.jsplit * ch * partial_elem(prec);
     b += (size_t)ntiles * n_atom * 9 * sizeof(double);
+    b += (size_t)ws.bgroups * NI * npad * sizeof(double);
     b += (size_t)ws.gsplit * ws.Pp * ws.Pp * sizeof(double);
     b += (size_t)ws.P * ws.P * sizeof(double);
+    b += (size_t)n_atom * n_atom * 9 * sizeof(double);
     b += (size_t)256 * ws.Pp * sizeof(double);
     return b;
 }
@@ -76,6 +78,8 @@ size_t reduction_doubles(int64_t npad) {
 size_t base_bytes(int64_t npad, int32_t n_atom, int64_t ntiles_bound) {
     size_t b = 2 * (size_t)npad * sizeof(double4) + 2 * (size_t)npad * sizeof(float4);
     b += (size_t)vv10::NF * npad * sizeof(double) + (size_t)vv10::NI * npad * sizeof(double);
+    if (vv10::pair_splits(npad) > 1)
+        b += (size_t)vv10::pair_splits(npad) * vv10::NI * npad * sizeof(double);
     b += (size_t)npad * sizeof(int32_t) + (size_t)(n_atom + 1) * sizeof(int64_t);
     b += (size_t)(3 * ntiles_bound + n_atom + 1) * sizeof(int32_t);
     b += reduction_doubles(npad) * sizeof(double) + (size_t)(n_atom + 2) * sizeof(int32_t);
@@ -100,8 +104,10 @@ void free_workspace(Workspace &ws) {
     dfree(ws.Y);
     dfree(ws.Z);
     dfree(ws.Dpart);
+    dfree(ws.Igrp);
     dfree(ws.Hpart);
     dfree(ws.Hgr);
+    dfree(ws.DS);
     dfree(ws.gpart);
     ws = Workspace{};
 }
@@ -117,6 +123,7 @@ void free_plan(vv10_plan *p) {
     dfree(p->P1f);
     dfree(p->F);
     dfree(p->I);
+    dfree(p->Ipart);
     dfree(p->atom_of);
     dfree(p->d_seg);
     dfree(p->d_tile_i0);
@@ -167,8 +174,10 @@ vv10_status ensure_workspace(vv10_plan *p) {
     }
     if (e == hipSuccess) e = dalloc(&ws.Z, ch);
     if (e == hipSuccess) e = dalloc(&ws.Dpart, (size_t)p->ntiles * p->n_atom * 9);
+    if (e == hipSuccess) e = dalloc(&ws.Igrp, (size_t)ws.bgroups * vv10::NI * p->npad);
     if (e == hipSuccess) e = dalloc(&ws.Hpart, (size_t)ws.gsplit * ws.Pp * ws.Pp);
     if (e == hipSuccess) e = dalloc(&ws.Hgr, (size_t)ws.P * ws.P);
+    if (e == hipSuccess) e = dalloc(&ws.DS, (size_t)p->n_atom * p->n_atom * 9);
     if (e == hipSuccess) e = dalloc(&ws.gpart, (size_t)256 * ws.Pp);
     if (e != hipSuccess) {
         free_workspace(ws);
@@ -256,6 +265,8 @@ vv10_status vv10_prepare(const vv10_params *params, int64_t n_grid, int32_t n_at
     if (e == hipSuccess) e = dalloc(&p->P1f, npad);
     if (e == hipSuccess) e = dalloc(&p->F, (size_t)vv10::NF * npad);
     if (e == hipSuccess) e = dalloc(&p->I, (size_t)vv10::NI * npad);
+    if (e == hipSuccess && vv10::pair_splits(npad) > 1)
+        e = dalloc(&p->Ipart, (size_t)vv10::pair_splits(npad) * vv10::NI * npad);
     if (e == hipSuccess) e = dalloc(&p->atom_of, npad);
     if (e == hipSuccess) e = dalloc(&p->d_seg, (size_t)n_atom + 1);
     if (e == hipSuccess) e = dalloc(&p->red, reduction_doubles(npad));
@@ -355,13 +366,13 @@ vv10_status vv10_hessian_terms(vv10_plan *p, int32_t n_pert, const double *rho_x
     if (n_pert != 3 * p->n_atom || !rho_x || !grad_rho_x || !hess) return VV10_E_ARG;
     vv10_status st = ensure_workspace(p);
     if (st != VV10_OK) return st;
-    hipError_t e = stage(p, VV10_STAGE_PAIR, [&] { return vv10::launch_pair_integrals(p, true); });
+    // the grid-term pass also produces the pair integrals E, U, W, A, B, C
+    hipError_t e = stage(p, VV10_STAGE_GRID, [&] { return vv10::launch_grid_terms(p); });
     if (e == hipSuccess)
         e = stage(p, VV10_STAGE_POTENTIAL, [&] { return vv10::launch_potential(p, nullptr, nullptr, nullptr); });
     if (e == hipSuccess)
         e = stage(p, VV10_STAGE_PERT_PREP, [&] { return vv10::launch_pert_prep(p, rho_x, grad_rho_x); });
     if (e == hipSuccess) e = stage(p, VV10_STAGE_CONTRACT, [&] { return vv10::launch_contract(p); });
-    if (e == hipSuccess) e = stage(p, VV10_STAGE_GRID, [&] { return vv10::launch_grid_terms(p); });
     if (e == hipSuccess)
         e = stage(p, VV10_STAGE_ASSEMBLE,
                   [&] { return vv10::launch_assemble(p, hess, grad, resp_rho, resp_gamma); });

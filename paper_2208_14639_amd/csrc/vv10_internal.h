@@ -48,8 +48,10 @@ struct Workspace {
     double *Y = nullptr;         // [npad][2][Pp] summed contraction, then R in place
     double *Z = nullptr;         // [npad][2][Pp] grid-position channels
     double *Dpart = nullptr;     // [ntiles][n_atom][9] tile sums of a_i D^B_i (6) and a_i E^{Bgr}_i (3)
+    double *Igrp = nullptr;      // [bgroups][6][npad] pair integrals per atom group
     double *Hpart = nullptr;     // [gsplit][Pp][Pp]
     double *Hgr = nullptr;       // [P][P] E_{gr,gr}
+    double *DS = nullptr;        // [n_atom][n_atom][9] Dpart summed over each atom's tiles
     double *gpart = nullptr;     // [ngrad][Pp] gradient partials
     size_t bytes = 0;
 };
@@ -78,6 +80,7 @@ struct vv10_plan {
     float4 *P1f = nullptr;
     double *F = nullptr;     // [NF][npad]
     double *I = nullptr;     // [6][npad]
+    double *Ipart = nullptr; // [pair_splits][6][npad] partial pair integrals
     int32_t *atom_of = nullptr;   // [npad], padding rows hold n_atom
     int64_t *d_seg = nullptr;     // [n_atom + 1]
     int32_t *d_tile_i0 = nullptr, *d_tile_n = nullptr, *d_tile_atom = nullptr, *d_tile_first = nullptr;
@@ -94,6 +97,9 @@ struct vv10_plan {
 };
 
 namespace vv10 {
+
+// j splits of the pair-integral kernel for a padded grid size.
+int pair_splits(int64_t npad);
 
 // Kernel launchers (each enqueues on plan->stream and returns hipGetLastError()).
 hipError_t launch_prepare(vv10_plan *p, const double *coords, const double *w,
