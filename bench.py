@@ -99,7 +99,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="water_hexamer",
                     choices=["water_dimer", "water_hexamer", "water_20mer"])
-    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--prec", default="bf16x3", choices=["fp64", "fp32", "bf16x3"],
+                    help="arithmetic of the headline path (default: split-BF16 mixed)")
+    ap.add_argument("--compare", default="fp64", choices=["fp64", "fp32", "bf16x3", "none"],
+                    help="also time this precision on the same workload (the 'vs FP64' ratio)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one device copy of 256 MiB first (HBM counter calibration)")
@@ -142,7 +145,7 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    def step():
+    def step(prec=prec, hess=hess, gradient=gradient, energy=energy, f_rho=f_rho, f_gamma=f_gamma):
         h = vv10.vv10_prepare(p.b, p.C, n, na, coords, w, atom_of, rho, grad, prec, stream)
         try:
             vv10.vv10_set_timing(h, True)
@@ -156,19 +159,21 @@ def main():
         st["potential_energy"] = st_e["potential"]
         return st
 
-    for k in range(args.warmup):
-        step()
-        log(f"warmup {k + 1}/{args.warmup} done")
-    torch.cuda.synchronize()
-    stages = []
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        stages.append(step())
-        log(f"step {k + 1}/{args.steps} done")
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    dt = (t1 - t0) / args.steps
-    stage_ms = {k: float(np.mean([s[k] for s in stages])) for k in stages[0]}
+    def timed(tag, **kw):
+        for k in range(args.warmup):
+            step(**kw)
+            log(f"{tag}: warmup {k + 1}/{args.warmup} done")
+        torch.cuda.synchronize()
+        stages = []
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            stages.append(step(**kw))
+            log(f"{tag}: step {k + 1}/{args.steps} done")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        return (t1 - t0) / args.steps, {k: float(np.mean([s[k] for s in stages])) for k in stages[0]}
+
+    dt, stage_ms = timed(args.prec)
     pair_pert = float(n) * n * P
     value = pair_pert / dt
 
@@ -182,7 +187,7 @@ def main():
     pair_rate = float(n) * n / (stage_ms["pair_energy"] * 1e-3)
 
     out = {
-        "metric": "VV10 Hessian grid-pair*perturbation/s",
+        "metric": "VV10 Hessian grid-pair\u00b7perturbation/s, mixed vs FP64, at stated err; p99 latency",
         "value": value,
         "unit": "pair*pert/s",
         "n_gpus": 1,
@@ -203,6 +208,21 @@ def main():
         "footprint_bytes": vv10.vv10_footprint_bytes(n, na, prec),
     }
 
+    cmp = None
+    if args.compare != "none" and args.compare != args.prec:
+        h2 = torch.empty_like(hess)
+        g2 = torch.empty_like(gradient)
+        e2 = torch.empty_like(energy)
+        fr2, fg2 = torch.empty_like(f_rho), torch.empty_like(f_gamma)
+        dt2, st2 = timed(args.compare, prec=vv10.PRECISIONS[args.compare], hess=h2, gradient=g2,
+                         energy=e2, f_rho=fr2, f_gamma=fg2)
+        cmp = dict(precision=args.compare, ms_per_step=dt2 * 1e3, value=pair_pert / dt2,
+                   stage_ms=st2, hess=h2.cpu().numpy(), energy=e2.item(),
+                   f_rho=fr2.cpu().numpy(), f_gamma=fg2.cpu().numpy())
+        out[f"vs_{args.compare}"] = {"precision": args.compare, "ms_per_step": dt2 * 1e3,
+                                     "value": pair_pert / dt2, "speedup": dt2 / dt,
+                                     "contract_ms": st2["contract"], "stage_ms": st2}
+
     # results of the last step, checked against the oracle when it ran in full
     H = hess.cpu().numpy()
     out["checks"] = {"hess_symmetric": bool(np.array_equal(H, H.T)),
@@ -213,15 +233,18 @@ def main():
         cb, ref = cpu_baseline(p)
         out["cpu_baseline"] = cb
         if ref is not None:
-            out["errors_vs_oracle"] = {
-                "energy_rel": abs(energy.item() - ref["E"]) / abs(ref["E"]),
-                "f_rho_normwise": float(np.max(np.abs(f_rho.cpu().numpy() - ref["f_rho"]))
-                                        / np.max(np.abs(ref["f_rho"]))),
-                "f_gamma_normwise": float(np.max(np.abs(f_gamma.cpu().numpy() - ref["f_gamma"]))
-                                          / np.max(np.abs(ref["f_gamma"]))),
-                "hess_normwise": float(np.max(np.abs(H - ref["H"])) / np.max(np.abs(ref["H"]))),
-                "hess_max_abs": float(np.max(np.abs(H - ref["H"]))),
-            }
+            def errs(e, fr, fg, HH):
+                return {
+                    "energy_rel": abs(e - ref["E"]) / abs(ref["E"]),
+                    "f_rho_normwise": float(np.max(np.abs(fr - ref["f_rho"])) / np.max(np.abs(ref["f_rho"]))),
+                    "f_gamma_normwise": float(np.max(np.abs(fg - ref["f_gamma"])) / np.max(np.abs(ref["f_gamma"]))),
+                    "hess_normwise": float(np.max(np.abs(HH - ref["H"])) / np.max(np.abs(ref["H"]))),
+                    "hess_max_abs": float(np.max(np.abs(HH - ref["H"]))),
+                }
+            out["errors_vs_oracle"] = errs(energy.item(), f_rho.cpu().numpy(), f_gamma.cpu().numpy(), H)
+            if cmp is not None:
+                out[f"vs_{args.compare}"]["errors_vs_oracle"] = errs(cmp["energy"], cmp["f_rho"],
+                                                                      cmp["f_gamma"], cmp["hess"])
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
