@@ -92,13 +92,68 @@ def cpu_baseline(p, budget_s=30.0):
                        f"full pair-integral pass)"), None
 
 
+def bench_batch(args, torch, np, inputs, vv10):
+    """64 molecules of uneven size in one graph launch per step."""
+    sizes = inputs.random_cluster_sizes(64, seed=1004)
+    probs = []
+    for m, k in enumerate(sizes):
+        probs.append(inputs.make_problem(k, 1500, 2000 + m))
+        if (m + 1) % 8 == 0:
+            log(f"generated {m + 1}/64 molecules")
+    pair_pert = float(sum(float(p.n_grid) ** 2 * p.n_pert for p in probs))
+    log(f"batch: {sum(p.n_grid for p in probs)} points, {pair_pert:.3e} pair*pert")
+    with vv10.Batch(probs, prec=args.prec, tiles="auto") as b:
+        for k in range(args.warmup):
+            b.run()
+            torch.cuda.synchronize()
+            log(f"warmup {k + 1}/{args.warmup} done")
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            b.run()
+            torch.cuda.synchronize()
+            log(f"step {k + 1}/{args.steps} done")
+        dt = (time.perf_counter() - t0) / args.steps
+        n_items, n_wg = b.info()
+        energies = b.energy.cpu().numpy()
+        blocks = [h.cpu().numpy() for h in b.blocks()]
+    out = {
+        "metric": "VV10 Hessian grid-pair\u00b7perturbation/s, mixed vs FP64, at stated err; p99 latency",
+        "value": pair_pert / dt, "unit": "pair*pert/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f32+f64"}[args.prec],
+        "data": "synthetic",
+        "config": {"workload": "batch64", "n_mol": len(probs), "waters": sizes, "n_pa": 1500,
+                   "precision": args.prec, "work_items": n_items, "persistent_workgroups": n_wg},
+        "roofline": None, "cpu_baseline": None,
+    }
+    # per-molecule check against the oracle on the smallest molecules
+    if not args.no_cpu_baseline:
+        import oracle
+        order = np.argsort([p.n_grid for p in probs])[:3]
+        errs = []
+        for m in order:
+            p = probs[m]
+            g, gx = oracle.problem_inputs(p)
+            H0, _ = oracle.hessian_terms(p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g,
+                                         p.b, p.C, p.rho_x, gx)
+            e0, _, _ = oracle.energy_potential(p.coords, p.weights, p.rho, g, p.b, p.C)
+            errs.append({"mol": int(m), "n_grid": p.n_grid,
+                         "energy_rel": abs(energies[m] - e0) / abs(e0),
+                         "hess_max_abs": float(np.max(np.abs(blocks[m] - H0)))})
+        out["errors_vs_oracle"] = errs
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="water_hexamer",
-                    choices=["water_dimer", "water_hexamer", "water_20mer"])
+                    choices=["water_dimer", "water_hexamer", "water_20mer", "batch64"],
+                    help="batch64: 64 random clusters of 1-30 waters, 1500 points/atom, "
+                         "one graph launch per step")
     ap.add_argument("--prec", default="bf16x3", choices=["fp64", "fp32", "bf16x3"],
                     help="arithmetic of the headline path (default: split-BF16 mixed)")
     ap.add_argument("--compare", default="fp64", choices=["fp64", "fp32", "bf16x3", "none"],
@@ -123,8 +178,13 @@ def main():
     vv10.load()
     prec = vv10.PRECISIONS[args.prec]
 
+    if args.workload == "batch64":
+        return bench_batch(args, torch, np, inputs, vv10)
+
+    from paper_2208_14639_amd import autotune
     p = inputs.make_workload(args.workload)
     n, na, P = p.n_grid, p.n_atom, p.n_pert
+    tuned = {name: autotune.lookup(n, na, name) for name in ("fp64", "fp32", "bf16x3")}
     log(f"workload {args.workload}: N={n} atoms={na} P={P} prec={args.prec}")
     f64 = lambda a: torch.as_tensor(a, dtype=torch.float64).to(dev).contiguous()
     coords, w, rho, grad = f64(p.coords), f64(p.weights), f64(p.rho), f64(p.grad_rho)
@@ -148,6 +208,9 @@ def main():
     def step(prec=prec, hess=hess, gradient=gradient, energy=energy, f_rho=f_rho, f_gamma=f_gamma):
         h = vv10.vv10_prepare(p.b, p.C, n, na, coords, w, atom_of, rho, grad, prec, stream)
         try:
+            tiles = tuned[vv10._prec_name(prec)]
+            if tiles is not None:
+                vv10.vv10_set_tiles(h, *tiles)
             vv10.vv10_set_timing(h, True)
             vv10.vv10_energy_potential(h, energy, f_rho, f_gamma)
             st_e = vv10.vv10_stage_times(h)
@@ -200,7 +263,8 @@ def main():
         "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f32+f64"}[args.prec],
         "data": "synthetic",
         "config": {"workload": args.workload, "n_grid": n, "n_atom": na, "n_pert": P,
-                   "precision": args.prec, "b": p.b, "C": p.C, "seed": p.seed},
+                   "precision": args.prec, "b": p.b, "C": p.C, "seed": p.seed,
+                   "tiles": tuned[args.prec] or "automatic"},
         "roofline": roofline,
         "stage_ms": stage_ms,
         "pair_kernel": {"pairs_per_s": pair_rate,

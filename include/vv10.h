@@ -157,6 +157,69 @@ vv10_status vv10_set_timing(vv10_plan *plan, int32_t enable);
  * (ms NULL), VV10_E_HIP. */
 vv10_status vv10_stage_times(vv10_plan *plan, double *ms);
 
+/* Tile-shape overrides for a plan (0 = the library's automatic choice):
+ *  jsplit   number of j splits of the perturbation contraction;
+ *  bgroups  number of atom groups the grid-term pass splits its sums into.
+ * Set before the plan's first vv10_hessian_terms (the workspace is sized by
+ * them); values are clamped to the valid range.  Used by the autotuner.
+ * Errors: VV10_E_STATE (NULL plan, or workspace already built), VV10_E_ARG. */
+typedef struct {
+    int32_t jsplit;
+    int32_t bgroups;
+} vv10_tiles;
+vv10_status vv10_set_tiles(vv10_plan *plan, const vv10_tiles *tiles);
+
+/* The tile shape a plan uses (after the overrides and clamping); builds the
+ * workspace if it does not exist yet.  tiles is HOST memory.
+ * Errors: VV10_E_STATE (NULL plan), VV10_E_ARG (tiles NULL), VV10_E_OOM. */
+vv10_status vv10_get_tiles(vv10_plan *plan, vv10_tiles *tiles);
+
+/* ------------------------------------------------------------------------ */
+/* Batches: many molecules (grids) of uneven size evaluated together.        */
+/* ------------------------------------------------------------------------ */
+typedef struct vv10_batch vv10_batch;
+
+/*
+ * vv10_batch_create -- prepare n_mol grids stored back to back.
+ *  grid_off  HOST [n_mol + 1], nondecreasing, grid_off[0] = 0: molecule m owns
+ *            points [grid_off[m], grid_off[m+1]) of coords, weights, atom_of,
+ *            rho and grad_rho (each laid out as for vv10_prepare).
+ *  atom_off  HOST [n_mol + 1]: molecule m has atom_off[m+1] - atom_off[m] >= 1
+ *            atoms; atom_of holds molecule-local atom indices.
+ *  tiles     HOST [n_mol] tile overrides, or NULL for automatic choices.
+ * Validates every molecule as vv10_prepare does (one stream synchronisation
+ * per molecule) and allocates every workspace.  Errors as vv10_prepare.
+ */
+vv10_status vv10_batch_create(const vv10_params *params, int32_t n_mol, const int64_t *grid_off,
+                              const int32_t *atom_off, const double *coords,
+                              const double *weights, const int32_t *atom_of, const double *rho,
+                              const double *grad_rho, vv10_precision prec,
+                              const vv10_tiles *tiles, hipStream_t stream, vv10_batch **out);
+
+/*
+ * vv10_batch_run -- energies and Hessian terms of every molecule.
+ *  rho_x       molecule m's [3 n_atom_m][N_m] block, blocks back to back.
+ *  grad_rho_x  molecule m's [3 n_atom_m][N_m][3] block, blocks back to back.
+ *  energy      [n_mol] VV10 energies.
+ *  hess        molecule m's [3 n_atom_m][3 n_atom_m] block, blocks back to back.
+ * The whole evaluation is one HIP graph: the per-molecule stages of all
+ * molecules run as independent branches around a single persistent
+ * contraction kernel that pulls (molecule, tile) work items, largest first.
+ * The graph is captured on the first call and replayed while the four
+ * pointers stay the same.  Asynchronous on the batch's stream.
+ * Each molecule's results equal those of vv10_hessian_terms on the same
+ * grid with the same tiles (same kernels, same reduction order).
+ * Errors: VV10_E_ARG, VV10_E_STATE, VV10_E_HIP.
+ */
+vv10_status vv10_batch_run(vv10_batch *batch, const double *rho_x, const double *grad_rho_x,
+                           double *energy, double *hess);
+
+/* Work items and persistent workgroups of the batch's contraction. */
+vv10_status vv10_batch_info(const vv10_batch *batch, int64_t *n_items, int32_t *n_workgroups);
+
+/* Destroy a batch (waits for its stream); NULL is accepted. */
+void vv10_batch_destroy(vv10_batch *batch);
+
 /* Device bytes a plan for this size holds once vv10_hessian_terms has run
  * (an upper bound; vv10_energy_potential alone needs less). */
 size_t vv10_footprint_bytes(int64_t n_grid, int32_t n_atom, vv10_precision prec);

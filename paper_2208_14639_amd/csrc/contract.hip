@@ -45,17 +45,23 @@ namespace {
 constexpr int kJC = 32;   // j points per LDS stage
 
 template <int NCB>
-__global__ __launch_bounds__(256, 2) void k_contract_f64(
-    int64_t npad, int64_t jlen, int32_t Pp, const double4 *__restrict__ P0,
-    const double4 *__restrict__ P1, const double *__restrict__ X, double *__restrict__ Yout) {
+constexpr int smem_f64() { return 2 * kJC * (int)sizeof(double4) + kJC * 2 * NCB * 16 * (int)sizeof(double); }
+
+template <int NCB>
+__device__ __forceinline__ void tile_f64(int64_t npad, int64_t jlen, int32_t Pp,
+                                         const double4 *__restrict__ P0,
+                                         const double4 *__restrict__ P1,
+                                         const double *__restrict__ X, double *__restrict__ Yout,
+                                         int64_t itile, int grp, int split, char *smem) {
     constexpr int NC = NCB * 16;
-    __shared__ double4 sA[kJC], sB[kJC];
-    __shared__ __attribute__((aligned(16))) double sX[kJC * 2 * NC];
+    double4 *sA = reinterpret_cast<double4 *>(smem);
+    double4 *sB = sA + kJC;
+    double *sX = reinterpret_cast<double *>(sB + kJC);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m = lane & 15, kq = lane >> 4;
-    const int64_t ibase = (int64_t)blockIdx.x * 64 + wave * 16;
-    const int col0 = blockIdx.y * NC;
-    const int64_t jbeg = (int64_t)blockIdx.z * jlen;
+    const int64_t ibase = itile * 64 + wave * 16;
+    const int col0 = grp * NC;
+    const int64_t jbeg = (int64_t)split * jlen;
     const int64_t jend = min(npad, jbeg + jlen);
     const double4 a0 = P0[ibase + m], a1 = P1[ibase + m];
     const double ci = a1.z;
@@ -116,7 +122,7 @@ __global__ __launch_bounds__(256, 2) void k_contract_f64(
     }
     // D layout of v_mfma_f64_16x16x4 (measured on gfx950): item r of lane l
     // holds row 4 r + l/16, column l%16
-    double *Yb = Yout + (int64_t)blockIdx.z * npad * 2 * Pp;
+    double *Yb = Yout + (int64_t)split * npad * 2 * Pp;
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
@@ -131,17 +137,23 @@ __global__ __launch_bounds__(256, 2) void k_contract_f64(
 // FP32 MFMA
 // ---------------------------------------------------------------------------
 template <int NCB>
-__global__ __launch_bounds__(256, 2) void k_contract_f32(
-    int64_t npad, int64_t jlen, int32_t Pp, const float4 *__restrict__ P0,
-    const float4 *__restrict__ P1, const float *__restrict__ X, float *__restrict__ Yout) {
+constexpr int smem_f32() { return 2 * kJC * (int)sizeof(float4) + kJC * 2 * NCB * 16 * (int)sizeof(float); }
+
+template <int NCB>
+__device__ __forceinline__ void tile_f32(int64_t npad, int64_t jlen, int32_t Pp,
+                                         const float4 *__restrict__ P0,
+                                         const float4 *__restrict__ P1,
+                                         const float *__restrict__ X, float *__restrict__ Yout,
+                                         int64_t itile, int grp, int split, char *smem) {
     constexpr int NC = NCB * 16;
-    __shared__ float4 sA[kJC], sB[kJC];
-    __shared__ __attribute__((aligned(16))) float sX[kJC * 2 * NC];
+    float4 *sA = reinterpret_cast<float4 *>(smem);
+    float4 *sB = sA + kJC;
+    float *sX = reinterpret_cast<float *>(sB + kJC);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m = lane & 15, kq = lane >> 4;
-    const int64_t ibase = (int64_t)blockIdx.x * 64 + wave * 16;
-    const int col0 = blockIdx.y * NC;
-    const int64_t jbeg = (int64_t)blockIdx.z * jlen;
+    const int64_t ibase = itile * 64 + wave * 16;
+    const int col0 = grp * NC;
+    const int64_t jbeg = (int64_t)split * jlen;
     const int64_t jend = min(npad, jbeg + jlen);
     const float4 a0 = P0[ibase + m], a1 = P1[ibase + m];
     const float ci = a1.z;
@@ -203,7 +215,7 @@ __global__ __launch_bounds__(256, 2) void k_contract_f32(
     }
     // D layout of the FP32 MFMAs (measured on gfx950): item r of lane l holds
     // row 4 (l/16) + r, column l%16
-    float *Yb = Yout + (int64_t)blockIdx.z * npad * 2 * Pp;
+    float *Yb = Yout + (int64_t)split * npad * 2 * Pp;
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
@@ -288,19 +300,27 @@ __device__ __forceinline__ Aops form_A(const float4 a0, const float4 a1, const f
 //    fixed MFMA/VALU interleave, staging point data through LDS or forcing
 //    three waves per SIMD were all slower on the 20-water grid).
 template <int NCB>
-__global__ __launch_bounds__(256, 2) void k_contract_bf16x3(
-    int64_t npad, int64_t jlen, int32_t Pp, const float4 *__restrict__ P0,
-    const float4 *__restrict__ P1, const bf16x8 *__restrict__ Xhi,
-    const bf16x8 *__restrict__ Xlo, float *__restrict__ Yout) {
+constexpr int smem_bf16x3() { return 2 * 2 * NCB * 16 * 4 * (int)sizeof(bf16x8); }
+
+template <int NCB>
+__device__ __forceinline__ void tile_bf16x3(int64_t npad, int64_t jlen, int32_t Pp,
+                                            const float4 *__restrict__ P0,
+                                            const float4 *__restrict__ P1,
+                                            const bf16x8 *__restrict__ Xhi,
+                                            const bf16x8 *__restrict__ Xlo,
+                                            float *__restrict__ Yout, int64_t itile, int grp,
+                                            int split, char *smem) {
     constexpr int NC = NCB * 16;
     constexpr int UNITS = NC * 4;                       // 8-bf16 units per block and array
     constexpr int PER = (UNITS + 255) / 256;            // units per thread and array
-    __shared__ bf16x8 sH[2][UNITS], sL[2][UNITS];      // [buffer][col][g]
+    typedef bf16x8 Buf[UNITS];
+    Buf *sH = reinterpret_cast<Buf *>(smem);            // [buffer][col][g]
+    Buf *sL = sH + 2;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m = lane & 15, g = lane >> 4;
-    const int64_t ibase = (int64_t)blockIdx.x * 64 + wave * 16;
-    const int col0 = blockIdx.y * NC;
-    const int64_t jbeg = (int64_t)blockIdx.z * jlen;
+    const int64_t ibase = itile * 64 + wave * 16;
+    const int col0 = grp * NC;
+    const int64_t jbeg = (int64_t)split * jlen;
     const int64_t jend = min(npad, jbeg + jlen);
     const float4 a0 = P0[ibase + m], a1 = P1[ibase + m];
     v4f accp[NCB], accq[NCB];
@@ -371,7 +391,7 @@ __global__ __launch_bounds__(256, 2) void k_contract_bf16x3(
         __syncthreads();
         buf ^= 1;
     }
-    float *Yb = Yout + (int64_t)blockIdx.z * npad * 2 * Pp;
+    float *Yb = Yout + (int64_t)split * npad * 2 * Pp;
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
@@ -380,6 +400,39 @@ __global__ __launch_bounds__(256, 2) void k_contract_bf16x3(
             Yb[(row * 2 + 0) * Pp + col0 + cb * 16 + m] = accp[cb][r];
             Yb[(row * 2 + 1) * Pp + col0 + cb * 16 + m] = accq[cb][r];
         }
+}
+
+// One workgroup per (i tile, column group, j split): blockIdx = (tile, group, split).
+template <int NCB>
+__global__ __launch_bounds__(256, 2) void k_contract_f64(int64_t npad, int64_t jlen, int32_t Pp,
+                                                         const double4 *__restrict__ P0,
+                                                         const double4 *__restrict__ P1,
+                                                         const double *__restrict__ X,
+                                                         double *__restrict__ Yout) {
+    __shared__ __attribute__((aligned(16))) char smem[smem_f64<NCB>()];
+    tile_f64<NCB>(npad, jlen, Pp, P0, P1, X, Yout, blockIdx.x, blockIdx.y, blockIdx.z, smem);
+}
+
+template <int NCB>
+__global__ __launch_bounds__(256, 2) void k_contract_f32(int64_t npad, int64_t jlen, int32_t Pp,
+                                                         const float4 *__restrict__ P0,
+                                                         const float4 *__restrict__ P1,
+                                                         const float *__restrict__ X,
+                                                         float *__restrict__ Yout) {
+    __shared__ __attribute__((aligned(16))) char smem[smem_f32<NCB>()];
+    tile_f32<NCB>(npad, jlen, Pp, P0, P1, X, Yout, blockIdx.x, blockIdx.y, blockIdx.z, smem);
+}
+
+template <int NCB>
+__global__ __launch_bounds__(256, 2) void k_contract_bf16x3(int64_t npad, int64_t jlen, int32_t Pp,
+                                                            const float4 *__restrict__ P0,
+                                                            const float4 *__restrict__ P1,
+                                                            const bf16x8 *__restrict__ Xhi,
+                                                            const bf16x8 *__restrict__ Xlo,
+                                                            float *__restrict__ Yout) {
+    __shared__ __attribute__((aligned(16))) char smem[smem_bf16x3<NCB>()];
+    tile_bf16x3<NCB>(npad, jlen, Pp, P0, P1, Xhi, Xlo, Yout, blockIdx.x, blockIdx.y, blockIdx.z,
+                     smem);
 }
 
 template <int NCB>
@@ -446,6 +499,79 @@ auto dispatch_ncb(int ncb, F &&f) -> decltype(f(std::integral_constant<int, 1>{}
     }
 }
 
+// ---------------------------------------------------------------------------
+// Persistent batched contraction: a fixed grid of workgroups pulls work items
+// (molecule, i tile, column group, j split) from an integer counter, largest
+// first.  Every item writes its own partial-output slab, so the results do
+// not depend on which workgroup ran which item.
+// ---------------------------------------------------------------------------
+template <int PREC>
+struct PersistentTraits;
+template <>
+struct PersistentTraits<VV10_FP64> {
+    static constexpr int kMaxNcb = 8;
+    static constexpr int kSmem = smem_f64<8>();
+};
+template <>
+struct PersistentTraits<VV10_MIXED_FP32> {
+    static constexpr int kMaxNcb = 12;
+    static constexpr int kSmem = smem_f32<12>();
+};
+template <>
+struct PersistentTraits<VV10_MIXED_BF16X3> {
+    static constexpr int kMaxNcb = 12;
+    static constexpr int kSmem = smem_bf16x3<12>();
+};
+
+template <int PREC, int NCB>
+__device__ __forceinline__ void run_item(const BatchMol &d, const BatchItem &it, char *smem) {
+    if constexpr (PREC == VV10_FP64) {
+        tile_f64<NCB>(d.npad, d.jlen, d.Pp, static_cast<const double4 *>(d.P0),
+                      static_cast<const double4 *>(d.P1), static_cast<const double *>(d.X),
+                      static_cast<double *>(d.Ypart), it.itile, it.grp, it.split, smem);
+    } else if constexpr (PREC == VV10_MIXED_FP32) {
+        tile_f32<NCB>(d.npad, d.jlen, d.Pp, static_cast<const float4 *>(d.P0),
+                      static_cast<const float4 *>(d.P1), static_cast<const float *>(d.X),
+                      static_cast<float *>(d.Ypart), it.itile, it.grp, it.split, smem);
+    } else {
+        const bf16x8 *xh = static_cast<const bf16x8 *>(d.X);
+        tile_bf16x3<NCB>(d.npad, d.jlen, d.Pp, static_cast<const float4 *>(d.P0),
+                         static_cast<const float4 *>(d.P1), xh, xh + d.npad * d.Pp * 2 / 8,
+                         static_cast<float *>(d.Ypart), it.itile, it.grp, it.split, smem);
+    }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(256, 2) void k_contract_persistent(const BatchMol *__restrict__ mols,
+                                                                const BatchItem *__restrict__ items,
+                                                                int32_t n_items,
+                                                                int32_t *__restrict__ counter) {
+    __shared__ __attribute__((aligned(16))) char smem[PersistentTraits<PREC>::kSmem];
+    __shared__ int32_t next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+        __syncthreads();
+        const int32_t k = next;
+        __syncthreads();
+        if (k >= n_items) break;          // every workgroup leaves once the list is drained
+        const BatchItem it = items[k];
+        const BatchMol d = mols[it.mol];
+        switch (d.ncb) {
+#define VV10_CASE(c) \
+    case c:          \
+        if constexpr (c <= PersistentTraits<PREC>::kMaxNcb) run_item<PREC, c>(d, it, smem); \
+        break;
+            VV10_CASE(1) VV10_CASE(2) VV10_CASE(3) VV10_CASE(4) VV10_CASE(5) VV10_CASE(6)
+            VV10_CASE(7) VV10_CASE(8) VV10_CASE(9) VV10_CASE(10) VV10_CASE(11) VV10_CASE(12)
+#undef VV10_CASE
+            default: break;
+        }
+        __syncthreads();                   // LDS is reused by the next item
+    }
+}
+
+__global__ void k_zero_counter(int32_t *c) { *c = 0; }
+
 }  // namespace
 
 int contract_blocks_per_cu(vv10_precision prec, int ncb) {
@@ -455,6 +581,39 @@ int contract_blocks_per_cu(vv10_precision prec, int ncb) {
 hipError_t launch_contract(vv10_plan *p) {
     if (p->ws.ncb < 1 || p->ws.ncb > max_ncb(p->prec)) return hipErrorInvalidValue;
     return dispatch_ncb(p->ws.ncb, [&](auto c) { return run<decltype(c)::value>(p); });
+}
+
+}  // namespace vv10
+
+namespace vv10 {
+
+int persistent_blocks_per_cu(vv10_precision prec) {
+    int nb = 0;
+    hipError_t e;
+    if (prec == VV10_FP64)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_contract_persistent<VV10_FP64>, 256, 0);
+    else if (prec == VV10_MIXED_FP32)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_contract_persistent<VV10_MIXED_FP32>, 256, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_contract_persistent<VV10_MIXED_BF16X3>, 256, 0);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return nb;
+}
+
+hipError_t launch_contract_persistent(vv10_precision prec, const BatchMol *mols,
+                                      const BatchItem *items, int32_t n_items, int32_t *counter,
+                                      int n_blocks, hipStream_t stream) {
+    k_zero_counter<<<1, 1, 0, stream>>>(counter);
+    if (prec == VV10_FP64)
+        k_contract_persistent<VV10_FP64><<<n_blocks, 256, 0, stream>>>(mols, items, n_items, counter);
+    else if (prec == VV10_MIXED_FP32)
+        k_contract_persistent<VV10_MIXED_FP32><<<n_blocks, 256, 0, stream>>>(mols, items, n_items, counter);
+    else
+        k_contract_persistent<VV10_MIXED_BF16X3><<<n_blocks, 256, 0, stream>>>(mols, items, n_items, counter);
+    return hipGetLastError();
 }
 
 }  // namespace vv10

@@ -13,7 +13,8 @@ using vv10::Workspace;
 namespace vv10 {
 
 void plan_workspace_shape(int64_t npad, int32_t n_atom, int32_t ntiles, int num_cu,
-                          vv10_precision prec, Workspace &ws) {
+                          vv10_precision prec, Workspace &ws, int32_t jsplit_override,
+                          int32_t bgroups_override) {
     ws.P = 3 * n_atom;
     const int ncb_total = (ws.P + 15) / 16;
     const int cap = max_ncb(prec);
@@ -41,12 +42,17 @@ void plan_workspace_shape(int64_t npad, int32_t n_atom, int32_t ntiles, int num_
             ws.jsplit = S;
         }
     }
+    if (jsplit_override > 0) {
+        const int max_split = (int)std::max<int64_t>(1, npad / 256);
+        ws.jsplit = std::max(min_split, std::min(jsplit_override, max_split));
+    }
     ws.jlen = ((npad / ws.jsplit + 31) / 32) * 32;
     while ((ws.jsplit - 1) * ws.jlen >= npad) --ws.jsplit;   // no empty split
     const int tiles = (ws.Pp + 63) / 64;
     ws.gsplit = (int)std::max<int64_t>(1, std::min<int64_t>((1024 + tiles * tiles - 1) / (tiles * tiles),
                                                              std::max<int64_t>(1, npad / 64)));
     ws.bgroups = std::max(1, std::min<int>(n_atom, (8192 + std::max(ntiles, 1) - 1) / std::max(ntiles, 1)));
+    if (bgroups_override > 0) ws.bgroups = std::min<int>(n_atom, bgroups_override);
 }
 
 size_t workspace_bytes(int64_t npad, int32_t n_atom, int32_t ntiles, vv10_precision prec,
@@ -152,10 +158,13 @@ bool injected_alloc_failure() {
     return --countdown == 0;
 }
 
-vv10_status ensure_workspace(vv10_plan *p) {
+}  // namespace
+
+vv10_status vv10::ensure_workspace(vv10_plan *p) {
     if (p->ws.X) return VV10_OK;
     Workspace ws;
-    vv10::plan_workspace_shape(p->npad, p->n_atom, p->ntiles, p->num_cu, p->prec, ws);
+    vv10::plan_workspace_shape(p->npad, p->n_atom, p->ntiles, p->num_cu, p->prec, ws,
+                               p->tiles_jsplit, p->tiles_bgroups);
     if (injected_alloc_failure()) return VV10_E_OOM;
     const size_t ch = (size_t)p->npad * 2 * ws.Pp;
     hipError_t e = hipSuccess;
@@ -188,6 +197,8 @@ vv10_status ensure_workspace(vv10_plan *p) {
     p->ws = ws;
     return VV10_OK;
 }
+
+namespace {
 
 // Run one stage, bracketed by timing events when timing is enabled.
 template <typename Fn>
@@ -364,7 +375,7 @@ vv10_status vv10_hessian_terms(vv10_plan *p, int32_t n_pert, const double *rho_x
     if (!p) return VV10_E_STATE;
     if (p->failed) return VV10_E_STATE;
     if (n_pert != 3 * p->n_atom || !rho_x || !grad_rho_x || !hess) return VV10_E_ARG;
-    vv10_status st = ensure_workspace(p);
+    vv10_status st = vv10::ensure_workspace(p);
     if (st != VV10_OK) return st;
     // the grid-term pass also produces the pair integrals E, U, W, A, B, C
     hipError_t e = stage(p, VV10_STAGE_GRID, [&] { return vv10::launch_grid_terms(p); });
@@ -381,6 +392,24 @@ vv10_status vv10_hessian_terms(vv10_plan *p, int32_t n_pert, const double *rho_x
         (void)hipGetLastError();
         return VV10_E_HIP;
     }
+    return VV10_OK;
+}
+
+vv10_status vv10_set_tiles(vv10_plan *p, const vv10_tiles *t) {
+    if (!p || p->ws.X) return VV10_E_STATE;
+    if (!t || t->jsplit < 0 || t->bgroups < 0) return VV10_E_ARG;
+    p->tiles_jsplit = t->jsplit;
+    p->tiles_bgroups = t->bgroups;
+    return VV10_OK;
+}
+
+vv10_status vv10_get_tiles(vv10_plan *p, vv10_tiles *t) {
+    if (!p) return VV10_E_STATE;
+    if (!t) return VV10_E_ARG;
+    const vv10_status st = vv10::ensure_workspace(p);
+    if (st != VV10_OK) return st;
+    t->jsplit = p->ws.jsplit;
+    t->bgroups = p->ws.bgroups;
     return VV10_OK;
 }
 

@@ -88,6 +88,9 @@ struct vv10_plan {
     int32_t *flag = nullptr; // [1 + n_atom + 1] validation flag and segment starts
     size_t base_bytes = 0;
 
+    // tile overrides (vv10_set_tiles); 0 = automatic
+    int32_t tiles_jsplit = 0, tiles_bgroups = 0;
+
     // per-stage timing (vv10_set_timing)
     bool timing = false;
     hipEvent_t ev[2 * VV10_NUM_STAGES] = {};
@@ -97,6 +100,23 @@ struct vv10_plan {
 };
 
 namespace vv10 {
+
+// Contraction operands of one molecule of a batch (device copy).
+struct BatchMol {
+    int64_t npad, jlen;
+    int32_t Pp, ncb;
+    const void *P0, *P1;   // double4 (FP64) or float4 (mixed) point data
+    const void *X;         // (p, q) channels in the plan's layout
+    void *Ypart;           // [jsplit][npad][2][Pp] partial outputs
+};
+// One unit of work of the persistent contraction.
+struct BatchItem {
+    int32_t mol, grp, split, itile;
+};
+int persistent_blocks_per_cu(vv10_precision prec);
+hipError_t launch_contract_persistent(vv10_precision prec, const BatchMol *mols,
+                                      const BatchItem *items, int32_t n_items, int32_t *counter,
+                                      int n_blocks, hipStream_t stream);
 
 // j splits of the pair-integral kernel for a padded grid size.
 int pair_splits(int64_t npad);
@@ -115,7 +135,10 @@ hipError_t launch_assemble(vv10_plan *p, double *hess, double *grad, double *res
 
 // Layout decisions shared by the host code.
 void plan_workspace_shape(int64_t npad, int32_t n_atom, int32_t ntiles, int num_cu,
-                          vv10_precision prec, Workspace &ws);
+                          vv10_precision prec, Workspace &ws, int32_t jsplit_override = 0,
+                          int32_t bgroups_override = 0);
+// Allocate the Hessian workspace of a plan (no-op when it exists).
+vv10_status ensure_workspace(vv10_plan *p);
 size_t workspace_bytes(int64_t npad, int32_t n_atom, int32_t ntiles, vv10_precision prec,
                        const Workspace &ws);
 // Resident workgroups per CU of the contraction kernel for this shape (0 if unknown).

@@ -36,6 +36,10 @@ class vv10_params(ctypes.Structure):
     _fields_ = [("b", ctypes.c_double), ("C", ctypes.c_double)]
 
 
+class vv10_tiles(ctypes.Structure):
+    _fields_ = [("jsplit", ctypes.c_int32), ("bgroups", ctypes.c_int32)]
+
+
 class VV10Error(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -69,12 +73,29 @@ def load() -> ctypes.CDLL:
     lib.vv10_status_string.argtypes = [st]
     lib.vv10_version.restype = ctypes.c_char_p
     lib.vv10_version.argtypes = []
+    lib.vv10_set_tiles.restype = st
+    lib.vv10_set_tiles.argtypes = [P, ctypes.POINTER(vv10_tiles)]
+    lib.vv10_get_tiles.restype = st
+    lib.vv10_get_tiles.argtypes = [P, ctypes.POINTER(vv10_tiles)]
+    lib.vv10_batch_create.restype = st
+    lib.vv10_batch_create.argtypes = [ctypes.POINTER(vv10_params), i32, P, P, P, P, P, P, P, st, P, P,
+                                      ctypes.POINTER(P)]
+    lib.vv10_batch_run.restype = st
+    lib.vv10_batch_run.argtypes = [P, P, P, P, P]
+    lib.vv10_batch_info.restype = st
+    lib.vv10_batch_info.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i32)]
+    lib.vv10_batch_destroy.restype = None
+    lib.vv10_batch_destroy.argtypes = [P]
     lib.vv10_set_timing.restype = st
     lib.vv10_set_timing.argtypes = [P, i32]
     lib.vv10_stage_times.restype = st
     lib.vv10_stage_times.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
     _lib = lib
     return lib
+
+
+def _prec_name(prec: int) -> str:
+    return {v: k for k, v in PRECISIONS.items()}[prec]
 
 
 def _ptr(t):
@@ -138,6 +159,64 @@ def vv10_hessian_terms(plan: int, n_pert: int, rho_x, grad_rho_x, hess, grad=Non
         raise VV10Error(st, "vv10_hessian_terms")
 
 
+def vv10_set_tiles(plan: int, jsplit: int = 0, bgroups: int = 0) -> None:
+    t = vv10_tiles(jsplit, bgroups)
+    st = load().vv10_set_tiles(plan, ctypes.byref(t))
+    if st != VV10_OK:
+        raise VV10Error(st, "vv10_set_tiles")
+
+
+def vv10_get_tiles(plan: int):
+    t = vv10_tiles()
+    st = load().vv10_get_tiles(plan, ctypes.byref(t))
+    if st != VV10_OK:
+        raise VV10Error(st, "vv10_get_tiles")
+    return int(t.jsplit), int(t.bgroups)
+
+
+def vv10_batch_create(b: float, C: float, grid_off, atom_off, coords, weights, atom_of, rho,
+                      grad_rho, prec: int = VV10_FP64, tiles=None, stream=None) -> int:
+    """grid_off / atom_off: host int sequences of length n_mol + 1; tiles: a
+    list of (jsplit, bgroups) per molecule or None.  Returns the batch handle."""
+    import numpy as np
+    lib = load()
+    go = np.ascontiguousarray(grid_off, dtype=np.int64)
+    ao = np.ascontiguousarray(atom_off, dtype=np.int32)
+    n_mol = len(go) - 1
+    tl = None
+    if tiles is not None:
+        tl = (vv10_tiles * n_mol)(*[vv10_tiles(int(j), int(g)) for j, g in tiles])
+    prm = vv10_params(b, C)
+    out = ctypes.c_void_p()
+    st = lib.vv10_batch_create(ctypes.byref(prm), n_mol, go.ctypes.data, ao.ctypes.data,
+                               _ptr(coords), _ptr(weights), _ptr(atom_of), _ptr(rho),
+                               _ptr(grad_rho), prec, ctypes.cast(tl, ctypes.c_void_p) if tl else None,
+                               _stream(stream), ctypes.byref(out))
+    if st != VV10_OK:
+        raise VV10Error(st, "vv10_batch_create")
+    return out.value
+
+
+def vv10_batch_run(batch: int, rho_x, grad_rho_x, energy, hess) -> None:
+    st = load().vv10_batch_run(batch, _ptr(rho_x), _ptr(grad_rho_x), _ptr(energy), _ptr(hess))
+    if st != VV10_OK:
+        raise VV10Error(st, "vv10_batch_run")
+
+
+def vv10_batch_info(batch: int):
+    n_items = ctypes.c_int64()
+    n_wg = ctypes.c_int32()
+    st = load().vv10_batch_info(batch, ctypes.byref(n_items), ctypes.byref(n_wg))
+    if st != VV10_OK:
+        raise VV10Error(st, "vv10_batch_info")
+    return n_items.value, n_wg.value
+
+
+def vv10_batch_destroy(batch: int) -> None:
+    if batch:
+        load().vv10_batch_destroy(batch)
+
+
 def vv10_set_timing(plan: int, enable: bool = True) -> None:
     st = load().vv10_set_timing(plan, 1 if enable else 0)
     if st != VV10_OK:
@@ -165,7 +244,7 @@ class Plan:
     n_grid, n_atom, b, C (e.g. inputs.Problem); arrays are copied to the
     device as FP64/int32 tensors."""
 
-    def __init__(self, problem, prec="fp64", device="cuda", stream=None):
+    def __init__(self, problem, prec="fp64", device="cuda", stream=None, tiles=None):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -182,6 +261,12 @@ class Plan:
         self.handle = vv10_prepare(problem.b, problem.C, self.n, self.n_atom, self.coords,
                                    self.weights, self.atom_of, self.rho, self.grad_rho,
                                    self.prec, stream)
+        if tiles == "auto":
+            from . import autotune
+            tiles = autotune.lookup(self.n, self.n_atom, _prec_name(self.prec))
+        if tiles is not None:
+            vv10_set_tiles(self.handle, *tiles)
+        self.tiles = tiles
 
     def _dev(self, a):
         return self.torch.as_tensor(a, dtype=self.torch.float64).to(self.device).contiguous()
@@ -214,6 +299,79 @@ class Plan:
     def close(self):
         if self.handle:
             vv10_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class Batch:
+    """Many problems evaluated together (one HIP graph per run).
+
+    ``problems`` is a sequence of inputs.Problem-like objects with derivatives;
+    all must share b and C.  ``run()`` returns (energies [n_mol] tensor,
+    list of Hessian blocks [P_m, P_m])."""
+
+    def __init__(self, problems, prec="bf16x3", device="cuda", tiles=None, stream=None):
+        import numpy as np
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.prec = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+        self.problems = list(problems)
+        n = [int(p.n_grid) for p in self.problems]
+        na = [int(p.n_atom) for p in self.problems]
+        self.grid_off = np.concatenate([[0], np.cumsum(n)]).astype(np.int64)
+        self.atom_off = np.concatenate([[0], np.cumsum(na)]).astype(np.int32)
+        self.P = [3 * a for a in na]
+        cat = lambda f: np.concatenate([np.asarray(f(p)).reshape(-1) for p in self.problems])
+        d = lambda a, dt=torch.float64: torch.as_tensor(a, dtype=dt).to(self.device).contiguous()
+        self.coords = d(cat(lambda p: p.coords))
+        self.weights = d(cat(lambda p: p.weights))
+        self.atom_of = d(cat(lambda p: p.atom_of), torch.int32)
+        self.rho = d(cat(lambda p: p.rho))
+        self.grad_rho = d(cat(lambda p: p.grad_rho))
+        self.rho_x = d(cat(lambda p: p.rho_x))
+        self.grad_rho_x = d(cat(lambda p: p.grad_rho_x))
+        self.energy = torch.empty(len(self.problems), dtype=torch.float64, device=self.device)
+        self.hess = torch.empty(sum(P * P for P in self.P), dtype=torch.float64, device=self.device)
+        if tiles == "auto":
+            from . import autotune
+            cache = autotune.load_cache()
+            tiles = [autotune.lookup(int(p.n_grid), int(p.n_atom), _prec_name(self.prec), cache)
+                     or (0, 0) for p in self.problems]
+        self.tiles = tiles
+        b0 = self.problems[0]
+        self.handle = vv10_batch_create(b0.b, b0.C, self.grid_off, self.atom_off, self.coords,
+                                        self.weights, self.atom_of, self.rho, self.grad_rho,
+                                        self.prec, tiles, stream)
+
+    def run(self):
+        vv10_batch_run(self.handle, self.rho_x, self.grad_rho_x, self.energy, self.hess)
+        return self.energy, self.blocks()
+
+    def blocks(self):
+        out, off = [], 0
+        for P in self.P:
+            out.append(self.hess[off:off + P * P].view(P, P))
+            off += P * P
+        return out
+
+    def info(self):
+        return vv10_batch_info(self.handle)
+
+    def close(self):
+        if self.handle:
+            vv10_batch_destroy(self.handle)
             self.handle = 0
 
     def __del__(self):

@@ -1,0 +1,127 @@
+"""Batched evaluation (one HIP graph with a persistent contraction) against
+the single-molecule path and the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_util import normwise, relerr
+import oracle
+from paper_2208_14639_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def batch_problems(n_mol, seed, n_pa=(150, 400), waters=(1, 4)):
+    rng = np.random.default_rng(seed)
+    out = []
+    for m in range(n_mol):
+        k = int(rng.integers(waters[0], waters[1] + 1))
+        pa = int(rng.integers(n_pa[0], n_pa[1] + 1))
+        out.append(inputs.make_problem(k, pa, seed * 100 + m))
+    return out
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_batch_equals_single_molecule_path(torch, prec):
+    from paper_2208_14639_amd import vv10
+    probs = batch_problems(5, 77)
+    with vv10.Batch(probs, prec=prec) as b:
+        e, blocks = b.run()
+        torch.cuda.synchronize()
+        n_items, n_wg = b.info()
+        _say(prec, "items", n_items, "workgroups", n_wg)
+        e = e.cpu().numpy()
+        Hb = [h.cpu().numpy() for h in blocks]
+    bitwise = True
+    for m, p in enumerate(probs):
+        with vv10.Plan(p, prec=prec) as pl:
+            out = pl.hessian_terms(p.rho_x, p.grad_rho_x)
+            es, _, _ = pl.energy_potential()
+            torch.cuda.synchronize()
+            H = out["hess"].cpu().numpy()
+        bitwise &= bool(np.array_equal(H, Hb[m]))
+        assert normwise(Hb[m], H) < 1e-13, (m, normwise(Hb[m], H))
+        # the batch's energy comes from the Hessian-mode pair pass, the single
+        # path's from the energy pass: same sums, different split boundaries
+        assert relerr(e[m], es.item()) < (1e-13 if prec == "fp64" else 1e-7)
+    # same tile functions, same per-item output slabs, same reduction order
+    assert bitwise
+
+
+def test_batch_fp64_matches_oracle(torch):
+    from paper_2208_14639_amd import vv10
+    probs = batch_problems(4, 78, n_pa=(60, 120))
+    with vv10.Batch(probs, prec="fp64") as b:
+        e, blocks = b.run()
+        torch.cuda.synchronize()
+        e = e.cpu().numpy()
+        Hb = [h.cpu().numpy() for h in blocks]
+    for m, p in enumerate(probs):
+        g, gx = oracle.problem_inputs(p)
+        H0, _ = oracle.hessian_terms(p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b,
+                                     p.C, p.rho_x, gx)
+        e0, _, _ = oracle.energy_potential(p.coords, p.weights, p.rho, g, p.b, p.C)
+        assert normwise(Hb[m], H0) < 1e-10
+        assert relerr(e[m], e0) < 1e-10
+
+
+def test_batch_mixed_bounds_vs_oracle(torch):
+    from paper_2208_14639_amd import vv10
+    probs = batch_problems(4, 79, n_pa=(60, 120))
+    with vv10.Batch(probs, prec="bf16x3") as b:
+        e, blocks = b.run()
+        torch.cuda.synchronize()
+        e = e.cpu().numpy()
+        Hb = [h.cpu().numpy() for h in blocks]
+    for m, p in enumerate(probs):
+        g, gx = oracle.problem_inputs(p)
+        H0, _ = oracle.hessian_terms(p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b,
+                                     p.C, p.rho_x, gx)
+        e0, _, _ = oracle.energy_potential(p.coords, p.weights, p.rho, g, p.b, p.C)
+        assert np.max(np.abs(Hb[m] - H0)) <= 1e-5
+        assert relerr(e[m], e0) <= 1e-6
+
+
+def test_graph_replays_with_eager_work_between(torch):
+    """Each replay of the captured graph equals the first result, with eager
+    work (another plan's evaluation and host syncs) between the replays."""
+    from paper_2208_14639_amd import vv10
+    probs = batch_problems(3, 80)
+    other = inputs.make_problem(2, 100, 5)
+    with vv10.Batch(probs, prec="bf16x3") as b:
+        e0, blocks0 = b.run()
+        torch.cuda.synchronize()
+        ref_e = e0.clone()
+        ref_h = b.hess.clone()
+        for rep in range(4):
+            with vv10.Plan(other, prec="fp64") as pl:
+                pl.hessian_terms(other.rho_x, other.grad_rho_x)
+            b.energy.fill_(0.0)
+            b.hess.fill_(0.0)
+            torch.cuda.synchronize()
+            b.run()
+            torch.cuda.synchronize()
+            assert torch.equal(b.energy, ref_e), rep
+            assert torch.equal(b.hess, ref_h), rep
+
+
+def test_tiles_override_consistent(torch):
+    from paper_2208_14639_amd import vv10
+    p = inputs.make_problem(3, 400, 81)
+    with vv10.Plan(p, prec="bf16x3") as pl:
+        Ha = pl.hessian_terms(p.rho_x, p.grad_rho_x)["hess"].cpu().numpy()
+    with vv10.Plan(p, prec="bf16x3", tiles=(5, 2)) as pl:
+        Hb = pl.hessian_terms(p.rho_x, p.grad_rho_x)["hess"].cpu().numpy()
+    assert np.max(np.abs(Ha - Hb)) < 1e-6
