@@ -145,6 +145,12 @@ typedef enum {
     VV10_NUM_STAGES = 6
 } vv10_stage;
 
+/* Rebind the plan to another HIP stream: later calls enqueue on `stream`.
+ * The caller orders the new stream after the plan's earlier work (for
+ * example with an event); the plan must not have calls in flight on two
+ * streams at once.  Errors: VV10_E_STATE (NULL plan). */
+vv10_status vv10_set_stream(vv10_plan *plan, hipStream_t stream);
+
 /* Enable (1) or disable (0) per-stage timing: while enabled, every call
  * records a HIP event pair on the plan's stream around each stage it runs.
  * Errors: VV10_E_STATE (NULL plan), VV10_E_HIP (event creation failed). */

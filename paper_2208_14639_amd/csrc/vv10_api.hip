@@ -403,6 +403,12 @@ vv10_status vv10_set_tiles(vv10_plan *p, const vv10_tiles *t) {
     return VV10_OK;
 }
 
+vv10_status vv10_set_stream(vv10_plan *p, hipStream_t stream) {
+    if (!p) return VV10_E_STATE;
+    p->stream = stream;
+    return VV10_OK;
+}
+
 vv10_status vv10_get_tiles(vv10_plan *p, vv10_tiles *t) {
     if (!p) return VV10_E_STATE;
     if (!t) return VV10_E_ARG;

@@ -1,0 +1,369 @@
+"""Continuous-batching server for VV10 Hessian-term requests.
+
+A request names a molecule (grid, density and perturbed densities) and asks
+for its energy and Hessian terms.  The scheduler keeps up to `n_slots`
+requests in flight at once, each on its own HIP stream, and admits a
+waiting request as soon as a slot is free AND its device footprint fits in
+what is left of the HBM budget; requests that arrive while others run are
+admitted as slots and memory free up, so their work overlaps on the device.
+Admission is first-come first-served, except that a request that does not
+fit may be overtaken by later ones that do (bounded by `max_bypass`, after
+which the head of the queue waits for memory).  A request larger than the
+whole budget is rejected.
+
+Device state of a molecule (its plan, inputs and workspace) stays resident
+after its request completes, keyed by molecule id, and is reused by later
+requests for the same molecule; idle resident state is evicted least
+recently used when the budget needs room.
+
+The scheduler is independent of the device: `GpuExecutor` runs requests
+through the HIP library; `FakeExecutor` (for tests on machines without a
+GPU) computes them with the CPU oracle and completes each after a delay
+proportional to N^2 P.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import threading
+import time
+from concurrent.futures import Future
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    mol_id: str
+    problem: object                 # inputs.Problem with derivatives
+    arrival: float = 0.0            # seconds on the server clock
+    # filled by the server
+    admitted: float = None
+    finished: float = None
+    status: str = "queued"          # queued, running, done, failed, rejected, cancelled
+    error: str = None
+
+    @property
+    def pair_pert(self) -> float:
+        n = float(self.problem.n_grid)
+        return n * n * self.problem.n_pert
+
+    @property
+    def latency(self) -> float:
+        return None if self.finished is None else self.finished - self.arrival
+
+
+def percentile(values, q):
+    if not values:
+        return None
+    v = sorted(values)
+    k = (len(v) - 1) * q / 100.0
+    lo, hi = int(k), min(int(k) + 1, len(v) - 1)
+    return v[lo] + (v[hi] - v[lo]) * (k - lo)
+
+
+class Server:
+    """Scheduler core.  Drive it either with `run_until_idle()` (single
+    thread, arrivals pre-scheduled) or with `start()` / `submit()` from other
+    threads."""
+
+    def __init__(self, executor, budget_bytes: int, n_slots: int = 4, max_bypass: int = 8,
+                 clock=time.monotonic):
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.n_slots = int(n_slots)
+        self.max_bypass = int(max_bypass)
+        self.clock = clock
+        self.t0 = clock()
+        self.queue = collections.deque()
+        self.pending = []               # (arrival, request, future) not yet arrived
+        self.running = {}               # slot -> (request, handle, future)
+        self.resident = collections.OrderedDict()   # mol_id -> (bytes, state), LRU order
+        self.pinned = collections.Counter()         # mol_id -> running requests using it
+        self.used = 0
+        self.peak_used = 0
+        self.done = []
+        self.lock = threading.Lock()
+        self.bypassed = 0
+        self._thread = None
+        self._stop = False
+
+    # -- time ------------------------------------------------------------
+    def now(self) -> float:
+        return self.clock() - self.t0
+
+    # -- submission --------------------------------------------------------
+    def submit(self, req: Request, at: float = None) -> Future:
+        """Queue a request (at server time `at`, default now)."""
+        fut = Future()
+        with self.lock:
+            if at is None or at <= self.now():
+                req.arrival = self.now() if at is None else at
+                self.queue.append((req, fut))
+            else:
+                req.arrival = at
+                self.pending.append((at, req, fut))
+                self.pending.sort(key=lambda x: x[0])
+        return fut
+
+    def cancel(self, rid: int) -> bool:
+        with self.lock:
+            for k, (req, fut) in enumerate(self.queue):
+                if req.rid == rid:
+                    del self.queue[k]
+                    req.status = "cancelled"
+                    fut.cancel()
+                    return True
+        return False
+
+    # -- memory ------------------------------------------------------------
+    def _footprint(self, req) -> int:
+        if req.mol_id in self.resident:
+            return 0
+        return self.ex.footprint(req.problem)
+
+    def _make_room(self, need: int) -> bool:
+        """Evict idle resident molecules (LRU) until `need` bytes fit."""
+        while self.used + need > self.budget:
+            victim = next((m for m in self.resident if self.pinned[m] == 0), None)
+            if victim is None:
+                return False
+            nbytes, state = self.resident.pop(victim)
+            self.ex.release(state)
+            self.used -= nbytes
+        return True
+
+    def _admit_one(self) -> bool:
+        free = [s for s in range(self.n_slots) if s not in self.running]
+        if not free or not self.queue:
+            return False
+        for k, (req, fut) in enumerate(self.queue):
+            if k > 0 and self.bypassed >= self.max_bypass:
+                break
+            if self.pinned[req.mol_id] > 0:
+                continue                    # one request per molecule at a time (shared state)
+            total = self.ex.footprint(req.problem)
+            if total > self.budget:
+                del self.queue[k]
+                req.status = "rejected"
+                req.error = f"footprint {total} bytes exceeds the budget {self.budget}"
+                req.finished = self.now()
+                self.done.append(req)
+                fut.set_exception(MemoryError(req.error))
+                return True
+            need = self._footprint(req)
+            if not self._make_room(need):
+                continue
+            del self.queue[k]
+            self.bypassed = self.bypassed + 1 if k > 0 else 0
+            slot = free[0]
+            try:
+                if req.mol_id in self.resident:
+                    nbytes, state = self.resident.pop(req.mol_id)
+                    self.resident[req.mol_id] = (nbytes, state)     # most recently used
+                else:
+                    state = self.ex.load(req.mol_id, req.problem)
+                    self.resident[req.mol_id] = (need, state)
+                    self.used += need
+                    self.peak_used = max(self.peak_used, self.used)
+                self.pinned[req.mol_id] += 1
+                handle = self.ex.start(state, req.problem, slot)
+            except Exception as e:          # the request fails; the server goes on
+                self.pinned[req.mol_id] -= 1 if self.pinned[req.mol_id] > 0 else 0
+                req.status, req.error, req.finished = "failed", repr(e), self.now()
+                self.done.append(req)
+                fut.set_exception(e)
+                return True
+            req.admitted = self.now()
+            req.status = "running"
+            self.running[slot] = (req, handle, fut)
+            return True
+        return False
+
+    def _reap(self) -> int:
+        n = 0
+        for slot in list(self.running):
+            req, handle, fut = self.running[slot]
+            try:
+                ready = self.ex.poll(handle)
+                if not ready:
+                    continue
+                result = self.ex.result(handle)
+                req.status = "done"
+                fut.set_result(result)
+            except Exception as e:
+                req.status, req.error = "failed", repr(e)
+                fut.set_exception(e)
+            req.finished = self.now()
+            self.pinned[req.mol_id] -= 1
+            del self.running[slot]
+            self.done.append(req)
+            n += 1
+        return n
+
+    def step(self) -> bool:
+        """One scheduling round; returns True while work remains."""
+        with self.lock:
+            now = self.now()
+            while self.pending and self.pending[0][0] <= now:
+                _, req, fut = self.pending.pop(0)
+                self.queue.append((req, fut))
+            self._reap()
+            while self._admit_one():
+                pass
+            return bool(self.queue or self.running or self.pending)
+
+    def run_until_idle(self, poll_s: float = 2e-4, timeout_s: float = None):
+        start = self.clock()
+        while self.step():
+            if timeout_s is not None and self.clock() - start > timeout_s:
+                raise TimeoutError("server did not drain")
+            time.sleep(poll_s)
+
+    # -- background mode ------------------------------------------------------
+    def start(self, poll_s: float = 2e-4):
+        def loop():
+            while not self._stop:
+                if not self.step():
+                    time.sleep(poll_s * 5)
+                else:
+                    time.sleep(poll_s)
+        self._thread = threading.Thread(target=loop, daemon=True)
+        self._thread.start()
+
+    def stop(self):
+        self._stop = True
+        if self._thread:
+            self._thread.join()
+
+    def close(self):
+        with self.lock:
+            for _, (nbytes, state) in self.resident.items():
+                self.ex.release(state)
+            self.resident.clear()
+            self.used = 0
+
+    # -- statistics ------------------------------------------------------------
+    def stats(self, skip: int = 0) -> dict:
+        reqs = sorted((r for r in self.done if r.status == "done"), key=lambda r: r.rid)[skip:]
+        lat = [r.latency for r in reqs]
+        if not reqs:
+            return {"completed": 0}
+        t_first = min(r.arrival for r in reqs)
+        t_last = max(r.finished for r in reqs)
+        work = sum(r.pair_pert for r in reqs)
+        return {
+            "completed": len(reqs),
+            "failed": sum(1 for r in self.done if r.status == "failed"),
+            "rejected": sum(1 for r in self.done if r.status == "rejected"),
+            "p50_s": percentile(lat, 50),
+            "p99_s": percentile(lat, 99),
+            "mean_s": sum(lat) / len(lat),
+            "throughput_pair_pert_per_s": work / (t_last - t_first) if t_last > t_first else None,
+            "peak_bytes": self.peak_used,
+            "budget_bytes": self.budget,
+        }
+
+
+class GpuExecutor:
+    """Runs requests through the HIP library, one HIP stream per slot."""
+
+    def __init__(self, prec: str = "bf16x3", n_slots: int = 4, device: str = "cuda", tiles="auto"):
+        import torch
+        from . import vv10
+        self.torch, self.vv10 = torch, vv10
+        self.prec = prec
+        self.dev = torch.device(device)
+        self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(n_slots)]
+        self.load_stream = torch.cuda.Stream(device=self.dev)   # uploads and preparation
+        self.tiles = tiles
+
+    def footprint(self, problem) -> int:
+        n, na = int(problem.n_grid), int(problem.n_atom)
+        inputs = 8 * n * (3 + 1 + 1 + 3) + 4 * n + 8 * 3 * na * n * 4
+        return self.vv10.vv10_footprint_bytes(n, na, self.vv10.PRECISIONS[self.prec]) + inputs
+
+    def load(self, mol_id, problem):
+        torch = self.torch
+        with torch.cuda.stream(self.load_stream):
+            plan = self.vv10.Plan(problem, prec=self.prec, device=self.dev,
+                                  stream=self.load_stream, tiles=self.tiles)
+            rx = torch.as_tensor(problem.rho_x, dtype=torch.float64).to(self.dev).contiguous()
+            gx = torch.as_tensor(problem.grad_rho_x, dtype=torch.float64).to(self.dev).contiguous()
+        self.load_stream.synchronize()
+        return {"plan": plan, "rx": rx, "gx": gx}
+
+    def start(self, state, problem, slot):
+        torch, vv = self.torch, self.vv10
+        s = self.streams[slot]
+        plan = state["plan"]
+        P = 3 * plan.n_atom
+        with torch.cuda.stream(s):
+            e = torch.empty(1, dtype=torch.float64, device=self.dev)
+            H = torch.empty((P, P), dtype=torch.float64, device=self.dev)
+        # the plan's previous calls completed before this request was admitted
+        # (one request per molecule at a time), so it can move to this slot
+        vv.vv10_set_stream(plan.handle, s)
+        vv.vv10_energy_potential(plan.handle, e)
+        vv.vv10_hessian_terms(plan.handle, P, state["rx"], state["gx"], H)
+        done = torch.cuda.Event()
+        done.record(s)
+        return {"done": done, "e": e, "H": H}
+
+    def poll(self, handle) -> bool:
+        return handle["done"].query()
+
+    def result(self, handle):
+        handle["done"].synchronize()
+        return handle["e"].item(), handle["H"].cpu().numpy()
+
+    def release(self, state):
+        state["plan"].close()
+        state.clear()
+
+
+class FakeExecutor:
+    """CPU stand-in: results from the FP64 oracle, completion after
+    `seconds_per_pair_pert * N^2 P` of wall time, footprint from the same
+    formula the library uses, optional injected failures."""
+
+    def __init__(self, seconds_per_pair_pert: float = 1e-9, fail_mol=None, clock=time.monotonic):
+        self.spp = seconds_per_pair_pert
+        self.fail_mol = set(fail_mol or ())
+        self.clock = clock
+        self.active = 0
+        self.max_active = 0
+
+    def footprint(self, problem) -> int:
+        n, na = int(problem.n_grid), int(problem.n_atom)
+        return 8 * n * (20 + 8 * 3 * na)
+
+    def load(self, mol_id, problem):
+        if mol_id in self.fail_mol:
+            raise RuntimeError(f"injected load failure for {mol_id}")
+        return {"mol": mol_id}
+
+    def start(self, state, problem, slot):
+        import oracle
+        g, gx = oracle.problem_inputs(problem)
+        e, _, _ = oracle.energy_potential(problem.coords, problem.weights, problem.rho, g,
+                                          problem.b, problem.C)
+        H, _ = oracle.hessian_terms(problem.atom_of, problem.n_atom, problem.coords,
+                                    problem.weights, problem.rho, g, problem.b, problem.C,
+                                    problem.rho_x, gx)
+        n = float(problem.n_grid)
+        self.active += 1
+        self.max_active = max(self.max_active, self.active)
+        return {"t_done": self.clock() + self.spp * n * n * problem.n_pert, "res": (e, H)}
+
+    def poll(self, handle) -> bool:
+        ready = self.clock() >= handle["t_done"]
+        if ready and not handle.get("counted"):
+            handle["counted"] = True
+            self.active -= 1
+        return ready
+
+    def result(self, handle):
+        return handle["res"]
+
+    def release(self, state):
+        state.clear()

@@ -75,6 +75,8 @@ def load() -> ctypes.CDLL:
     lib.vv10_version.argtypes = []
     lib.vv10_set_tiles.restype = st
     lib.vv10_set_tiles.argtypes = [P, ctypes.POINTER(vv10_tiles)]
+    lib.vv10_set_stream.restype = st
+    lib.vv10_set_stream.argtypes = [P, P]
     lib.vv10_get_tiles.restype = st
     lib.vv10_get_tiles.argtypes = [P, ctypes.POINTER(vv10_tiles)]
     lib.vv10_batch_create.restype = st
@@ -164,6 +166,12 @@ def vv10_set_tiles(plan: int, jsplit: int = 0, bgroups: int = 0) -> None:
     st = load().vv10_set_tiles(plan, ctypes.byref(t))
     if st != VV10_OK:
         raise VV10Error(st, "vv10_set_tiles")
+
+
+def vv10_set_stream(plan: int, stream) -> None:
+    st = load().vv10_set_stream(plan, _stream(stream))
+    if st != VV10_OK:
+        raise VV10Error(st, "vv10_set_stream")
 
 
 def vv10_get_tiles(plan: int):
