@@ -230,9 +230,18 @@ void vv10_batch_destroy(vv10_batch *batch);
  * (an upper bound; vv10_energy_potential alone needs less). */
 size_t vv10_footprint_bytes(int64_t n_grid, int32_t n_atom, vv10_precision prec);
 
-/* Destroy a plan and free its device memory (NULL is accepted).  Waits for
- * the plan's stream to finish the plan's work first. */
+/* Destroy a plan (NULL is accepted).  Waits for the plan's stream to finish
+ * the plan's work, then returns its device memory to the library's
+ * per-device cache, from which later plans of similar sizes are served. */
 void vv10_destroy(vv10_plan *plan);
+
+/* Bytes of device memory held in the library's cache (freed plans' blocks
+ * kept for reuse), summed over devices. */
+size_t vv10_cached_bytes(void);
+
+/* Return every cached block to the HIP runtime (hipFree).  Blocks still
+ * owned by live plans are not affected.  Call with no library work in flight. */
+void vv10_release_cached(void);
 
 /* Static description of a status code. */
 const char *vv10_status_string(vv10_status s);

@@ -45,9 +45,9 @@ void destroy_batch(vv10_batch *b) {
     for (hipStream_t s : b->side)
         if (s) (void)hipStreamDestroy(s);
     if (b->cap) (void)hipStreamDestroy(b->cap);
-    if (b->d_mols) (void)hipFree(b->d_mols);
-    if (b->d_items) (void)hipFree(b->d_items);
-    if (b->d_counter) (void)hipFree(b->d_counter);
+    vv10::dev_free(b->d_mols);
+    vv10::dev_free(b->d_items);
+    vv10::dev_free(b->d_counter);
     delete b;
 }
 
@@ -172,9 +172,12 @@ vv10_status vv10_batch_create(const vv10_params *params, int32_t n_mol, const in
         if (b->n_items > INT32_MAX) st = VV10_E_ARG;
     }
     if (st == VV10_OK) {
-        hipError_t e = hipMalloc(&b->d_mols, mols.size() * sizeof(vv10::BatchMol));
-        if (e == hipSuccess) e = hipMalloc(&b->d_items, std::max<size_t>(1, items.size()) * sizeof(vv10::BatchItem));
-        if (e == hipSuccess) e = hipMalloc(&b->d_counter, sizeof(int32_t));
+        hipError_t e = vv10::dev_alloc(reinterpret_cast<void **>(&b->d_mols),
+                                       mols.size() * sizeof(vv10::BatchMol));
+        if (e == hipSuccess)
+            e = vv10::dev_alloc(reinterpret_cast<void **>(&b->d_items),
+                                std::max<size_t>(1, items.size()) * sizeof(vv10::BatchItem));
+        if (e == hipSuccess) e = vv10::dev_alloc(reinterpret_cast<void **>(&b->d_counter), sizeof(int32_t));
         if (e == hipSuccess)
             e = hipMemcpy(b->d_mols, mols.data(), mols.size() * sizeof(vv10::BatchMol), hipMemcpyHostToDevice);
         if (e == hipSuccess && !items.empty())

@@ -96,12 +96,10 @@ template <typename T>
 hipError_t dalloc(T **p, size_t count) {
     *p = nullptr;
     if (count == 0) count = 1;
-    return hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T));
+    return vv10::dev_alloc(reinterpret_cast<void **>(p), count * sizeof(T));
 }
 
-void dfree(void *ptr) {
-    if (ptr) (void)hipFree(ptr);
-}
+void dfree(void *ptr) { vv10::dev_free(ptr); }
 
 void free_workspace(Workspace &ws) {
     dfree(ws.X);
@@ -131,11 +129,7 @@ void free_plan(vv10_plan *p) {
     dfree(p->I);
     dfree(p->Ipart);
     dfree(p->atom_of);
-    dfree(p->d_seg);
-    dfree(p->d_tile_i0);
-    dfree(p->d_tile_n);
-    dfree(p->d_tile_atom);
-    dfree(p->d_tile_first);
+    dfree(p->d_meta);
     dfree(p->red);
     dfree(p->flag);
     delete p;
@@ -279,7 +273,6 @@ vv10_status vv10_prepare(const vv10_params *params, int64_t n_grid, int32_t n_at
     if (e == hipSuccess && vv10::pair_splits(npad) > 1)
         e = dalloc(&p->Ipart, (size_t)vv10::pair_splits(npad) * vv10::NI * npad);
     if (e == hipSuccess) e = dalloc(&p->atom_of, npad);
-    if (e == hipSuccess) e = dalloc(&p->d_seg, (size_t)n_atom + 1);
     if (e == hipSuccess) e = dalloc(&p->red, reduction_doubles(npad));
     if (e == hipSuccess) e = dalloc(&p->flag, (size_t)n_atom + 2);
     if (e != hipSuccess) {
@@ -322,33 +315,35 @@ vv10_status vv10_prepare(const vv10_params *params, int64_t n_grid, int32_t n_at
     }
     p->ntiles = (int32_t)p->tile_i0.size();
     p->tile_first[n_atom] = p->ntiles;
-    if (e == hipSuccess) e = dalloc(&p->d_tile_i0, (size_t)p->ntiles);
-    if (e == hipSuccess) e = dalloc(&p->d_tile_n, (size_t)p->ntiles);
-    if (e == hipSuccess) e = dalloc(&p->d_tile_atom, (size_t)p->ntiles);
-    if (e == hipSuccess) e = dalloc(&p->d_tile_first, (size_t)n_atom + 1);
+    // one host image and one copy for all grid metadata (the image lives in
+    // the plan, so the copy needs no synchronisation here)
+    auto align = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t o_seg = 0;
+    const size_t o_i0 = align(o_seg + p->seg.size() * sizeof(int64_t));
+    const size_t o_n = align(o_i0 + p->tile_i0.size() * sizeof(int32_t));
+    const size_t o_atom = align(o_n + p->tile_n.size() * sizeof(int32_t));
+    const size_t o_first = align(o_atom + p->tile_atom.size() * sizeof(int32_t));
+    const size_t meta_bytes = align(o_first + p->tile_first.size() * sizeof(int32_t));
+    p->h_meta.assign(meta_bytes, 0);
+    std::memcpy(p->h_meta.data() + o_seg, p->seg.data(), p->seg.size() * sizeof(int64_t));
+    std::memcpy(p->h_meta.data() + o_i0, p->tile_i0.data(), p->tile_i0.size() * sizeof(int32_t));
+    std::memcpy(p->h_meta.data() + o_n, p->tile_n.data(), p->tile_n.size() * sizeof(int32_t));
+    std::memcpy(p->h_meta.data() + o_atom, p->tile_atom.data(), p->tile_atom.size() * sizeof(int32_t));
+    std::memcpy(p->h_meta.data() + o_first, p->tile_first.data(), p->tile_first.size() * sizeof(int32_t));
+    if (e == hipSuccess) e = dalloc(&p->d_meta, meta_bytes);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(p->d_seg, p->seg.data(), p->seg.size() * sizeof(int64_t),
-                           hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(p->d_tile_i0, p->tile_i0.data(), p->tile_i0.size() * sizeof(int32_t),
-                           hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(p->d_tile_n, p->tile_n.data(), p->tile_n.size() * sizeof(int32_t),
-                           hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(p->d_tile_atom, p->tile_atom.data(), p->tile_atom.size() * sizeof(int32_t),
-                           hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(p->d_tile_first, p->tile_first.data(),
-                           p->tile_first.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream);
-    // the host vectors are read by the copies above: wait before returning
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        e = hipMemcpyAsync(p->d_meta, p->h_meta.data(), meta_bytes, hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) {
         vv10_status st = hip_status(e);
         (void)hipGetLastError();
         free_plan(p);
         return st;
     }
+    p->d_seg = reinterpret_cast<int64_t *>(p->d_meta + o_seg);
+    p->d_tile_i0 = reinterpret_cast<int32_t *>(p->d_meta + o_i0);
+    p->d_tile_n = reinterpret_cast<int32_t *>(p->d_meta + o_n);
+    p->d_tile_atom = reinterpret_cast<int32_t *>(p->d_meta + o_atom);
+    p->d_tile_first = reinterpret_cast<int32_t *>(p->d_meta + o_first);
     p->base_bytes = base_bytes(npad, n_atom, p->ntiles);
     *out = p;
     return VV10_OK;

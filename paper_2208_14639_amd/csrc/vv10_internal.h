@@ -82,6 +82,9 @@ struct vv10_plan {
     double *I = nullptr;     // [6][npad]
     double *Ipart = nullptr; // [pair_splits][6][npad] partial pair integrals
     int32_t *atom_of = nullptr;   // [npad], padding rows hold n_atom
+    // grid metadata, one device block (d_meta) holding the views below
+    char *d_meta = nullptr;
+    std::vector<char> h_meta;     // host image of d_meta (lives as long as the plan)
     int64_t *d_seg = nullptr;     // [n_atom + 1]
     int32_t *d_tile_i0 = nullptr, *d_tile_n = nullptr, *d_tile_atom = nullptr, *d_tile_first = nullptr;
     double *red = nullptr;   // reduction scratch
@@ -117,6 +120,12 @@ int persistent_blocks_per_cu(vv10_precision prec);
 hipError_t launch_contract_persistent(vv10_precision prec, const BatchMol *mols,
                                       const BatchItem *items, int32_t n_items, int32_t *counter,
                                       int n_blocks, hipStream_t stream);
+
+// Device allocations of the library (per-device caching allocator).
+hipError_t dev_alloc(void **ptr, size_t bytes);
+void dev_free(void *ptr);
+size_t dev_cached_bytes();
+void dev_release_cached();
 
 // j splits of the pair-integral kernel for a padded grid size.
 int pair_splits(int64_t npad);

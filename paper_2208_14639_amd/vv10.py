@@ -75,6 +75,10 @@ def load() -> ctypes.CDLL:
     lib.vv10_version.argtypes = []
     lib.vv10_set_tiles.restype = st
     lib.vv10_set_tiles.argtypes = [P, ctypes.POINTER(vv10_tiles)]
+    lib.vv10_cached_bytes.restype = ctypes.c_size_t
+    lib.vv10_cached_bytes.argtypes = []
+    lib.vv10_release_cached.restype = None
+    lib.vv10_release_cached.argtypes = []
     lib.vv10_set_stream.restype = st
     lib.vv10_set_stream.argtypes = [P, P]
     lib.vv10_get_tiles.restype = st
@@ -166,6 +170,14 @@ def vv10_set_tiles(plan: int, jsplit: int = 0, bgroups: int = 0) -> None:
     st = load().vv10_set_tiles(plan, ctypes.byref(t))
     if st != VV10_OK:
         raise VV10Error(st, "vv10_set_tiles")
+
+
+def vv10_cached_bytes() -> int:
+    return int(load().vv10_cached_bytes())
+
+
+def vv10_release_cached() -> None:
+    load().vv10_release_cached()
 
 
 def vv10_set_stream(plan: int, stream) -> None:
