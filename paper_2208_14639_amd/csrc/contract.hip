@@ -31,8 +31,15 @@
 //          lo = bf16(v - hi), and three products hi*hi + hi*lo + lo*hi are
 //          accumulated (relative error about 2^-16 per product).
 //
-// The mixed modes accumulate one j-split in FP32 and write FP32 partials,
-// which the assembly sums over splits in FP64.
+// The mixed modes carry the factor -3/2 of Phi in X (the perturbation
+// packing scales both channels), so their pair arithmetic forms K / (-3/2)
+// with r = 1 / (g g' s) in place of Phi.  Using 1/(g g') = s r and
+// 1/s = g g' r, each pair needs one reciprocal and
+//   A = r (1/g + 1/s),  A' = r (1/g' + 1/s),  Q = 2 r (1/s^2 + 1/(g g')),
+//   t1 = c_i Q - A',  t2 = c_j Q - A,
+//   K_pp = r - c_i A + c_j t1,  K_pq = R^2 t1,  K_qp = R^2 t2,  K_qq = R^4 Q.
+// They accumulate one j-split in FP32 and write FP32 partials, which the
+// assembly sums over splits in FP64.
 #include <type_traits>
 
 #include "dev_common.h"
@@ -136,6 +143,31 @@ __device__ __forceinline__ void tile_f64(int64_t npad, int64_t jlen, int32_t Pp,
 // ---------------------------------------------------------------------------
 // FP32 MFMA
 // ---------------------------------------------------------------------------
+// The four kernel-derivative values of pair (i, j), divided by -3/2 (see the
+// file header); a = (x, y, z, omega), b = (kappa, ., c, .) of each point.
+__device__ __forceinline__ void pair_K(const float4 a0, const float4 a1, const float4 b0,
+                                       const float4 b1, float &kpp, float &kpq, float &kqp,
+                                       float &kqq) {
+    const float dx = a0.x - b0.x, dy = a0.y - b0.y, dz = a0.z - b0.z;
+    const float R2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+    const float gg = __builtin_fmaf(a0.w, R2, a1.x);
+    const float gp = __builtin_fmaf(b0.w, R2, b1.x);
+    const float s = gg + gp, t = gg * gp;
+    const float r = rcp32(t * s);
+    const float sr = s * r;                           // 1 / (g g')
+    const float is = t * r;                           // 1 / s
+    const float A = r * __builtin_fmaf(gp, sr, is);   // r (1/g + 1/s)
+    const float Ap = r * __builtin_fmaf(gg, sr, is);  // r (1/g' + 1/s)
+    const float Q = (r + r) * __builtin_fmaf(is, is, sr);
+    const float ci = a1.z, cj = b1.z;
+    const float t1 = __builtin_fmaf(ci, Q, -Ap);
+    const float t2 = __builtin_fmaf(cj, Q, -A);
+    kpp = __builtin_fmaf(cj, t1, __builtin_fmaf(-ci, A, r));
+    kpq = R2 * t1;
+    kqp = R2 * t2;
+    kqq = (R2 * R2) * Q;
+}
+
 template <int NCB>
 constexpr int smem_f32() { return 2 * kJC * (int)sizeof(float4) + kJC * 2 * NCB * 16 * (int)sizeof(float); }
 
@@ -156,7 +188,6 @@ __device__ __forceinline__ void tile_f32(int64_t npad, int64_t jlen, int32_t Pp,
     const int64_t jbeg = (int64_t)split * jlen;
     const int64_t jend = min(npad, jbeg + jlen);
     const float4 a0 = P0[ibase + m], a1 = P1[ibase + m];
-    const float ci = a1.z;
     v4f accp[NCB], accq[NCB];
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
@@ -179,25 +210,8 @@ __device__ __forceinline__ void tile_f32(int64_t npad, int64_t jlen, int32_t Pp,
 #pragma unroll 2
         for (int jj = 0; jj < kJC; jj += 4) {
             const int jl = jj + kq;
-            const float4 b0 = sA[jl], b1 = sB[jl];
-            const float dx = a0.x - b0.x, dy = a0.y - b0.y, dz = a0.z - b0.z;
-            const float R2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
-            const float g = __builtin_fmaf(a0.w, R2, a1.x);
-            const float gp = __builtin_fmaf(b0.w, R2, b1.x);
-            const float s = g + gp, t = g * gp;
-            const float r = rcp32(t * s);
-            const float phi = -1.5f * r;
-            const float sr = s * r;
-            const float ig = gp * sr, igp = g * sr, is = t * r;
-            const float Pg = -phi * (ig + is);
-            const float Pgp = -phi * (igp + is);
-            const float Pgg = 2.f * phi * __builtin_fmaf(ig, igp, is * is);
-            const float cj = b1.z;
-            const float u = __builtin_fmaf(ci, Pgg, Pgp);
-            const float kpp = __builtin_fmaf(cj, u, __builtin_fmaf(ci, Pg, phi));
-            const float kpq = R2 * u;
-            const float kqp = R2 * __builtin_fmaf(cj, Pgg, Pg);
-            const float kqq = R2 * R2 * Pgg;
+            float kpp, kpq, kqp, kqq;
+            pair_K(a0, a1, sA[jl], sB[jl], kpp, kpq, kqp, kqq);
             const float *xr = sX + (jl * 2) * NC + m;
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) {
@@ -238,36 +252,19 @@ struct Aops {          // A operands of one 16 x 16 pair block (per lane: 4 pair
 
 // Split two FP32 values into packed bf16 hi (round to nearest even) and lo
 // (the rounded remainder): returns the packed words (v0 in the low half).
+// The low half of hi is widened with a byte permute, which keeps the compiler
+// from converting v0 a second time.  Contraction is off so that v - hi is a
+// plain subtraction in every kernel that inlines this (a product fused into
+// it in one kernel and not in another would break bitwise agreement between
+// the single-molecule and batched contractions).
 __device__ __forceinline__ void split2(float v0, float v1, uint32_t &hi, uint32_t &lo) {
+#pragma clang fp contract(off)
     const bf16x2 h = {(__bf16)v0, (__bf16)v1};
     hi = __builtin_bit_cast(uint32_t, h);
-    const float h0 = __uint_as_float(hi << 16), h1 = __uint_as_float(hi & 0xffff0000u);
+    const float h0 = __uint_as_float(__builtin_amdgcn_perm(0u, hi, 0x01000c0cu));   // hi << 16
+    const float h1 = __uint_as_float(hi & 0xffff0000u);
     const bf16x2 l = {(__bf16)(v0 - h0), (__bf16)(v1 - h1)};
     lo = __builtin_bit_cast(uint32_t, l);
-}
-
-// The four kernel-derivative values of pair (i, j) (see the file header).
-__device__ __forceinline__ void pair_K(const float4 a0, const float4 a1, const float4 b0,
-                                       const float4 b1, float &kpp, float &kpq, float &kqp,
-                                       float &kqq) {
-    const float dx = a0.x - b0.x, dy = a0.y - b0.y, dz = a0.z - b0.z;
-    const float R2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
-    const float gg = __builtin_fmaf(a0.w, R2, a1.x);
-    const float gp = __builtin_fmaf(b0.w, R2, b1.x);
-    const float s = gg + gp, t = gg * gp;
-    const float r = rcp32(t * s);
-    const float phi = -1.5f * r;
-    const float sr = s * r;
-    const float ig = gp * sr, igp = gg * sr, is = t * r;
-    const float Pg = -phi * (ig + is);
-    const float Pgp = -phi * (igp + is);
-    const float Pgg = 2.f * phi * __builtin_fmaf(ig, igp, is * is);
-    const float ci = a1.z, cj = b1.z;
-    const float u = __builtin_fmaf(ci, Pgg, Pgp);
-    kpp = __builtin_fmaf(cj, u, __builtin_fmaf(ci, Pg, phi));
-    kpq = R2 * u;
-    kqp = R2 * __builtin_fmaf(cj, Pgg, Pg);
-    kqq = R2 * R2 * Pgg;
 }
 
 // A operands of the block whose 4 j points of this lane are b0[jj], b1[jj].

@@ -135,6 +135,8 @@ __global__ __launch_bounds__(256) void k_prep(
 // The channels are stored as the contraction of the plan's mode reads them:
 //   FP64 / FP32: X[i][c][x];
 //   BF16X3: hi = bf16(v), lo = bf16(v - hi), each as [i/16][x][2 (i mod 16) + c].
+// The mixed modes store -3/2 p and -3/2 q: their contraction forms the pair
+// kernel divided by the -3/2 factor of Phi.
 // A 32 x 32 (point x perturbation) tile is staged through LDS so that the
 // [P][N] reads are coalesced.
 constexpr int TT = 32;
@@ -170,8 +172,9 @@ __global__ __launch_bounds__(256) void k_pert_prep(
         if (i >= npad || x >= Pp) continue;
         const double rx = sr[tx][ty + k], gxv = sg[tx][ty + k];
         const double wi = F[F_W * npad + i], r = F[F_RHO * npad + i];
-        const double p = wi * rx;
-        const double qv = wi * r * (F[F_OMR * npad + i] * rx + F[F_OMG * npad + i] * gxv);
+        const double sc = MODE == VV10_FP64 ? 1.0 : -1.5;
+        const double p = sc * wi * rx;
+        const double qv = sc * wi * r * (F[F_OMR * npad + i] * rx + F[F_OMG * npad + i] * gxv);
         if (MODE == VV10_FP64) {
             double *X = static_cast<double *>(Xv);
             X[(i * 2 + 0) * Pp + x] = p;

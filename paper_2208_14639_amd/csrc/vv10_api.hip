@@ -48,8 +48,9 @@ void plan_workspace_shape(int64_t npad, int32_t n_atom, int32_t ntiles, int num_
     }
     ws.jlen = ((npad / ws.jsplit + 31) / 32) * 32;
     while ((ws.jsplit - 1) * ws.jlen >= npad) --ws.jsplit;   // no empty split
+    // assembly GEMM: about one workgroup per CU over (64 x 64 tiles) x slices
     const int tiles = (ws.Pp + 63) / 64;
-    ws.gsplit = (int)std::max<int64_t>(1, std::min<int64_t>((1024 + tiles * tiles - 1) / (tiles * tiles),
+    ws.gsplit = (int)std::max<int64_t>(1, std::min<int64_t>((num_cu + tiles * tiles - 1) / (tiles * tiles),
                                                              std::max<int64_t>(1, npad / 64)));
     ws.bgroups = std::max(1, std::min<int>(n_atom, (8192 + std::max(ntiles, 1) - 1) / std::max(ntiles, 1)));
     if (bgroups_override > 0) ws.bgroups = std::min<int>(n_atom, bgroups_override);
@@ -64,10 +65,8 @@ size_t workspace_bytes(int64_t npad, int32_t n_atom, int32_t ntiles, vv10_precis
     if (!alias) b += (size_t)ws.jsplit * ch * partial_elem(prec);
     b += (size_t)ntiles * n_atom * 9 * sizeof(double);
     b += (size_t)ws.bgroups * NI * npad * sizeof(double);
-    b += (size_t)ws.gsplit * ws.Pp * ws.Pp * sizeof(double);
-    b += (size_t)ws.P * ws.P * sizeof(double);
+    b += (size_t)(ws.gsplit + 1) * (ws.Pp + 1) * ws.Pp * sizeof(double);
     b += (size_t)n_atom * n_atom * 9 * sizeof(double);
-    b += (size_t)256 * ws.Pp * sizeof(double);
     return b;
 }
 
@@ -110,9 +109,8 @@ void free_workspace(Workspace &ws) {
     dfree(ws.Dpart);
     dfree(ws.Igrp);
     dfree(ws.Hpart);
-    dfree(ws.Hgr);
+    dfree(ws.Hsum);
     dfree(ws.DS);
-    dfree(ws.gpart);
     ws = Workspace{};
 }
 
@@ -178,10 +176,9 @@ vv10_status vv10::ensure_workspace(vv10_plan *p) {
     if (e == hipSuccess) e = dalloc(&ws.Z, ch);
     if (e == hipSuccess) e = dalloc(&ws.Dpart, (size_t)p->ntiles * p->n_atom * 9);
     if (e == hipSuccess) e = dalloc(&ws.Igrp, (size_t)ws.bgroups * vv10::NI * p->npad);
-    if (e == hipSuccess) e = dalloc(&ws.Hpart, (size_t)ws.gsplit * ws.Pp * ws.Pp);
-    if (e == hipSuccess) e = dalloc(&ws.Hgr, (size_t)ws.P * ws.P);
+    if (e == hipSuccess) e = dalloc(&ws.Hpart, (size_t)ws.gsplit * (ws.Pp + 1) * ws.Pp);
+    if (e == hipSuccess) e = dalloc(&ws.Hsum, (size_t)(ws.Pp + 1) * ws.Pp);
     if (e == hipSuccess) e = dalloc(&ws.DS, (size_t)p->n_atom * p->n_atom * 9);
-    if (e == hipSuccess) e = dalloc(&ws.gpart, (size_t)256 * ws.Pp);
     if (e != hipSuccess) {
         free_workspace(ws);
         (void)hipGetLastError();

@@ -39,7 +39,7 @@ struct Workspace {
     int32_t ncb = 0, ngroups = 0;  // 16-column blocks per contraction group, groups
     int32_t jsplit = 1;          // j splits of the contraction
     int64_t jlen = 0;            // j points per split (multiple of 32)
-    int32_t gsplit = 1;          // splits of the assembly GEMM
+    int32_t gsplit = 1;          // point slices of the assembly GEMM
     int32_t bgroups = 1;         // atom groups of the grid-term kernel
     void *X = nullptr;           // (p, q) channels: FP64 or FP32 [npad][2][Pp];
                                  // BF16X3: hi then lo, each [npad/16][Pp][32] bf16
@@ -49,10 +49,9 @@ struct Workspace {
     double *Z = nullptr;         // [npad][2][Pp] grid-position channels
     double *Dpart = nullptr;     // [ntiles][n_atom][9] tile sums of a_i D^B_i (6) and a_i E^{Bgr}_i (3)
     double *Igrp = nullptr;      // [bgroups][6][npad] pair integrals per atom group
-    double *Hpart = nullptr;     // [gsplit][Pp][Pp]
-    double *Hgr = nullptr;       // [P][P] E_{gr,gr}
+    double *Hpart = nullptr;     // [gsplit][Pp + 1][Pp] GEMM slices; row Pp: gradient
+    double *Hsum = nullptr;      // [Pp + 1][Pp] the slices summed
     double *DS = nullptr;        // [n_atom][n_atom][9] Dpart summed over each atom's tiles
-    double *gpart = nullptr;     // [ngrad][Pp] gradient partials
     size_t bytes = 0;
 };
 
