@@ -228,13 +228,20 @@ __device__ __forceinline__ int sym_index(int a, int b) {
 }
 
 // E_{gr,gr}[(A,a)][(B,b)] = DS[A][B][(a,b)] for B != A; the diagonal blocks
-// are -sum_{C != A} DS[A][C][(a,b)] (translational invariance).
+// are -sum_{C != A} DS[A][C][(a,b)] (translational invariance).  The D sums
+// are symmetric in the atom pair and formed for A < B only.
+__device__ __forceinline__ double dsym(int32_t n_atom, const double *__restrict__ DS, int A, int B,
+                                       int c) {
+    const int lo = A < B ? A : B, hi = A < B ? B : A;
+    return DS[((int64_t)lo * n_atom + hi) * 9 + c];
+}
+
 __device__ __forceinline__ double egrgr(int32_t n_atom, const double *__restrict__ DS, int A, int B,
                                         int c) {
-    if (A != B) return DS[((int64_t)A * n_atom + B) * 9 + c];
+    if (A != B) return dsym(n_atom, DS, A, B, c);
     double v = 0.0;
     for (int C = 0; C < n_atom; ++C)
-        if (C != A) v -= DS[((int64_t)A * n_atom + C) * 9 + c];
+        if (C != A) v -= dsym(n_atom, DS, A, C, c);
     return v;
 }
 

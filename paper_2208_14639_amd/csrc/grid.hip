@@ -12,7 +12,8 @@
 //   Z[i][0][3B+a] = E^{Bgr}_{i,a} + c_i U^{Bgr}_{i,a},  Z[i][1][3B+a] = W^{Bgr}_{i,a}
 // (the two channels that multiply p and q in E_{G,gr}), and per tile t of
 // outer points (all in one atom A) the sums
-//   Dpart[t][B][0..5] = sum_{i in t} a_i D^B_i   (xx, yy, zz, xy, xz, yz)
+//   Dpart[t][B][0..5] = sum_{i in t} a_i D^B_i   (xx, yy, zz, xy, xz, yz; B > A only,
+//                                                  zero for B < A)
 //   Dpart[t][B][6..8] = sum_{i in t} a_i E^{Bgr}_i
 // from which the assembly builds E_{gr,gr} and the grid part of the
 // gradient.  The own-atom slot B = O(i) follows from translational
@@ -36,11 +37,11 @@ namespace {
 
 constexpr int TG = kGridTile;
 
-// Pair integrals of one (i, j) pair (the Section II.A/II.B inner sums), added
-// to c[0..5] = E, U, W, A, B, C; returns the shared geometry for the grid terms.
+// Shared geometry of one (i, j) pair: with r = 1/(g g' s), p = a_j r
+// (a_j Phi = -3/2 p), 1/g = g' s r, 1/g' = g s r, 1/s = g g' r.
 template <typename T>
 struct PairGeo {
-    T R2, g, gp, s, r, pa, ig, igp, is;
+    T R2, p, ig, igp, is, h;
 };
 
 template <typename T, typename T4>
@@ -48,34 +49,86 @@ __device__ __forceinline__ PairGeo<T> pair_geo(const T4 a0, const T4 a1, const T
     PairGeo<T> q;
     const T dx = b0.x - a0.x, dy = b0.y - a0.y, dz = b0.z - a0.z;
     q.R2 = dx * dx + dy * dy + dz * dz;
-    q.g = a0.w * q.R2 + a1.x;
-    q.gp = b0.w * q.R2 + b1.x;
-    q.s = q.g + q.gp;
-    const T tt = q.g * q.gp;
-    if constexpr (sizeof(T) == 8) q.r = rcp64(tt * q.s); else q.r = rcp32(tt * q.s);
-    q.pa = T(-1.5) * b1.y * q.r;                 // a_j Phi_ij
-    const T sr = q.s * q.r;
-    q.ig = q.gp * sr;
-    q.igp = q.g * sr;
-    q.is = tt * q.r;
+    const T g = a0.w * q.R2 + a1.x;
+    const T gp = b0.w * q.R2 + b1.x;
+    const T s = g + gp;
+    const T tt = g * gp;
+    T r;
+    if constexpr (sizeof(T) == 8) r = rcp64(tt * s); else r = rcp32(tt * s);
+    q.p = b1.y * r;
+    const T sr = s * r;
+    q.ig = gp * sr;
+    q.igp = g * sr;
+    q.is = tt * r;
+    q.h = q.ig + q.is;
     return q;
 }
 
+// Pair-integral sums, scaled: c[0] += p, c[1] += p h, c[2] += p h R^2,
+// c[3..5] += p m (R^2)^{0,1,2} with m = 1/s^2 + 1/(s g) + 1/g^2 = h^2 - (1/s)(1/g).
+// Then E = -3/2 c0, U = 3/2 c1, W = 3/2 c2, (A, B, C) = -3 (c3, c4, c5).
 template <typename T>
 __device__ __forceinline__ void add_pair_integrals(const PairGeo<T> &q, T *c) {
-    const T u = q.pa * (q.ig + q.is);
-    const T m2 = T(2) * q.pa * (q.is * q.is + q.is * q.ig + q.ig * q.ig);
-    c[0] += q.pa;
-    c[1] -= u;
-    c[2] -= u * q.R2;
-    c[3] += m2;
-    c[4] += m2 * q.R2;
-    c[5] += m2 * q.R2 * q.R2;
+    const T ph = q.p * q.h;
+    const T pm = q.p * (q.h * q.h - q.is * q.ig);
+    const T pmR2 = pm * q.R2;
+    c[0] += q.p;
+    c[1] += ph;
+    c[2] += ph * q.R2;
+    c[3] += pm;
+    c[4] += pmR2;
+    c[5] += pmR2 * q.R2;
+}
+
+// One LDS chunk of points j of atom B != A: pair integrals into pc, grid
+// sums into c (see k_grid); the D sums only when DSUM.
+template <bool DSUM, typename T, typename T4>
+__device__ __forceinline__ void grid_chunk(const T4 a0, const T4 a1, const T4 *sA, const T4 *sB,
+                                           int cnt, T *pc, T *c) {
+    const T oi = a0.w;
+#pragma unroll 2
+    for (int jj = 0; jj < cnt; ++jj) {
+        const T4 b0 = sA[jj];
+        const PairGeo<T> q = pair_geo<T>(a0, a1, b0, sB[jj]);
+        add_pair_integrals(q, pc);
+        const T dx = b0.x - a0.x, dy = b0.y - a0.y, dz = b0.z - a0.z;
+        const T Ti = oi * q.ig, Tj = b0.w * q.igp, Ts = (oi + b0.w) * q.is;
+        const T T_ = Ti + Tj + Ts;
+        const T TQ = T_ * q.h + Ti * q.ig + Ts * q.is;
+        const T e = q.p * T_;
+        const T u = q.p * TQ;
+        const T v = q.p * (q.R2 * TQ - q.h);
+        c[0] += e * dx; c[1] += e * dy; c[2] += e * dz;
+        c[3] += u * dx; c[4] += u * dy; c[5] += u * dz;
+        c[6] += v * dx; c[7] += v * dy; c[8] += v * dz;
+        if (DSUM) {
+            const T S = T_ * T_ + Ti * Ti + Tj * Tj + Ts * Ts;
+            const T ps = q.p * S;
+            const T psx = ps * dx, psy = ps * dy, psz = ps * dz;
+            c[9] += psx * dx;
+            c[10] += psy * dy;
+            c[11] += psz * dz;
+            c[12] += psx * dy;
+            c[13] += psx * dz;
+            c[14] += psy * dz;
+            c[15] += e;
+        }
+    }
 }
 
 // Fused with the pair integrals of the Hessian call: the group of atoms B of
 // a workgroup also covers the outer point's own atom for E, U, W, A, B, C,
 // whose per-group partial sums go to Ipart[group][6][npad].
+//
+// Per pair (B != A), with Ti = omega_i/g, Tj = omega_j/g', Ts = (omega_i + omega_j)/s,
+// T = Ti + Tj + Ts, TQ = T h + Ti/g + Ts/s, S = T^2 + Ti^2 + Tj^2 + Ts^2, the
+// scaled sums
+//   g[0..2] = sum p T d,  g[3..5] = sum p TQ d,  g[6..8] = sum p (R^2 TQ - h) d,
+//   g[9..14] = sum p S d d^T (xx, yy, zz, xy, xz, yz),  g[15] = sum p T
+// give e d, u d, v d and D through e = 3 p T, u = -3 p TQ, v = -3 p (R^2 TQ - h),
+// D = 6 sum p S d d^T - 3 (sum p T) I.  The D sums are symmetric in the two
+// atoms (the summand a_i a_j Phi (2 S d d^T - T I) is symmetric in i, j), so
+// they are formed for B > A only and the assembly reads them for both orders.
 template <typename T, typename T4>
 __global__ __launch_bounds__(64) void k_grid(
     int32_t n_atom, int32_t Pp, int32_t bgroups, int64_t npad, const int64_t *__restrict__ seg,
@@ -91,12 +144,11 @@ __global__ __launch_bounds__(64) void k_grid(
     const int64_t i = (int64_t)tile_i0[t] + (live ? lane : 0);
     const T4 a0 = P0[i], a1 = P1[i];
     const double ai = live ? (double)a1.y : 0.0, ci = (double)a1.z;
-    const T oi = a0.w;
     double pint[6] = {};
     for (int B = grp; B < n_atom; B += bgroups) {
         const int64_t jb = seg[B], je = seg[B + 1];
-        // [0..2] e d, [3..5] u d, [6..8] v d, [9..14] D (xx, yy, zz, xy, xz, yz)
-        double acc[15] = {};
+        const bool dsum = B > A;
+        double acc[16] = {};
         for (int64_t j0 = jb; j0 < je; j0 += TG) {
             __syncthreads();
             const int64_t j = j0 + lane;
@@ -107,67 +159,54 @@ __global__ __launch_bounds__(64) void k_grid(
             T pc[6] = {};
             if (B == A) {
                 // own atom: pair integrals only (grid-position terms vanish)
+#pragma unroll 4
                 for (int jj = 0; jj < cnt; ++jj) {
                     const PairGeo<T> q = pair_geo<T>(a0, a1, sA[jj], sB[jj]);
                     add_pair_integrals(q, pc);
                 }
             } else {
-                T c[15] = {};
-                for (int jj = 0; jj < cnt; ++jj) {
-                    const T4 b0 = sA[jj];
-                    const PairGeo<T> q = pair_geo<T>(a0, a1, b0, sB[jj]);
-                    add_pair_integrals(q, pc);
-                    const T dx = b0.x - a0.x, dy = b0.y - a0.y, dz = b0.z - a0.z;
-                    const T Ti = oi * q.ig, Tj = b0.w * q.igp, Ts = (oi + b0.w) * q.is;
-                    const T T_ = Ti + Tj + Ts;
-                    const T h = q.ig + q.is;
-                    const T TQ = T_ * h + Ti * q.ig + Ts * q.is;
-                    const T e = T(-2) * q.pa * T_;
-                    const T u = T(2) * q.pa * TQ;
-                    const T v = T(2) * q.pa * (q.R2 * TQ - h);
-                    const T S = T_ * T_ + Ti * Ti + Tj * Tj + Ts * Ts;
-                    const T dd = T(-4) * q.pa * S;          // coefficient of d d^T
-                    const T di = -e;                        // coefficient of I (= 2 a_j Phi T)
-                    c[0] += e * dx; c[1] += e * dy; c[2] += e * dz;
-                    c[3] += u * dx; c[4] += u * dy; c[5] += u * dz;
-                    c[6] += v * dx; c[7] += v * dy; c[8] += v * dz;
-                    const T ddx = dd * dx, ddy = dd * dy;
-                    c[9] += ddx * dx + di;
-                    c[10] += ddy * dy + di;
-                    c[11] += dd * dz * dz + di;
-                    c[12] += ddx * dy;
-                    c[13] += ddx * dz;
-                    c[14] += ddy * dz;
-                }
+                T c[16] = {};
+                if (dsum) grid_chunk<true, T, T4>(a0, a1, sA, sB, cnt, pc, c);
+                else grid_chunk<false, T, T4>(a0, a1, sA, sB, cnt, pc, c);
 #pragma unroll
-                for (int k = 0; k < 15; ++k) acc[k] += (double)c[k];
+                for (int k = 0; k < 16; ++k) acc[k] += (double)c[k];
             }
 #pragma unroll
             for (int k = 0; k < 6; ++k) pint[k] += (double)pc[k];
         }
         if (B == A) continue;
+        // E^{Bgr} = 3 acc[0..2], U^{Bgr} = -3 acc[3..5], W^{Bgr} = -3 acc[6..8]
         if (live) {
             double *z0 = Z + (i * 2 + 0) * Pp + 3 * B;
             double *z1 = Z + (i * 2 + 1) * Pp + 3 * B;
-            z0[0] = acc[0] + ci * acc[3];
-            z0[1] = acc[1] + ci * acc[4];
-            z0[2] = acc[2] + ci * acc[5];
-            z1[0] = acc[6];
-            z1[1] = acc[7];
-            z1[2] = acc[8];
+            z0[0] = 3.0 * (acc[0] - ci * acc[3]);
+            z0[1] = 3.0 * (acc[1] - ci * acc[4]);
+            z0[2] = 3.0 * (acc[2] - ci * acc[5]);
+            z1[0] = -3.0 * acc[6];
+            z1[1] = -3.0 * acc[7];
+            z1[2] = -3.0 * acc[8];
         }
-        const double red[9] = {ai * acc[9], ai * acc[10], ai * acc[11], ai * acc[12], ai * acc[13],
-                               ai * acc[14], ai * acc[0], ai * acc[1], ai * acc[2]};
+        const double di = -3.0 * acc[15];
+        const double red[9] = {ai * (6.0 * acc[9] + di), ai * (6.0 * acc[10] + di),
+                               ai * (6.0 * acc[11] + di), ai * 6.0 * acc[12],
+                               ai * 6.0 * acc[13], ai * 6.0 * acc[14],
+                               ai * 3.0 * acc[0], ai * 3.0 * acc[1], ai * 3.0 * acc[2]};
         double *dp = Dpart + ((int64_t)t * n_atom + B) * 9;
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
+            if (k < 6 && !dsum) {
+                if (lane == 0) dp[k] = 0.0;
+                continue;
+            }
             const double tot = wave_sum(red[k]);
             if (lane == 0) dp[k] = tot;
         }
     }
-    if (live)
+    if (live) {
+        const double sc[6] = {-1.5, 1.5, 1.5, -3.0, -3.0, -3.0};
 #pragma unroll
-        for (int k = 0; k < 6; ++k) Ipart[((int64_t)grp * NI + k) * npad + i] = pint[k];
+        for (int k = 0; k < 6; ++k) Ipart[((int64_t)grp * NI + k) * npad + i] = sc[k] * pint[k];
+    }
 }
 
 // I[k][i] = sum over atom groups of Ipart[grp][k][i] (group order), i < n.

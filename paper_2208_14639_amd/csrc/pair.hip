@@ -7,8 +7,10 @@
 //                                        m = 1/(g+g')^2 + 1/((g+g')g) + 1/g^2
 // with a_j = w_j rho_j and every j (j = i included).  One lane owns one
 // outer point i; j points stream through LDS and are read as wave-wide
-// broadcasts.  All 1/g, 1/g', 1/(g+g') come from one reciprocal of
-// g g' (g+g').
+// broadcasts.  All 1/g, 1/g', 1/(g+g') come from one reciprocal
+// r = 1/(g g' (g+g')); the loop sums p = a_j r times h, R^2 h and
+// m (R^2)^{0,1,2} (m = h^2 - 1/((g+g') g)), and the constant factors
+// (a_j Phi = -3/2 p) are applied to the sums.
 #include <algorithm>
 
 #include "dev_common.h"
@@ -55,17 +57,19 @@ __global__ __launch_bounds__(256) void k_pair(int64_t npad, int64_t jlen,
             const T s = g + gp, t = g * gp;
             T r;
             if constexpr (sizeof(T) == 8) r = rcp64(t * s); else r = rcp32(t * s);
-            const T pa = T(-1.5) * b1.y * r;       // a_j Phi_ij
-            const T ig = gp * s * r, is = t * r;
-            const T u = pa * (ig + is);
-            e += pa;
-            uu -= u;
-            ww -= u * R2;
+            const T pj = b1.y * r;
+            const T ig = gp * (s * r), is = t * r;
+            const T h = ig + is;
+            const T ph = pj * h;
+            e += pj;
+            uu += ph;
+            ww += ph * R2;
             if (HESS) {
-                const T m2 = T(2) * pa * (is * is + is * ig + ig * ig);
-                aa += m2;
-                bb += m2 * R2;
-                cc += m2 * R2 * R2;
+                const T pm = pj * (h * h - is * ig);
+                const T pmR2 = pm * R2;
+                aa += pm;
+                bb += pmR2;
+                cc += pmR2 * R2;
             }
         }
         E += (double)e;
@@ -86,7 +90,8 @@ __global__ __launch_bounds__(256) void k_pair(int64_t npad, int64_t jlen,
     __syncthreads();
     const int nout = HESS ? 6 : 3;
     for (int k = wave; k < nout; k += 4) {
-        const double v = red[0][k][lane] + red[1][k][lane] + red[2][k][lane] + red[3][k][lane];
+        const double sc = k == 0 ? -1.5 : (k < 3 ? 1.5 : -3.0);   // E; U, W; A, B, C
+        const double v = sc * (red[0][k][lane] + red[1][k][lane] + red[2][k][lane] + red[3][k][lane]);
         Ipart[((int64_t)blockIdx.y * NI + k) * npad + i] = v;
     }
 }
