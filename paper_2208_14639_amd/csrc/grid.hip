@@ -86,7 +86,7 @@ template <bool DSUM, typename T, typename T4>
 __device__ __forceinline__ void grid_chunk(const T4 a0, const T4 a1, const T4 *sA, const T4 *sB,
                                            int cnt, T *pc, T *c) {
     const T oi = a0.w;
-#pragma unroll 2
+#pragma unroll 4
     for (int jj = 0; jj < cnt; ++jj) {
         const T4 b0 = sA[jj];
         const PairGeo<T> q = pair_geo<T>(a0, a1, b0, sB[jj]);
