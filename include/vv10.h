@@ -153,6 +153,7 @@ vv10_status vv10_set_stream(vv10_plan *plan, hipStream_t stream);
 
 /* Enable (1) or disable (0) per-stage timing: while enabled, every call
  * records a HIP event pair on the plan's stream around each stage it runs.
+ * The events come from a per-device pool; vv10_destroy returns them.
  * Errors: VV10_E_STATE (NULL plan), VV10_E_HIP (event creation failed). */
 vv10_status vv10_set_timing(vv10_plan *plan, int32_t enable);
 

@@ -202,6 +202,7 @@ __global__ __launch_bounds__(256) void k_hsum(int64_t len, int S, const double *
     const int sb = min(S, wave * q), se = min(S, sb + q);
     double a = 0.0;
     if (e < len)
+#pragma unroll 16
         for (int s = sb; s < se; ++s) a += Hpart[(int64_t)s * len + e];
     part[wave][lane] = a;
     __syncthreads();
@@ -217,6 +218,7 @@ __global__ __launch_bounds__(256) void k_dsum(int32_t n_atom, const int32_t *__r
     const int A = (int)(k / (9LL * n_atom));
     const int rem = (int)(k - (int64_t)A * 9 * n_atom);   // B * 9 + c
     double v = 0.0;
+#pragma unroll 8
     for (int t = tile_first[A]; t < tile_first[A + 1]; ++t) v += Dpart[(int64_t)t * n_atom * 9 + rem];
     DS[k] = v;
 }

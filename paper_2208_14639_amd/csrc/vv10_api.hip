@@ -4,7 +4,10 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <vector>
 
 #include "vv10_internal.h"
 
@@ -100,6 +103,30 @@ hipError_t dalloc(T **p, size_t count) {
 
 void dfree(void *ptr) { vv10::dev_free(ptr); }
 
+// Timing events are kept in a per-device pool: plans take them when timing
+// is switched on and give them back when destroyed (after their stream has
+// been synchronised), so short-lived timed plans create no events.
+std::mutex g_ev_mutex;
+std::map<int, std::vector<hipEvent_t>> g_ev_pool;
+
+hipError_t take_event(int device, hipEvent_t *ev) {
+    {
+        std::lock_guard<std::mutex> lock(g_ev_mutex);
+        auto &v = g_ev_pool[device];
+        if (!v.empty()) {
+            *ev = v.back();
+            v.pop_back();
+            return hipSuccess;
+        }
+    }
+    return hipEventCreate(ev);
+}
+
+void give_event(int device, hipEvent_t ev) {
+    std::lock_guard<std::mutex> lock(g_ev_mutex);
+    g_ev_pool[device].push_back(ev);
+}
+
 void free_workspace(Workspace &ws) {
     dfree(ws.X);
     dfree(ws.L);
@@ -117,7 +144,7 @@ void free_workspace(Workspace &ws) {
 void free_plan(vv10_plan *p) {
     if (!p) return;
     for (auto &ev : p->ev)
-        if (ev) (void)hipEventDestroy(ev);
+        if (ev) give_event(p->device, ev);
     free_workspace(p->ws);
     dfree(p->P0);
     dfree(p->P1);
@@ -415,7 +442,8 @@ vv10_status vv10_set_timing(vv10_plan *p, int32_t enable) {
     if (!p) return VV10_E_STATE;
     if (enable && !p->ev[0]) {
         for (auto &ev : p->ev) {
-            if (hipEventCreate(&ev) != hipSuccess) {
+            if (take_event(p->device, &ev) != hipSuccess) {
+                ev = nullptr;
                 (void)hipGetLastError();
                 return VV10_E_HIP;
             }
