@@ -145,6 +145,81 @@ def bench_batch(args, torch, np, inputs, vv10):
     print(json.dumps(out), flush=True)
 
 
+def bench_trial_response(args, torch, np, inputs, vv10, n_t=54):
+    """CPSCF-style use of vv10_trial_response: the hexamer plan is prepared
+    once, and every step evaluates f^{rho,t}, f^{gamma,t} of n_t seeded trial
+    densities on it (the first call also forms the pair integrals the plan
+    then keeps; it is timed separately)."""
+    p = inputs.make_workload("water_hexamer", with_derivatives=False)
+    n = p.n_grid
+    rt, gt = inputs.trial_densities(p, n_t, seed=1006)
+    dev = torch.device("cuda:0")
+    rt_d = torch.as_tensor(rt).to(dev).contiguous()
+    gt_d = torch.as_tensor(gt).to(dev).contiguous()
+    pair_t = float(n) * n * n_t
+    with vv10.Plan(p, prec=args.prec) as pl:
+        vv10.vv10_set_timing(pl.handle, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fr, fg = pl.trial_response(rt_d, gt_d)
+        torch.cuda.synchronize()
+        first_ms = (time.perf_counter() - t0) * 1e3
+        first_stages = vv10.vv10_stage_times(pl.handle)
+        for k in range(args.warmup):
+            pl.trial_response(rt_d, gt_d)
+        torch.cuda.synchronize()
+        stages = []
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            fr, fg = pl.trial_response(rt_d, gt_d)
+            stages.append(vv10.vv10_stage_times(pl.handle))
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        stage_ms = {k: float(np.mean([st[k] for st in stages])) for k in ("pert_prep", "contract", "assemble")}
+        fr, fg = fr.cpu().numpy(), fg.cpu().numpy()
+    t_con = stage_ms["contract"] * 1e-3
+    mfma_key = {"fp64": "mfma_f64", "fp32": "mfma_f32", "bf16x3": "mfma_bf16"}[args.prec]
+    achieved = FLOPS_PER_PAIR_PERT * pair_t / t_con / 1e12
+    out = {
+        "metric": "VV10 Hessian grid-pair\u00b7perturbation/s, mixed vs FP64, at stated err; p99 latency",
+        "value": pair_t / dt, "unit": "pair*pert/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f32+f64"}[args.prec],
+        "data": "synthetic",
+        "config": {"workload": "trial_response_hexamer", "n_grid": n, "n_trial": n_t,
+                   "precision": args.prec, "seed": 1006},
+        "roofline": dict(bound="mfma", kernel=f"k_contract_{args.prec}", achieved=achieved,
+                         peak=PEAKS_TFLOPS[mfma_key], unit="TFLOP/s",
+                         frac=achieved / PEAKS_TFLOPS[mfma_key], traffic=None),
+        "stage_ms": stage_ms,
+        "first_call_ms": first_ms, "first_call_pair_ms": first_stages["pair"],
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        g = oracle.gamma(p.grad_rho)
+        gam_t = oracle.gamma_x(p.grad_rho, gt)
+        # rows 0..k of the oracle's response (one pair-integral pass per call),
+        # k calibrated on 16 rows to about 10 s
+        t0 = time.perf_counter()
+        oracle.response_rows(0, 16, p.coords, p.weights, p.rho, g, p.b, p.C, rt, gam_t)
+        t16 = time.perf_counter() - t0
+        k = max(16, min(n, int(16 * 10.0 / max(t16, 1e-3))))
+        t0 = time.perf_counter()
+        Yr, Yg = oracle.response_rows(0, k, p.coords, p.weights, p.rho, g, p.b, p.C, rt, gam_t)
+        dtc = time.perf_counter() - t0
+        err = max(float(np.max(np.abs(fr[:, :k] - Yr)) / np.max(np.abs(fr))),
+                  float(np.max(np.abs(fg[:, :k] - Yg)) / np.max(np.abs(fg))))
+        out["cpu_baseline"] = dict(value=k * n * n_t / dtc, unit="pair*pert/s",
+                                   cores=oracle.num_threads(), kind="oracle", seconds=dtc,
+                                   sample=f"response rows 0..{k} of N={n}, n_t={n_t} "
+                                          f"(one full pair-integral pass included)")
+        out["errors_vs_oracle"] = {"response_rows_0_to_k_normwise": err}
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
 def bench_served(args, torch, np, inputs, vv10, pool_size=16, n_requests=96, n_warm=8):
     """Poisson stream of requests (1-30 waters, 1000-2500 points/atom) through
     the continuous-batching server; p50/p99 latency and throughput."""
@@ -212,7 +287,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="water_hexamer",
-                    choices=["water_dimer", "water_hexamer", "water_20mer", "batch64", "served"],
+                    choices=["water_dimer", "water_hexamer", "water_20mer", "batch64", "served",
+                             "trial_response"],
                     help="batch64: 64 random clusters of 1-30 waters, 1500 points/atom, "
                          "one graph launch per step")
     ap.add_argument("--prec", default="bf16x3", choices=["fp64", "fp32", "bf16x3"],
@@ -243,6 +319,8 @@ def main():
         return bench_batch(args, torch, np, inputs, vv10)
     if args.workload == "served":
         return bench_served(args, torch, np, inputs, vv10)
+    if args.workload == "trial_response":
+        return bench_trial_response(args, torch, np, inputs, vv10)
 
     from paper_2208_14639_amd import autotune
     p = inputs.make_workload(args.workload)

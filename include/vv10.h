@@ -133,6 +133,37 @@ vv10_status vv10_hessian_terms(vv10_plan *plan, int32_t n_pert, const double *rh
                                const double *grad_rho_x, double *hess, double *grad,
                                double *resp_rho, double *resp_gamma);
 
+/* Largest n_t accepted by vv10_trial_response. */
+#define VV10_MAX_TRIAL 65536
+
+/*
+ * vv10_trial_response -- VV10 part of the contracted orbital Hessian for
+ * n_t trial densities (Section II.B, the f^{rho,t}, f^{gamma,t} equations
+ * that enter G^t_{mu nu}; the same quantities drive CPSCF and TDDFT):
+ *   f^{rho,t}_i   = sum_j w_j (f^{rho rho}_ij rho^t_j + 2 f^{rho gamma}_ij gamma^t_j)
+ *   f^{gamma,t}_i = sum_j w_j (f^{gamma rho}_ij rho^t_j + 2 f^{gamma gamma}_ij gamma^t_j)
+ * with gamma^t_j = grad rho_j . grad rho^t_j and the second-derivative
+ * matrices including their delta_ij (same-point) terms; that is, the
+ * derivative of the potential (f^rho, f^gamma of vv10_energy_potential)
+ * along rho + t rho^t.
+ *
+ *  n_t         number of trial densities, 0 <= n_t <= VV10_MAX_TRIAL (0: no-op).
+ *  rho_t       [n_t][N] DEVICE, FP64: trial densities on the grid.
+ *  grad_rho_t  [n_t][N][3] DEVICE, FP64: their gradients.
+ *  f_rho_t     [n_t][N] DEVICE, FP64 output.
+ *  f_gamma_t   [n_t][N] DEVICE, FP64 output.
+ * The pair integrals the same-point terms need are computed by the plan's
+ * first call and kept; the workspace for n_t columns is kept and rebuilt
+ * when n_t changes.  Asynchronous on the plan's stream.
+ * Errors: VV10_E_ARG, VV10_E_OOM (workspace), VV10_E_STATE, VV10_E_HIP.
+ */
+vv10_status vv10_trial_response(vv10_plan *plan, int32_t n_t, const double *rho_t,
+                                const double *grad_rho_t, double *f_rho_t, double *f_gamma_t);
+
+/* Device bytes that vv10_trial_response adds to a plan for n_t trial
+ * densities (upper bound over devices); 0 for invalid sizes. */
+size_t vv10_response_footprint_bytes(int64_t n_grid, int32_t n_t, vv10_precision prec);
+
 /* Stages of the library's launch sequence, for vv10_stage_times. */
 typedef enum {
     VV10_STAGE_PAIR = 0,      /* pair integrals E, U, W of vv10_energy_potential */

@@ -33,6 +33,47 @@ namespace vv10 {
 
 namespace {
 
+// Per-point quantities of the same-point (delta_ij) terms.
+struct PointFields {
+    double w, r, omr, omg, kar, omrr, omrg, omgg, karr, U, W, A, B, C;
+};
+
+__device__ __forceinline__ PointFields point_fields(const double *__restrict__ F,
+                                                    const double *__restrict__ I, int64_t npad,
+                                                    int64_t i) {
+    PointFields f;
+    f.w = F[F_W * npad + i];
+    f.r = F[F_RHO * npad + i];
+    f.omr = F[F_OMR * npad + i];
+    f.omg = F[F_OMG * npad + i];
+    f.kar = F[F_KAR * npad + i];
+    f.omrr = F[F_OMRR * npad + i];
+    f.omrg = F[F_OMRG * npad + i];
+    f.omgg = F[F_OMGG * npad + i];
+    f.karr = F[F_KARR * npad + i];
+    f.U = I[I_U * npad + i];
+    f.W = I[I_W * npad + i];
+    f.A = I[I_A * npad + i];
+    f.B = I[I_B * npad + i];
+    f.C = I[I_C * npad + i];
+    return f;
+}
+
+// Yr, Yg of one point and perturbation from the contraction's channel sums
+// (yp, yq) and the perturbation values (rx = rho^x, gx = gamma^x).
+__device__ __forceinline__ void point_response(const PointFields &f, double rx, double gx,
+                                               double yp, double yq, double &Yr, double &Yg) {
+    const double dk = f.kar * rx;
+    const double dw = f.omr * rx + f.omg * gx;
+    const double loc_r = f.U * dk + f.W * dw + rx * (f.kar * f.U + f.omr * f.W)
+                       + f.r * (f.A * f.kar * dk + f.B * (f.kar * dw + f.omr * dk) + f.C * f.omr * dw)
+                       + f.r * (f.karr * rx * f.U + (f.omrr * rx + f.omrg * gx) * f.W);
+    const double loc_g = rx * f.omg * f.W + f.r * (f.B * f.omg * dk + f.C * f.omg * dw)
+                       + f.r * (f.omrg * rx + f.omgg * gx) * f.W;
+    Yr = yp + f.r * f.omr * yq + loc_r;
+    Yg = f.r * f.omg * yq + loc_g;
+}
+
 // One wave per point; the partials are FP64 or FP32 ([S][npad][2][Pp]; for
 // FP64 with one split they alias Y, read before R is written in place).
 template <typename T>
@@ -44,13 +85,7 @@ __global__ __launch_bounds__(256) void k_resp(
     const int lane = threadIdx.x & 63;
     const int64_t i = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (i >= n) return;
-    const double w = F[F_W * npad + i], r = F[F_RHO * npad + i];
-    const double omr = F[F_OMR * npad + i], omg = F[F_OMG * npad + i];
-    const double kar = F[F_KAR * npad + i];
-    const double omrr = F[F_OMRR * npad + i], omrg = F[F_OMRG * npad + i];
-    const double omgg = F[F_OMGG * npad + i], karr = F[F_KARR * npad + i];
-    const double U = I[I_U * npad + i], W = I[I_W * npad + i];
-    const double Ai = I[I_A * npad + i], Bi = I[I_B * npad + i], Ci = I[I_C * npad + i];
+    const PointFields f = point_fields(F, I, npad, i);
     const int A = atom_of[i];
     const double *z0 = Z + (i * 2 + 0) * Pp, *z1 = Z + (i * 2 + 1) * Pp;
 
@@ -83,27 +118,62 @@ __global__ __launch_bounds__(256) void k_resp(
             yp += (double)Ypart[s * len + o];
             yq += (double)Ypart[s * len + o + Pp];
         }
-        const double rx = L[o], gx = L[o + Pp];
-        const double dk = kar * rx;
-        const double dw = omr * rx + omg * gx;
-        const double loc_r = U * dk + W * dw + rx * (kar * U + omr * W)
-                           + r * (Ai * kar * dk + Bi * (kar * dw + omr * dk) + Ci * omr * dw)
-                           + r * (karr * rx * U + (omrr * rx + omrg * gx) * W);
-        const double loc_g = rx * omg * W + r * (Bi * omg * dk + Ci * omg * dw)
-                           + r * (omrg * rx + omgg * gx) * W;
-        const double Yr = yp + r * omr * yq + loc_r;
-        const double Yg = r * omg * yq + loc_g;
+        double Yr, Yg;
+        point_response(f, L[o], L[o + Pp], yp, yq, Yr, Yg);
         const int a = x % 3;
         const bool self = x / 3 == A;
         const double o0 = a == 0 ? own0[0] : (a == 1 ? own0[1] : own0[2]);
         const double o1 = a == 0 ? own1[0] : (a == 1 ? own1[1] : own1[2]);
         const double zp = self ? o0 : z0[x];
         const double zq = self ? o1 : z1[x];
-        const double Zr = zp + r * omr * zq, Zg = r * omg * zq;
-        *y0 = w * (Yr + 2.0 * Zr);
-        *y1 = w * (Yg + 2.0 * Zg);
+        const double Zr = zp + f.r * f.omr * zq, Zg = f.r * f.omg * zq;
+        *y0 = f.w * (Yr + 2.0 * Zr);
+        *y1 = f.w * (Yg + 2.0 * Zg);
         if (resp_rho) resp_rho[(int64_t)x * n + i] = Yr;
         if (resp_gamma) resp_gamma[(int64_t)x * n + i] = Yg;
+    }
+}
+
+// Trial-density response: f^{rho,t}_i = Yr, f^{gamma,t}_i = Yg of
+// point_response for every trial column t (the perturbation packing wrote
+// L = (rho^t, 2 grad rho . grad rho^t), which carries the factor 2 of the
+// gamma terms).  32 points x 64 columns per workgroup, transposed through
+// LDS so that the [n_t][N] outputs are written along points.
+constexpr int TRI = 32, TRX = 64;
+template <typename T>
+__global__ __launch_bounds__(256) void k_trial_resp(
+    int64_t n, int64_t npad, int32_t P, int32_t Pp, int32_t S, const double *__restrict__ F,
+    const double *__restrict__ I, const double *__restrict__ L, const T *__restrict__ Ypart,
+    double *__restrict__ f_rho_t, double *__restrict__ f_gamma_t) {
+    __shared__ double sR[TRI][TRX + 1], sG[TRI][TRX + 1];
+    const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+    const int64_t i0 = (int64_t)blockIdx.x * TRI;
+    const int x = blockIdx.y * TRX + tx;
+    const int64_t len = npad * 2 * Pp;
+    for (int rr = ty; rr < TRI; rr += 4) {
+        const int64_t i = i0 + rr;
+        double Yr = 0.0, Yg = 0.0;
+        if (i < n && x < P) {
+            const int64_t o = (i * 2) * Pp + x;
+            double yp = (double)Ypart[o], yq = (double)Ypart[o + Pp];
+            for (int s = 1; s < S; ++s) {
+                yp += (double)Ypart[s * len + o];
+                yq += (double)Ypart[s * len + o + Pp];
+            }
+            point_response(point_fields(F, I, npad, i), L[o], L[o + Pp], yp, yq, Yr, Yg);
+        }
+        sR[rr][tx] = Yr;
+        sG[rr][tx] = Yg;
+    }
+    __syncthreads();
+    const int il = tid & (TRI - 1);
+    for (int c = tid / TRI; c < TRX; c += 256 / TRI) {
+        const int xx = blockIdx.y * TRX + c;
+        const int64_t i = i0 + il;
+        if (xx < P && i < n) {
+            f_rho_t[(int64_t)xx * n + i] = sR[il][c];
+            f_gamma_t[(int64_t)xx * n + i] = sG[il][c];
+        }
     }
 }
 
@@ -271,6 +341,20 @@ __global__ __launch_bounds__(256) void k_finish(int32_t n_atom, int32_t P, int32
 }
 
 }  // namespace
+
+hipError_t launch_trial_response(vv10_plan *p, double *f_rho_t, double *f_gamma_t) {
+    const Workspace &ws = p->rws;
+    dim3 grid((unsigned)((p->n + TRI - 1) / TRI), (unsigned)((ws.P + TRX - 1) / TRX));
+    if (p->prec == VV10_FP64)
+        k_trial_resp<double><<<grid, 256, 0, p->stream>>>(
+            p->n, p->npad, ws.P, ws.Pp, ws.jsplit, p->F, p->Ir, ws.L,
+            static_cast<const double *>(ws.Ypart), f_rho_t, f_gamma_t);
+    else
+        k_trial_resp<float><<<grid, 256, 0, p->stream>>>(
+            p->n, p->npad, ws.P, ws.Pp, ws.jsplit, p->F, p->Ir, ws.L,
+            static_cast<const float *>(ws.Ypart), f_rho_t, f_gamma_t);
+    return hipGetLastError();
+}
 
 hipError_t launch_assemble(vv10_plan *p, double *hess, double *grad, double *resp_rho,
                            double *resp_gamma) {

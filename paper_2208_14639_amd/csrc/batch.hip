@@ -70,7 +70,7 @@ hipError_t enqueue_batch(vv10_batch *b, const double *rho_x, const double *grad_
         p->stream = b->side[m % K];
         e = vv10::launch_grid_terms(p);
         if (e == hipSuccess) e = vv10::launch_potential(p, energy + m, nullptr, nullptr);
-        if (e == hipSuccess) e = vv10::launch_pert_prep(p, rho_x + b->rx_off[m], grad_rho_x + b->gx_off[m]);
+        if (e == hipSuccess) e = vv10::launch_pert_prep(p, p->ws, rho_x + b->rx_off[m], grad_rho_x + b->gx_off[m]);
     }
     for (int k = 0; k < K && e == hipSuccess; ++k) {
         e = hipEventRecord(b->ev[1 + k], b->side[k]);

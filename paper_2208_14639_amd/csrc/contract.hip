@@ -433,8 +433,7 @@ __global__ __launch_bounds__(256, 2) void k_contract_bf16x3(int64_t npad, int64_
 }
 
 template <int NCB>
-hipError_t run(vv10_plan *p) {
-    const Workspace &ws = p->ws;
+hipError_t run(vv10_plan *p, const Workspace &ws) {
     dim3 grid((unsigned)(p->npad / 64), (unsigned)ws.ngroups, (unsigned)ws.jsplit);
     if (p->prec == VV10_FP64) {
         if constexpr (NCB <= 8)
@@ -575,9 +574,9 @@ int contract_blocks_per_cu(vv10_precision prec, int ncb) {
     return dispatch_ncb(ncb, [&](auto c) { return occupancy<decltype(c)::value>(prec); });
 }
 
-hipError_t launch_contract(vv10_plan *p) {
-    if (p->ws.ncb < 1 || p->ws.ncb > max_ncb(p->prec)) return hipErrorInvalidValue;
-    return dispatch_ncb(p->ws.ncb, [&](auto c) { return run<decltype(c)::value>(p); });
+hipError_t launch_contract(vv10_plan *p, const Workspace &ws) {
+    if (ws.ncb < 1 || ws.ncb > max_ncb(p->prec)) return hipErrorInvalidValue;
+    return dispatch_ncb(ws.ncb, [&](auto c) { return run<decltype(c)::value>(p, ws); });
 }
 
 }  // namespace vv10

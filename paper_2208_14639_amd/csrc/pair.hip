@@ -171,11 +171,11 @@ int pair_splits(int64_t npad) {
     return S;
 }
 
-hipError_t launch_pair_integrals(vv10_plan *p, bool hessian_mode) {
+hipError_t launch_pair_integrals(vv10_plan *p, bool hessian_mode, double *I_out) {
     const int S = pair_splits(p->npad);
     const int64_t jlen = ((p->npad / S + JC - 1) / JC) * JC;
     dim3 grid((unsigned)(p->npad / 64), (unsigned)S);
-    double *Ipart = S == 1 ? p->I : p->Ipart;
+    double *Ipart = S == 1 ? I_out : p->Ipart;
     if (p->prec == VV10_FP64) {
         if (hessian_mode)
             k_pair<double, double4, true><<<grid, 256, 0, p->stream>>>(p->npad, jlen, p->P0, p->P1, Ipart);
@@ -190,7 +190,7 @@ hipError_t launch_pair_integrals(vv10_plan *p, bool hessian_mode) {
     if (S > 1) {
         const int nout = hessian_mode ? 6 : 3;
         const int64_t tot = (int64_t)nout * p->npad;
-        k_sum_integrals<<<(unsigned)((tot + 255) / 256), 256, 0, p->stream>>>(p->npad, nout, S, Ipart, p->I);
+        k_sum_integrals<<<(unsigned)((tot + 255) / 256), 256, 0, p->stream>>>(p->npad, nout, S, Ipart, I_out);
     }
     return hipGetLastError();
 }

@@ -214,8 +214,8 @@ hipError_t launch_prepare(vv10_plan *p, const double *coords, const double *w,
     return hipGetLastError();
 }
 
-hipError_t launch_pert_prep(vv10_plan *p, const double *rho_x, const double *grad_rho_x) {
-    const Workspace &ws = p->ws;
+hipError_t launch_pert_prep(vv10_plan *p, const Workspace &ws, const double *rho_x,
+                            const double *grad_rho_x) {
     dim3 grid((unsigned)((p->npad + TT - 1) / TT), (unsigned)((ws.Pp + TT - 1) / TT));
     if (p->prec == VV10_FP64)
         k_pert_prep<VV10_FP64><<<grid, 256, 0, p->stream>>>(p->n, p->npad, ws.P, ws.Pp, rho_x,

@@ -17,8 +17,8 @@ namespace vv10 {
 
 void plan_workspace_shape(int64_t npad, int32_t n_atom, int32_t ntiles, int num_cu,
                           vv10_precision prec, Workspace &ws, int32_t jsplit_override,
-                          int32_t bgroups_override) {
-    ws.P = 3 * n_atom;
+                          int32_t bgroups_override, int32_t n_cols) {
+    ws.P = n_cols > 0 ? n_cols : 3 * n_atom;
     const int ncb_total = (ws.P + 15) / 16;
     const int cap = max_ncb(prec);
     ws.ngroups = (ncb_total + cap - 1) / cap;
@@ -70,6 +70,15 @@ size_t workspace_bytes(int64_t npad, int32_t n_atom, int32_t ntiles, vv10_precis
     b += (size_t)ws.bgroups * NI * npad * sizeof(double);
     b += (size_t)(ws.gsplit + 1) * (ws.Pp + 1) * ws.Pp * sizeof(double);
     b += (size_t)n_atom * n_atom * 9 * sizeof(double);
+    return b;
+}
+
+size_t response_bytes(int64_t npad, vv10_precision prec, const Workspace &ws) {
+    const size_t ch = (size_t)npad * 2 * ws.Pp;
+    size_t b = ch * sizeof(double);                           // L
+    b += ch * (prec == VV10_FP64 ? 8 : 4);                    // X
+    b += (size_t)ws.jsplit * ch * partial_elem(prec);         // partials
+    b += (size_t)NI * npad * sizeof(double);                  // pair integrals
     return b;
 }
 
@@ -146,6 +155,8 @@ void free_plan(vv10_plan *p) {
     for (auto &ev : p->ev)
         if (ev) give_event(p->device, ev);
     free_workspace(p->ws);
+    free_workspace(p->rws);
+    dfree(p->Ir);
     dfree(p->P0);
     dfree(p->P1);
     dfree(p->P0f);
@@ -213,6 +224,39 @@ vv10_status vv10::ensure_workspace(vv10_plan *p) {
     }
     ws.bytes = vv10::workspace_bytes(p->npad, p->n_atom, p->ntiles, p->prec, ws);
     p->ws = ws;
+    return VV10_OK;
+}
+
+// Allocate the trial-response workspace for n_t columns (rebuilt when n_t
+// changes) and the response's pair-integral table.
+static vv10_status ensure_response_workspace(vv10_plan *p, int32_t n_t) {
+    if (!p->Ir) {
+        if (dalloc(&p->Ir, (size_t)vv10::NI * p->npad) != hipSuccess) {
+            (void)hipGetLastError();
+            return VV10_E_OOM;
+        }
+        p->ir_ready = false;
+    }
+    if (p->rws.X && p->rws.P == n_t) return VV10_OK;
+    free_workspace(p->rws);
+    Workspace ws;
+    vv10::plan_workspace_shape(p->npad, p->n_atom, p->ntiles, p->num_cu, p->prec, ws, 0, 0, n_t);
+    if (injected_alloc_failure()) return VV10_E_OOM;
+    const size_t ch = (size_t)p->npad * 2 * ws.Pp;
+    hipError_t e = hipSuccess;
+    char *xb = nullptr, *yp = nullptr;
+    e = dalloc(&xb, ch * (p->prec == VV10_FP64 ? 8 : 4));
+    ws.X = xb;
+    if (e == hipSuccess) e = dalloc(&ws.L, ch);
+    if (e == hipSuccess) e = dalloc(&yp, ch * ws.jsplit * vv10::partial_elem(p->prec));
+    ws.Ypart = yp;
+    if (e != hipSuccess) {
+        free_workspace(ws);
+        (void)hipGetLastError();
+        return hip_status(e);
+    }
+    ws.bytes = vv10::response_bytes(p->npad, p->prec, ws);
+    p->rws = ws;
     return VV10_OK;
 }
 
@@ -377,7 +421,7 @@ vv10_status vv10_energy_potential(vv10_plan *p, double *energy, double *f_rho, d
     if (!p) return VV10_E_STATE;
     if (p->failed) return VV10_E_STATE;
     if (!energy) return VV10_E_ARG;
-    hipError_t e = stage(p, VV10_STAGE_PAIR, [&] { return vv10::launch_pair_integrals(p, false); });
+    hipError_t e = stage(p, VV10_STAGE_PAIR, [&] { return vv10::launch_pair_integrals(p, false, p->I); });
     if (e == hipSuccess)
         e = stage(p, VV10_STAGE_POTENTIAL, [&] { return vv10::launch_potential(p, energy, f_rho, f_gamma); });
     if (e != hipSuccess) {
@@ -401,8 +445,8 @@ vv10_status vv10_hessian_terms(vv10_plan *p, int32_t n_pert, const double *rho_x
     if (e == hipSuccess)
         e = stage(p, VV10_STAGE_POTENTIAL, [&] { return vv10::launch_potential(p, nullptr, nullptr, nullptr); });
     if (e == hipSuccess)
-        e = stage(p, VV10_STAGE_PERT_PREP, [&] { return vv10::launch_pert_prep(p, rho_x, grad_rho_x); });
-    if (e == hipSuccess) e = stage(p, VV10_STAGE_CONTRACT, [&] { return vv10::launch_contract(p); });
+        e = stage(p, VV10_STAGE_PERT_PREP, [&] { return vv10::launch_pert_prep(p, p->ws, rho_x, grad_rho_x); });
+    if (e == hipSuccess) e = stage(p, VV10_STAGE_CONTRACT, [&] { return vv10::launch_contract(p, p->ws); });
     if (e == hipSuccess)
         e = stage(p, VV10_STAGE_ASSEMBLE,
                   [&] { return vv10::launch_assemble(p, hess, grad, resp_rho, resp_gamma); });
@@ -412,6 +456,42 @@ vv10_status vv10_hessian_terms(vv10_plan *p, int32_t n_pert, const double *rho_x
         return VV10_E_HIP;
     }
     return VV10_OK;
+}
+
+vv10_status vv10_trial_response(vv10_plan *p, int32_t n_t, const double *rho_t,
+                                const double *grad_rho_t, double *f_rho_t, double *f_gamma_t) {
+    if (!p) return VV10_E_STATE;
+    if (p->failed) return VV10_E_STATE;
+    if (n_t < 0 || n_t > VV10_MAX_TRIAL) return VV10_E_ARG;
+    if (n_t == 0) return VV10_OK;
+    if (!rho_t || !grad_rho_t || !f_rho_t || !f_gamma_t) return VV10_E_ARG;
+    const vv10_status st = ensure_response_workspace(p, n_t);
+    if (st != VV10_OK) return st;
+    hipError_t e = hipSuccess;
+    if (!p->ir_ready) {
+        e = stage(p, VV10_STAGE_PAIR, [&] { return vv10::launch_pair_integrals(p, true, p->Ir); });
+        if (e == hipSuccess) p->ir_ready = true;
+    }
+    if (e == hipSuccess)
+        e = stage(p, VV10_STAGE_PERT_PREP, [&] { return vv10::launch_pert_prep(p, p->rws, rho_t, grad_rho_t); });
+    if (e == hipSuccess) e = stage(p, VV10_STAGE_CONTRACT, [&] { return vv10::launch_contract(p, p->rws); });
+    if (e == hipSuccess)
+        e = stage(p, VV10_STAGE_ASSEMBLE, [&] { return vv10::launch_trial_response(p, f_rho_t, f_gamma_t); });
+    if (e != hipSuccess) {
+        p->failed = true;
+        (void)hipGetLastError();
+        return VV10_E_HIP;
+    }
+    return VV10_OK;
+}
+
+size_t vv10_response_footprint_bytes(int64_t n_grid, int32_t n_t, vv10_precision prec) {
+    if (n_grid < 1 || n_t < 1) return 0;
+    const int64_t npad = ((n_grid + vv10::kPad - 1) / vv10::kPad) * vv10::kPad;
+    Workspace ws;
+    vv10::plan_workspace_shape(npad, 1, 1, 256, prec, ws, 0, 0, n_t);
+    ws.jsplit = std::max(ws.jsplit, 16);   // upper bound over devices and occupancies
+    return vv10::response_bytes(npad, prec, ws);
 }
 
 vv10_status vv10_set_tiles(vv10_plan *p, const vv10_tiles *t) {

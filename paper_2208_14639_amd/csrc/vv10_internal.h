@@ -99,6 +99,13 @@ struct vv10_plan {
     bool ran[VV10_NUM_STAGES] = {};
 
     vv10::Workspace ws;
+
+    // trial-density response (vv10_trial_response): a workspace for its n_t
+    // columns (X, L, partials only) and the Hessian-mode pair integrals
+    // E..C, computed by its first call and kept
+    vv10::Workspace rws;
+    double *Ir = nullptr;    // [6][npad]
+    bool ir_ready = false;
 };
 
 namespace vv10 {
@@ -133,18 +140,24 @@ int pair_splits(int64_t npad);
 hipError_t launch_prepare(vv10_plan *p, const double *coords, const double *w,
                           const int32_t *atom_of, const double *rho,
                           const double *grad_rho);
-hipError_t launch_pair_integrals(vv10_plan *p, bool hessian_mode);
+hipError_t launch_pair_integrals(vv10_plan *p, bool hessian_mode, double *I_out);
 hipError_t launch_potential(vv10_plan *p, double *energy, double *f_rho, double *f_gamma);
-hipError_t launch_pert_prep(vv10_plan *p, const double *rho_x, const double *grad_rho_x);
-hipError_t launch_contract(vv10_plan *p);
+hipError_t launch_pert_prep(vv10_plan *p, const Workspace &ws, const double *rho_x,
+                            const double *grad_rho_x);
+hipError_t launch_contract(vv10_plan *p, const Workspace &ws);
 hipError_t launch_grid_terms(vv10_plan *p);
+hipError_t launch_trial_response(vv10_plan *p, double *f_rho_t, double *f_gamma_t);
 hipError_t launch_assemble(vv10_plan *p, double *hess, double *grad, double *resp_rho,
                            double *resp_gamma);
 
 // Layout decisions shared by the host code.
+// n_cols: contraction columns (0 = the 3 n_atom nuclear perturbations).
 void plan_workspace_shape(int64_t npad, int32_t n_atom, int32_t ntiles, int num_cu,
                           vv10_precision prec, Workspace &ws, int32_t jsplit_override = 0,
-                          int32_t bgroups_override = 0);
+                          int32_t bgroups_override = 0, int32_t n_cols = 0);
+// Bytes of the trial-response workspace (X, L and partials for n_t columns)
+// plus its pair-integral table.
+size_t response_bytes(int64_t npad, vv10_precision prec, const Workspace &ws);
 // Allocate the Hessian workspace of a plan (no-op when it exists).
 vv10_status ensure_workspace(vv10_plan *p);
 size_t workspace_bytes(int64_t npad, int32_t n_atom, int32_t ntiles, vv10_precision prec,

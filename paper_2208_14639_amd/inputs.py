@@ -241,6 +241,29 @@ def displaced(p: Problem, atom: int, axis: int, h: float, with_derivatives=False
     return build_problem(mol, p.atom_of, p.offsets, p.radii, with_derivatives, p.seed)
 
 
+def trial_densities(p: Problem, n_t: int, seed: int, scale: float = 0.2):
+    """n_t seeded trial densities with analytic gradients, [n_t, N] and [n_t, N, 3].
+
+    Each is sum_A (c_tA + (r - R_A) . v_tA) f_A(r), with f_A the atom's term of
+    the model density and c_tA, v_tA normal with standard deviation `scale`:
+    charge moved between atoms and each atom polarised, the shapes a
+    first-order density response takes.  Values of either sign."""
+    rng = np.random.default_rng(seed)
+    mol = p.mol
+    n = p.n_grid
+    c = rng.standard_normal((n_t, mol.n_atom)) * scale
+    v = rng.standard_normal((n_t, mol.n_atom, 3)) * scale
+    rt = np.zeros((n_t, n))
+    gt = np.zeros((n_t, n, 3))
+    for A in range(mol.n_atom):
+        f, g, _ = _slater_terms(mol, A, p.coords, 1)
+        d = p.coords - mol.R[A]
+        s = c[:, A][:, None] + v[:, A, :] @ d.T              # [n_t, N]
+        rt += s * f[None, :]
+        gt += s[:, :, None] * g[None, :, :] + f[None, :, None] * v[:, A, None, :]
+    return np.ascontiguousarray(rt), np.ascontiguousarray(gt)
+
+
 def random_cluster_sizes(n_mol: int, seed: int, lo: int = 1, hi: int = 30):
     rng = np.random.default_rng(seed)
     return [int(k) for k in rng.integers(lo, hi + 1, size=n_mol)]

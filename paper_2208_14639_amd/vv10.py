@@ -67,6 +67,10 @@ def load() -> ctypes.CDLL:
     lib.vv10_hessian_terms.argtypes = [P, i32, P, P, P, P, P, P]
     lib.vv10_footprint_bytes.restype = ctypes.c_size_t
     lib.vv10_footprint_bytes.argtypes = [i64, i32, st]
+    lib.vv10_trial_response.restype = st
+    lib.vv10_trial_response.argtypes = [P, i32, P, P, P, P]
+    lib.vv10_response_footprint_bytes.restype = ctypes.c_size_t
+    lib.vv10_response_footprint_bytes.argtypes = [i64, i32, st]
     lib.vv10_destroy.restype = None
     lib.vv10_destroy.argtypes = [P]
     lib.vv10_status_string.restype = ctypes.c_char_p
@@ -163,6 +167,17 @@ def vv10_hessian_terms(plan: int, n_pert: int, rho_x, grad_rho_x, hess, grad=Non
                                    _ptr(grad), _ptr(resp_rho), _ptr(resp_gamma))
     if st != VV10_OK:
         raise VV10Error(st, "vv10_hessian_terms")
+
+
+def vv10_trial_response(plan: int, n_t: int, rho_t, grad_rho_t, f_rho_t, f_gamma_t) -> None:
+    st = load().vv10_trial_response(plan, n_t, _ptr(rho_t), _ptr(grad_rho_t), _ptr(f_rho_t),
+                                    _ptr(f_gamma_t))
+    if st != VV10_OK:
+        raise VV10Error(st, "vv10_trial_response")
+
+
+def vv10_response_footprint_bytes(n_grid: int, n_t: int, prec: int = VV10_FP64) -> int:
+    return int(load().vv10_response_footprint_bytes(n_grid, n_t, prec))
 
 
 def vv10_set_tiles(plan: int, jsplit: int = 0, bgroups: int = 0) -> None:
@@ -315,6 +330,17 @@ class Plan:
         if resp:
             out["resp_rho"], out["resp_gamma"] = rr, rg
         return out
+
+    def trial_response(self, rho_t, grad_rho_t):
+        """f^{rho,t}, f^{gamma,t} ([n_t, N] each) of n_t trial densities."""
+        t = self.torch
+        rt = rho_t if isinstance(rho_t, t.Tensor) and rho_t.is_cuda else self._dev(rho_t)
+        gt = grad_rho_t if isinstance(grad_rho_t, t.Tensor) and grad_rho_t.is_cuda else self._dev(grad_rho_t)
+        n_t = int(rt.shape[0])
+        fr = t.empty((n_t, self.n), dtype=t.float64, device=self.device)
+        fg = t.empty((n_t, self.n), dtype=t.float64, device=self.device)
+        vv10_trial_response(self.handle, n_t, rt, gt, fr, fg)
+        return fr, fg
 
     def close(self):
         if self.handle:

@@ -1,4 +1,6 @@
 """Checks of the seeded problem generator (no VV10 arithmetic here)."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -84,3 +86,22 @@ def test_translational_invariance_of_derivatives(small_dimer):
 def test_workload_sizes(name, n, P):
     p = inputs.make_workload(name, with_derivatives=False)
     assert p.n_grid == n and p.n_pert == P
+
+
+def test_trial_densities_gradient_and_seed():
+    """Trial densities: analytic gradient matches central differences of the
+    values, and the seed fixes them."""
+    p = inputs.make_problem(2, 30, 3, with_derivatives=False)
+    rt, gt = inputs.trial_densities(p, 3, 9)
+    rt2, gt2 = inputs.trial_densities(p, 3, 9)
+    assert np.array_equal(rt, rt2) and np.array_equal(gt, gt2)
+    assert rt.shape == (3, p.n_grid) and gt.shape == (3, p.n_grid, 3)
+    h = 1e-6
+    for k in (0, 17, 101):
+        for ax in range(3):
+            q1 = dataclasses.replace(p, coords=p.coords.copy())
+            q2 = dataclasses.replace(p, coords=p.coords.copy())
+            q1.coords[k, ax] += h
+            q2.coords[k, ax] -= h
+            d = (inputs.trial_densities(q1, 3, 9)[0][:, k] - inputs.trial_densities(q2, 3, 9)[0][:, k]) / (2 * h)
+            assert np.allclose(d, gt[:, k, ax], rtol=1e-6, atol=1e-9)

@@ -244,6 +244,28 @@ def test_response_rows_match_matrices(tiny_problem):
     assert np.max(np.abs(Yg - Yg2)) <= 1e-12 * np.max(np.abs(Yg2))
 
 
+def test_trial_response_is_potential_derivative(small_dimer):
+    """f^{rho,t}_i = sum_j w_j (f^{rho rho}_ij rho^t_j + 2 f^{rho gamma}_ij gamma^t_j) and
+    f^{gamma,t}_i likewise, gamma^t = grad rho . grad rho^t (Section II.B, the
+    contracted orbital-Hessian response): the derivatives of the potential f^rho,
+    f^gamma along rho + h rho^t, grad rho + h grad rho^t.  The oracle's response
+    rows with gamma channel 2 grad rho . grad rho^t must match central differences
+    of its potential."""
+    p = small_dimer
+    rt, gt = inputs.trial_densities(p, 2, 5)
+    g = oracle.gamma(p.grad_rho)
+    Yr, Yg = oracle.response_rows(0, p.n_grid, p.coords, p.weights, p.rho, g, p.b, p.C, rt,
+                                  oracle.gamma_x(p.grad_rho, gt))
+    for t in range(2):
+        h = 2e-3 / np.max(np.abs(rt[t]) / p.rho)          # rho + h rho^t stays positive
+        pot = lambda e: np.concatenate(_ep(p, rho=p.rho + e * rt[t],
+                                           gam=oracle.gamma(p.grad_rho + e * gt[t]))[1:])
+        d = richardson(pot, h)
+        n = p.n_grid
+        for got, want in ((d[:n], Yr[t]), (d[n:], Yg[t])):
+            assert np.max(np.abs(got - want)) <= 1e-6 * np.max(np.abs(want))
+
+
 # --------------------------------------------------------------------------
 # Grid-position intermediates and nuclear derivatives (Sections II.A, II.B)
 # --------------------------------------------------------------------------
