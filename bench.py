@@ -145,6 +145,73 @@ def bench_batch(args, torch, np, inputs, vv10):
     print(json.dumps(out), flush=True)
 
 
+def bench_gradient(args, torch, np, inputs, vv10):
+    """Geometry-optimisation step on the hexamer: prepare, energy/potential and
+    the nuclear gradient alone (vv10_gradient), then destroy."""
+    p = inputs.make_workload("water_hexamer")
+    n, na, P = p.n_grid, p.n_atom, p.n_pert
+    dev = torch.device("cuda:0")
+    f64 = lambda a: torch.as_tensor(a, dtype=torch.float64).to(dev).contiguous()
+    coords, w, rho, grad = f64(p.coords), f64(p.weights), f64(p.rho), f64(p.grad_rho)
+    atom_of = torch.as_tensor(p.atom_of, dtype=torch.int32).to(dev).contiguous()
+    rho_x, grad_x = f64(p.rho_x), f64(p.grad_rho_x)
+    energy = torch.empty(1, dtype=torch.float64, device=dev)
+    gradient = torch.empty(P, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream().cuda_stream
+    prec = vv10.PRECISIONS[args.prec]
+
+    def step():
+        h = vv10.vv10_prepare(p.b, p.C, n, na, coords, w, atom_of, rho, grad, prec, stream)
+        try:
+            vv10.vv10_set_timing(h, True)
+            vv10.vv10_energy_potential(h, energy, None, None)
+            vv10.vv10_gradient(h, P, rho_x, grad_x, gradient)
+            st = vv10.vv10_stage_times(h)
+        finally:
+            vv10.vv10_destroy(h)
+        return st
+
+    for k in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stages = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        stages.append(step())
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    stage_ms = {k: float(np.mean([st[k] for st in stages])) for k in ("pair", "grid", "potential", "assemble")}
+    out = {
+        "metric": "VV10 Hessian grid-pair\u00b7perturbation/s, mixed vs FP64, at stated err; p99 latency",
+        "value": float(n) * n * P / dt, "unit": "pair*pert/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "f32+f64"}[args.prec],
+        "data": "synthetic",
+        "config": {"workload": "gradient_hexamer", "n_grid": n, "n_atom": na, "n_pert": P,
+                   "precision": args.prec, "seed": p.seed},
+        "roofline": None,
+        "stage_ms": stage_ms,
+        "grad_pass_pairs_per_s": float(n) * n / (stage_ms["grid"] * 1e-3),
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        g, gx = oracle.problem_inputs(p)
+        t0 = time.perf_counter()
+        G0 = oracle.gradient(p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b, p.C, p.rho_x, gx)
+        e0, _, _ = oracle.energy_potential(p.coords, p.weights, p.rho, g, p.b, p.C)
+        dtc = time.perf_counter() - t0
+        out["cpu_baseline"] = dict(value=float(n) * n * P / dtc, unit="pair*pert/s",
+                                   cores=oracle.num_threads(), kind="oracle", seconds=dtc,
+                                   sample=f"whole workload: energy, potential and gradient, N={n}")
+        Gg = gradient.cpu().numpy()
+        out["errors_vs_oracle"] = {"energy_rel": abs(energy.item() - e0) / abs(e0),
+                                   "grad_normwise": float(np.max(np.abs(Gg - G0)) / np.max(np.abs(G0)))}
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
 def bench_trial_response(args, torch, np, inputs, vv10, n_t=54):
     """CPSCF-style use of vv10_trial_response: the hexamer plan is prepared
     once, and every step evaluates f^{rho,t}, f^{gamma,t} of n_t seeded trial
@@ -288,7 +355,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="water_hexamer",
                     choices=["water_dimer", "water_hexamer", "water_20mer", "batch64", "served",
-                             "trial_response"],
+                             "trial_response", "gradient"],
                     help="batch64: 64 random clusters of 1-30 waters, 1500 points/atom, "
                          "one graph launch per step")
     ap.add_argument("--prec", default="bf16x3", choices=["fp64", "fp32", "bf16x3"],
@@ -321,6 +388,8 @@ def main():
         return bench_served(args, torch, np, inputs, vv10)
     if args.workload == "trial_response":
         return bench_trial_response(args, torch, np, inputs, vv10)
+    if args.workload == "gradient":
+        return bench_gradient(args, torch, np, inputs, vv10)
 
     from paper_2208_14639_amd import autotune
     p = inputs.make_workload(args.workload)

@@ -133,6 +133,23 @@ vv10_status vv10_hessian_terms(vv10_plan *plan, int32_t n_pert, const double *rh
                                const double *grad_rho_x, double *hess, double *grad,
                                double *resp_rho, double *resp_gamma);
 
+/*
+ * vv10_gradient -- VV10 nuclear gradient alone (Section II.A):
+ *   grad[x] = E^x_G + E^x_gr,
+ *   E^x_G  = sum_i w_i (f^rho_i rho^x_i + f^gamma_i gamma^x_i),  gamma^x = 2 grad rho . grad rho^x,
+ *   E^A_gr = sum_{i in A} w_i rho_i E^{Agr}_i = -sum_{B != A} sum_{i in A} w_i rho_i E^{Bgr}_i
+ * (the first form; weight derivatives zero).  Costs one pass over the pairs
+ * for E, U, W and the E^{Bgr} sums, without the Hessian contraction; the
+ * same value as the grad output of vv10_hessian_terms.
+ *  n_pert      must equal 3 n_atom.
+ *  rho_x       [n_pert][N] DEVICE, FP64 (as for vv10_hessian_terms).
+ *  grad_rho_x  [n_pert][N][3] DEVICE, FP64.
+ *  grad        [n_pert] DEVICE, FP64 output.
+ * Errors: VV10_E_ARG, VV10_E_OOM, VV10_E_STATE, VV10_E_HIP.
+ */
+vv10_status vv10_gradient(vv10_plan *plan, int32_t n_pert, const double *rho_x,
+                          const double *grad_rho_x, double *grad);
+
 /* Largest n_t accepted by vv10_trial_response. */
 #define VV10_MAX_TRIAL 65536
 

@@ -342,6 +342,54 @@ __global__ __launch_bounds__(256) void k_finish(int32_t n_atom, int32_t P, int32
 
 }  // namespace
 
+// Gradient (Section II.A, first form of the grid part): for x = 3 A + a,
+//   grad[x] = sum_i w_i (f^rho_i rho^x_i + f^gamma_i gamma^x_i)
+//           - sum_{B != A} sum_{tiles t of A} Gpart[t][B][a],
+// gamma^x = 2 grad rho . grad rho^x.  One workgroup per x; both sums are
+// fixed-order tree reductions, added at the end.
+__global__ __launch_bounds__(256) void k_gradient(int64_t n, int64_t npad, int32_t n_atom,
+                                                  const int32_t *__restrict__ tile_first,
+                                                  const double *__restrict__ F,
+                                                  const double *__restrict__ rho_x,
+                                                  const double *__restrict__ grad_rho_x,
+                                                  const double *__restrict__ Gpart,
+                                                  double *__restrict__ grad) {
+    __shared__ double sg[256], sr[256];
+    const int tid = threadIdx.x, x = blockIdx.x, A = x / 3, a = x % 3;
+    const double *rx = rho_x + (int64_t)x * n;
+    const double *gx = grad_rho_x + (int64_t)x * n * 3;
+    double eg = 0.0;
+    for (int64_t i = tid; i < n; i += 256) {
+        const double gam = 2.0 * (F[F_GX * npad + i] * gx[3 * i] + F[F_GY * npad + i] * gx[3 * i + 1] +
+                                  F[F_GZ * npad + i] * gx[3 * i + 2]);
+        eg += F[F_W * npad + i] * (F[F_FR * npad + i] * rx[i] + F[F_FG * npad + i] * gam);
+    }
+    const int t0 = tile_first[A], nt = tile_first[A + 1] - t0;
+    double gr = 0.0;
+    for (int k = tid; k < n_atom * nt; k += 256) {
+        const int B = k / nt, t = t0 + k % nt;
+        if (B != A) gr -= Gpart[((int64_t)t * n_atom + B) * 3 + a];
+    }
+    sg[tid] = eg;
+    sr[tid] = gr;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (tid < off) {
+            sg[tid] += sg[tid + off];
+            sr[tid] += sr[tid + off];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) grad[x] = sg[0] + sr[0];
+}
+
+hipError_t launch_gradient(vv10_plan *p, const double *rho_x, const double *grad_rho_x, double *grad) {
+    k_gradient<<<(unsigned)(3 * p->n_atom), 256, 0, p->stream>>>(p->n, p->npad, p->n_atom,
+                                                                 p->d_tile_first, p->F, rho_x,
+                                                                 grad_rho_x, p->gw.Gpart, grad);
+    return hipGetLastError();
+}
+
 hipError_t launch_trial_response(vv10_plan *p, double *f_rho_t, double *f_gamma_t) {
     const Workspace &ws = p->rws;
     dim3 grid((unsigned)((p->n + TRI - 1) / TRI), (unsigned)((ws.P + TRX - 1) / TRX));

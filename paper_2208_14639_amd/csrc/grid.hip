@@ -209,17 +209,93 @@ __global__ __launch_bounds__(64) void k_grid(
     }
 }
 
-// I[k][i] = sum over atom groups of Ipart[grp][k][i] (group order), i < n.
-__global__ __launch_bounds__(256) void k_sum_groups(int64_t n, int64_t npad, int G,
+// I[k][i] = sum over atom groups of Ipart[grp][k][i] (group order), k < nrows, i < n.
+__global__ __launch_bounds__(256) void k_sum_groups(int64_t n, int64_t npad, int G, int nrows,
                                                     const double *__restrict__ Ipart,
                                                     double *__restrict__ I) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= (int64_t)NI * n) return;
+    if (e >= (int64_t)nrows * n) return;
     const int k = (int)(e / n);
     const int64_t i = e - (int64_t)k * n;
     double a = 0.0;
-    for (int gidx = 0; gidx < G; ++gidx) a += Ipart[((int64_t)gidx * NI + k) * npad + i];
+    for (int gidx = 0; gidx < G; ++gidx) a += Ipart[((int64_t)gidx * nrows + k) * npad + i];
     I[k * npad + i] = a;
+}
+
+// Gradient pass (Section II.A): the pair integrals E, U, W of every outer
+// point (over all j) and, per tile t of outer points (atom A) and atom
+// B != A, Gpart[t][B][a] = sum_{i in t} a_i E^{Bgr}_{i,a} (zero for B = A),
+// from which the grid part of the gradient follows,
+// E_gr = -sum_{B != A} sum_{i in A} a_i E^{Bgr}_i (translational invariance).
+// The layout and the scaled sums are those of k_grid: E^{Bgr}_i = 3 sum_j p T d.
+template <typename T, typename T4>
+__global__ __launch_bounds__(64) void k_grid_grad(
+    int32_t n_atom, int32_t bgroups, int64_t npad, const int64_t *__restrict__ seg,
+    const int32_t *__restrict__ tile_i0, const int32_t *__restrict__ tile_n,
+    const int32_t *__restrict__ tile_atom, const T4 *__restrict__ P0,
+    const T4 *__restrict__ P1, double *__restrict__ Gpart, double *__restrict__ Ipart) {
+    __shared__ T4 sA[TG], sB[TG];
+    const int t = blockIdx.x, grp = blockIdx.y, lane = threadIdx.x;
+    const int A = tile_atom[t];
+    const int nt = tile_n[t];
+    const bool live = lane < nt;
+    const int64_t i = (int64_t)tile_i0[t] + (live ? lane : 0);
+    const T4 a0 = P0[i], a1 = P1[i];
+    const double ai = live ? (double)a1.y : 0.0;
+    const T oi = a0.w;
+    double pint[3] = {};
+    for (int B = grp; B < n_atom; B += bgroups) {
+        const int64_t jb = seg[B], je = seg[B + 1];
+        double acc[3] = {};
+        for (int64_t j0 = jb; j0 < je; j0 += TG) {
+            __syncthreads();
+            const int64_t j = j0 + lane;
+            sA[lane] = P0[j < je ? j : jb];
+            sB[lane] = P1[j < je ? j : jb];
+            __syncthreads();
+            const int cnt = (int)min((int64_t)TG, je - j0);
+            T pc[3] = {}, c[3] = {};
+            if (B == A) {
+#pragma unroll 4
+                for (int jj = 0; jj < cnt; ++jj) {
+                    const PairGeo<T> q = pair_geo<T>(a0, a1, sA[jj], sB[jj]);
+                    const T ph = q.p * q.h;
+                    pc[0] += q.p;
+                    pc[1] += ph;
+                    pc[2] += ph * q.R2;
+                }
+            } else {
+#pragma unroll 4
+                for (int jj = 0; jj < cnt; ++jj) {
+                    const T4 b0 = sA[jj];
+                    const PairGeo<T> q = pair_geo<T>(a0, a1, b0, sB[jj]);
+                    const T ph = q.p * q.h;
+                    pc[0] += q.p;
+                    pc[1] += ph;
+                    pc[2] += ph * q.R2;
+                    const T e = q.p * (oi * q.ig + b0.w * q.igp + (oi + b0.w) * q.is);
+                    c[0] += e * (b0.x - a0.x);
+                    c[1] += e * (b0.y - a0.y);
+                    c[2] += e * (b0.z - a0.z);
+                }
+#pragma unroll
+                for (int k = 0; k < 3; ++k) acc[k] += (double)c[k];
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) pint[k] += (double)pc[k];
+        }
+        double *gp = Gpart + ((int64_t)t * n_atom + B) * 3;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double tot = B == A ? 0.0 : wave_sum(ai * 3.0 * acc[k]);
+            if (lane == 0) gp[k] = tot;
+        }
+    }
+    if (live) {
+        const double sc[3] = {-1.5, 1.5, 1.5};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) Ipart[((int64_t)grp * 3 + k) * npad + i] = sc[k] * pint[k];
+    }
 }
 
 }  // namespace
@@ -236,8 +312,25 @@ hipError_t launch_grid_terms(vv10_plan *p) {
             p->n_atom, ws.Pp, ws.bgroups, p->npad, p->d_seg, p->d_tile_i0, p->d_tile_n,
             p->d_tile_atom, p->P0f, p->P1f, ws.Z, ws.Dpart, ws.Igrp);
     const int64_t tot = (int64_t)NI * p->n;
-    k_sum_groups<<<(unsigned)((tot + 255) / 256), 256, 0, p->stream>>>(p->n, p->npad, ws.bgroups,
+    k_sum_groups<<<(unsigned)((tot + 255) / 256), 256, 0, p->stream>>>(p->n, p->npad, ws.bgroups, NI,
                                                                        ws.Igrp, p->I);
+    return hipGetLastError();
+}
+
+hipError_t launch_grid_grad(vv10_plan *p) {
+    const GradWork &gw = p->gw;
+    dim3 grid((unsigned)p->ntiles, (unsigned)gw.bgroups);
+    if (p->prec == VV10_FP64)
+        k_grid_grad<double, double4><<<grid, TG, 0, p->stream>>>(
+            p->n_atom, gw.bgroups, p->npad, p->d_seg, p->d_tile_i0, p->d_tile_n, p->d_tile_atom,
+            p->P0, p->P1, gw.Gpart, gw.Igrp);
+    else
+        k_grid_grad<float, float4><<<grid, TG, 0, p->stream>>>(
+            p->n_atom, gw.bgroups, p->npad, p->d_seg, p->d_tile_i0, p->d_tile_n, p->d_tile_atom,
+            p->P0f, p->P1f, gw.Gpart, gw.Igrp);
+    const int64_t tot = (int64_t)3 * p->n;
+    k_sum_groups<<<(unsigned)((tot + 255) / 256), 256, 0, p->stream>>>(p->n, p->npad, gw.bgroups, 3,
+                                                                       gw.Igrp, p->I);
     return hipGetLastError();
 }
 

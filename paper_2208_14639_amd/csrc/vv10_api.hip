@@ -157,6 +157,8 @@ void free_plan(vv10_plan *p) {
     free_workspace(p->ws);
     free_workspace(p->rws);
     dfree(p->Ir);
+    dfree(p->gw.Gpart);
+    dfree(p->gw.Igrp);
     dfree(p->P0);
     dfree(p->P1);
     dfree(p->P0f);
@@ -257,6 +259,26 @@ static vv10_status ensure_response_workspace(vv10_plan *p, int32_t n_t) {
     }
     ws.bytes = vv10::response_bytes(p->npad, p->prec, ws);
     p->rws = ws;
+    return VV10_OK;
+}
+
+// Allocate the gradient-only pass's buffers (once per plan).
+static vv10_status ensure_gradient_work(vv10_plan *p) {
+    if (p->gw.Gpart) return VV10_OK;
+    Workspace ws;
+    vv10::plan_workspace_shape(p->npad, p->n_atom, p->ntiles, p->num_cu, p->prec, ws,
+                               p->tiles_jsplit, p->tiles_bgroups);
+    vv10::GradWork gw;
+    gw.bgroups = ws.bgroups;
+    hipError_t e = dalloc(&gw.Gpart, (size_t)p->ntiles * p->n_atom * 3);
+    if (e == hipSuccess) e = dalloc(&gw.Igrp, (size_t)gw.bgroups * 3 * p->npad);
+    if (e != hipSuccess) {
+        dfree(gw.Gpart);
+        dfree(gw.Igrp);
+        (void)hipGetLastError();
+        return hip_status(e);
+    }
+    p->gw = gw;
     return VV10_OK;
 }
 
@@ -450,6 +472,26 @@ vv10_status vv10_hessian_terms(vv10_plan *p, int32_t n_pert, const double *rho_x
     if (e == hipSuccess)
         e = stage(p, VV10_STAGE_ASSEMBLE,
                   [&] { return vv10::launch_assemble(p, hess, grad, resp_rho, resp_gamma); });
+    if (e != hipSuccess) {
+        p->failed = true;
+        (void)hipGetLastError();
+        return VV10_E_HIP;
+    }
+    return VV10_OK;
+}
+
+vv10_status vv10_gradient(vv10_plan *p, int32_t n_pert, const double *rho_x,
+                          const double *grad_rho_x, double *grad) {
+    if (!p) return VV10_E_STATE;
+    if (p->failed) return VV10_E_STATE;
+    if (n_pert != 3 * p->n_atom || !rho_x || !grad_rho_x || !grad) return VV10_E_ARG;
+    const vv10_status st = ensure_gradient_work(p);
+    if (st != VV10_OK) return st;
+    hipError_t e = stage(p, VV10_STAGE_GRID, [&] { return vv10::launch_grid_grad(p); });
+    if (e == hipSuccess)
+        e = stage(p, VV10_STAGE_POTENTIAL, [&] { return vv10::launch_potential(p, nullptr, nullptr, nullptr); });
+    if (e == hipSuccess)
+        e = stage(p, VV10_STAGE_ASSEMBLE, [&] { return vv10::launch_gradient(p, rho_x, grad_rho_x, grad); });
     if (e != hipSuccess) {
         p->failed = true;
         (void)hipGetLastError();

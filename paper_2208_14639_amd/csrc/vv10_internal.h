@@ -55,6 +55,13 @@ struct Workspace {
     size_t bytes = 0;
 };
 
+// Buffers of the gradient-only pass (vv10_gradient).
+struct GradWork {
+    int32_t bgroups = 0;
+    double *Gpart = nullptr;     // [ntiles][n_atom][3] tile sums of a_i E^{Bgr}_i
+    double *Igrp = nullptr;      // [bgroups][3][npad] E, U, W per atom group
+};
+
 }  // namespace vv10
 
 struct vv10_plan {
@@ -106,6 +113,9 @@ struct vv10_plan {
     vv10::Workspace rws;
     double *Ir = nullptr;    // [6][npad]
     bool ir_ready = false;
+
+    // gradient-only pass (vv10_gradient)
+    vv10::GradWork gw;
 };
 
 namespace vv10 {
@@ -146,6 +156,8 @@ hipError_t launch_pert_prep(vv10_plan *p, const Workspace &ws, const double *rho
                             const double *grad_rho_x);
 hipError_t launch_contract(vv10_plan *p, const Workspace &ws);
 hipError_t launch_grid_terms(vv10_plan *p);
+hipError_t launch_grid_grad(vv10_plan *p);
+hipError_t launch_gradient(vv10_plan *p, const double *rho_x, const double *grad_rho_x, double *grad);
 hipError_t launch_trial_response(vv10_plan *p, double *f_rho_t, double *f_gamma_t);
 hipError_t launch_assemble(vv10_plan *p, double *hess, double *grad, double *resp_rho,
                            double *resp_gamma);

@@ -67,6 +67,8 @@ def load() -> ctypes.CDLL:
     lib.vv10_hessian_terms.argtypes = [P, i32, P, P, P, P, P, P]
     lib.vv10_footprint_bytes.restype = ctypes.c_size_t
     lib.vv10_footprint_bytes.argtypes = [i64, i32, st]
+    lib.vv10_gradient.restype = st
+    lib.vv10_gradient.argtypes = [P, i32, P, P, P]
     lib.vv10_trial_response.restype = st
     lib.vv10_trial_response.argtypes = [P, i32, P, P, P, P]
     lib.vv10_response_footprint_bytes.restype = ctypes.c_size_t
@@ -167,6 +169,12 @@ def vv10_hessian_terms(plan: int, n_pert: int, rho_x, grad_rho_x, hess, grad=Non
                                    _ptr(grad), _ptr(resp_rho), _ptr(resp_gamma))
     if st != VV10_OK:
         raise VV10Error(st, "vv10_hessian_terms")
+
+
+def vv10_gradient(plan: int, n_pert: int, rho_x, grad_rho_x, grad) -> None:
+    st = load().vv10_gradient(plan, n_pert, _ptr(rho_x), _ptr(grad_rho_x), _ptr(grad))
+    if st != VV10_OK:
+        raise VV10Error(st, "vv10_gradient")
 
 
 def vv10_trial_response(plan: int, n_t: int, rho_t, grad_rho_t, f_rho_t, f_gamma_t) -> None:
@@ -330,6 +338,16 @@ class Plan:
         if resp:
             out["resp_rho"], out["resp_gamma"] = rr, rg
         return out
+
+    def gradient(self, rho_x, grad_rho_x):
+        """Nuclear gradient [3 n_atom] alone."""
+        t = self.torch
+        P = 3 * self.n_atom
+        rx = rho_x if isinstance(rho_x, t.Tensor) and rho_x.is_cuda else self._dev(rho_x)
+        gx = grad_rho_x if isinstance(grad_rho_x, t.Tensor) and grad_rho_x.is_cuda else self._dev(grad_rho_x)
+        g = t.empty(P, dtype=t.float64, device=self.device)
+        vv10_gradient(self.handle, P, rx, gx, g)
+        return g
 
     def trial_response(self, rho_t, grad_rho_t):
         """f^{rho,t}, f^{gamma,t} ([n_t, N] each) of n_t trial densities."""
