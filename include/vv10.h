@@ -110,6 +110,34 @@ vv10_status vv10_prepare(const vv10_params *params, int64_t n_grid, int32_t n_at
 vv10_status vv10_energy_potential(vv10_plan *plan, double *energy, double *f_rho,
                                   double *f_gamma);
 
+/* Outputs of vv10_nuclear_terms: each is DEVICE memory, FP64, or NULL (not
+ * formed); P = 3 n_atom, perturbation x = 3 A + alpha. */
+typedef struct {
+    double *hess;        /* [P][P] E_{G,G} + E_{G,gr} + E_{G,gr}^T + E_{gr,gr}, symmetrised */
+    double *grad;        /* [P] nuclear gradient E_G + E_gr (Section II.A) */
+    double *resp_rho;    /* [P][N] sum_j w_j (f^{rho rho}_ij rho^x_j + f^{rho gamma}_ij gamma^x_j) */
+    double *resp_gamma;  /* [P][N] sum_j w_j (f^{gamma rho}_ij rho^x_j + f^{gamma gamma}_ij gamma^x_j) */
+    double *fock_rho;    /* [P][N] resp_rho + E^{Agr}_i + rho_i (kappa_r U^{Agr}_i + omega_r W^{Agr}_i) */
+    double *fock_gamma;  /* [P][N] resp_gamma + rho_i omega_g W^{Agr}_i */
+} vv10_nuclear_outputs;
+
+/*
+ * vv10_nuclear_terms -- every nuclear-perturbation output of one pass over
+ * the pairs (Section II.B): the Hessian terms (below), the gradient, the
+ * response rows, and the grid-level coefficients of the Fock nuclear
+ * derivative F^A_{mu nu} = F^A_G + F^A_gr (weight terms zero): fock_rho
+ * multiplies w_i phi_mu phi_nu and fock_gamma multiplies
+ * 2 w_i grad rho . grad(phi_mu phi_nu) in the second line of F^A_G plus
+ * F^A_gr; the first line of F^A_G (f^rho, f^gamma times basis-function
+ * derivatives) belongs to the caller.  fock_rho/fock_gamma equal the
+ * derivative of the potential f^rho, f^gamma when nucleus A moves with its
+ * grid points.  Outputs set to NULL are not formed (no output: no work).
+ *  n_pert, rho_x, grad_rho_x as for vv10_hessian_terms; out non-NULL.
+ * Errors: VV10_E_ARG, VV10_E_OOM (workspace), VV10_E_STATE, VV10_E_HIP.
+ */
+vv10_status vv10_nuclear_terms(vv10_plan *plan, int32_t n_pert, const double *rho_x,
+                               const double *grad_rho_x, const vv10_nuclear_outputs *out);
+
 /*
  * vv10_hessian_terms -- nuclear-Hessian grid terms for all 3 n_atom
  * perturbations at once (Section II.B, nine-term split with the weight
@@ -127,6 +155,7 @@ vv10_status vv10_energy_potential(vv10_plan *plan, double *energy, double *f_rho
  *  grad        [n_pert] or NULL: nuclear gradient E_G + E_gr (Section II.A).
  *  resp_rho    [n_pert][N] or NULL: sum_j w_j (f^{rho rho}_ij rho^x_j + f^{rho gamma}_ij gamma^x_j).
  *  resp_gamma  [n_pert][N] or NULL: sum_j w_j (f^{gamma rho}_ij rho^x_j + f^{gamma gamma}_ij gamma^x_j).
+ * (vv10_nuclear_terms with these outputs.)
  * Errors: VV10_E_ARG, VV10_E_OOM (workspace), VV10_E_STATE, VV10_E_HIP.
  */
 vv10_status vv10_hessian_terms(vv10_plan *plan, int32_t n_pert, const double *rho_x,

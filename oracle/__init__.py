@@ -210,6 +210,32 @@ def hessian_terms(atom_of, n_atom, coords, w, rho, gam, b, C, rho_x, gam_x,
     return H, info
 
 
+def fock_nuclear_terms(atom_of, n_atom, coords, w, rho, gam, b, C, rho_x, gam_x):
+    """Grid-level coefficients of the VV10 Fock nuclear derivative (Section II.B,
+    the second line of F^A_{mu nu,G} and F^A_{mu nu,gr}; weight terms zero): for
+    perturbation x = 3 B + a and point i,
+      v_rho[x][i]   = sum_j w_j (f^{rho rho}_ij rho^x_j + f^{rho gamma}_ij gamma^x_j)
+                      + E^{Bgr}_{i,a} + rho_i (kappa_r U^{Bgr}_{i,a} + omega_r W^{Bgr}_{i,a})
+      v_gamma[x][i] = sum_j w_j (f^{gamma rho}_ij rho^x_j + f^{gamma gamma}_ij gamma^x_j)
+                      + rho_i omega_g W^{Bgr}_{i,a}
+    (the coefficients of w_i phi_mu phi_nu and of 2 w_i grad rho . grad(phi_mu phi_nu)),
+    with the own-atom slot of E/U/W^{Bgr} from translational invariance."""
+    n = len(w)
+    Yr, Yg = response_rows(0, n, coords, w, rho, gam, b, C, rho_x, gam_x)
+    E, U, W = grid_vectors(atom_of, n_atom, coords, w, rho, gam, b, C)
+    kr, orr, og = np.zeros(n), np.zeros(n), np.zeros(n)
+    for i in range(n):
+        pt = point(b, C, float(rho[i]), float(gam[i]))
+        kr[i], orr[i], og[i] = pt["kappa_r"], pt["omega_r"], pt["omega_g"]
+    P = 3 * n_atom
+    vr, vg = Yr.copy(), Yg.copy()
+    for x in range(P):
+        B, a = divmod(x, 3)
+        vr[x] += E[:, B, a] + rho * (kr * U[:, B, a] + orr * W[:, B, a])
+        vg[x] += rho * og * W[:, B, a]
+    return vr, vg
+
+
 def problem_inputs(p):
     """(gamma, gamma^x) of an inputs.Problem via the oracle's own definitions."""
     g = gamma(p.grad_rho)

@@ -16,6 +16,8 @@
 //    the grid channels Zr = Z_p + rho omega_r Z_q, Zg = rho omega_g Z_q (the
 //    own-atom slot filled by translational invariance, a wave reduction over
 //    the other atoms' slots), and R = w (Yr + 2 Zr, Yg + 2 Zg), written over Y.
+//    Optional outputs: Yr, Yg (response rows) and Yr + Zr, Yg + Zg (the
+//    grid-level coefficients of the Fock nuclear derivative).
 // 2. k_gemm: per slice s of points, Hpart[s][l][m] = sum_i L_i^T R_i with
 //    L = (rho^x, gamma^x) on FP64 MFMA, so that sum_s Hpart[s] = E_GG + 2 E_{G,gr}
 //    (E_GG without the rho^{AB} term); row Pp of each slice holds the gradient
@@ -81,7 +83,7 @@ __global__ __launch_bounds__(256) void k_resp(
     int64_t n, int64_t npad, int32_t P, int32_t Pp, int32_t S, const int32_t *__restrict__ atom_of,
     const double *__restrict__ F, const double *__restrict__ I, const double *__restrict__ L,
     const T *Ypart, double *Y, const double *__restrict__ Z, double *__restrict__ resp_rho,
-    double *__restrict__ resp_gamma) {
+    double *__restrict__ resp_gamma, double *__restrict__ fock_rho, double *__restrict__ fock_gamma) {
     const int lane = threadIdx.x & 63;
     const int64_t i = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (i >= n) return;
@@ -131,6 +133,8 @@ __global__ __launch_bounds__(256) void k_resp(
         *y1 = f.w * (Yg + 2.0 * Zg);
         if (resp_rho) resp_rho[(int64_t)x * n + i] = Yr;
         if (resp_gamma) resp_gamma[(int64_t)x * n + i] = Yg;
+        if (fock_rho) fock_rho[(int64_t)x * n + i] = Yr + Zr;
+        if (fock_gamma) fock_gamma[(int64_t)x * n + i] = Yg + Zg;
     }
 }
 
@@ -325,6 +329,7 @@ __global__ __launch_bounds__(256) void k_finish(int32_t n_atom, int32_t P, int32
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t PP = (int64_t)P * P;
     if (k < PP) {
+        if (!hess) return;
         const int l = (int)(k / P), m = (int)(k % P);
         const int A = l / 3, a = l % 3, B = m / 3, b = m % 3;
         const int c = sym_index(a, b);
@@ -404,21 +409,24 @@ hipError_t launch_trial_response(vv10_plan *p, double *f_rho_t, double *f_gamma_
     return hipGetLastError();
 }
 
-hipError_t launch_assemble(vv10_plan *p, double *hess, double *grad, double *resp_rho,
-                           double *resp_gamma) {
+hipError_t launch_assemble(vv10_plan *p, const vv10_nuclear_outputs &out) {
     const Workspace &ws = p->ws;
     const int64_t n = p->n;
+    double *hess = out.hess, *grad = out.grad;
     {
         const unsigned nb = (unsigned)((n + 3) / 4);
         if (p->prec == VV10_FP64)
             k_resp<double><<<nb, 256, 0, p->stream>>>(
                 n, p->npad, ws.P, ws.Pp, ws.jsplit, p->atom_of, p->F, p->I, ws.L,
-                static_cast<const double *>(ws.Ypart), ws.Y, ws.Z, resp_rho, resp_gamma);
+                static_cast<const double *>(ws.Ypart), ws.Y, ws.Z, out.resp_rho, out.resp_gamma,
+                out.fock_rho, out.fock_gamma);
         else
             k_resp<float><<<nb, 256, 0, p->stream>>>(
                 n, p->npad, ws.P, ws.Pp, ws.jsplit, p->atom_of, p->F, p->I, ws.L,
-                static_cast<const float *>(ws.Ypart), ws.Y, ws.Z, resp_rho, resp_gamma);
+                static_cast<const float *>(ws.Ypart), ws.Y, ws.Z, out.resp_rho, out.resp_gamma,
+                out.fock_rho, out.fock_gamma);
     }
+    if (!hess && !grad) return hipGetLastError();
     {
         const int64_t slice = (n + ws.gsplit - 1) / ws.gsplit;
         const unsigned tiles = (unsigned)((ws.Pp + 63) / 64);

@@ -454,12 +454,14 @@ vv10_status vv10_energy_potential(vv10_plan *p, double *energy, double *f_rho, d
     return VV10_OK;
 }
 
-vv10_status vv10_hessian_terms(vv10_plan *p, int32_t n_pert, const double *rho_x,
-                               const double *grad_rho_x, double *hess, double *grad,
-                               double *resp_rho, double *resp_gamma) {
+vv10_status vv10_nuclear_terms(vv10_plan *p, int32_t n_pert, const double *rho_x,
+                               const double *grad_rho_x, const vv10_nuclear_outputs *out) {
     if (!p) return VV10_E_STATE;
     if (p->failed) return VV10_E_STATE;
-    if (n_pert != 3 * p->n_atom || !rho_x || !grad_rho_x || !hess) return VV10_E_ARG;
+    if (n_pert != 3 * p->n_atom || !rho_x || !grad_rho_x || !out) return VV10_E_ARG;
+    if (!out->hess && !out->grad && !out->resp_rho && !out->resp_gamma && !out->fock_rho &&
+        !out->fock_gamma)
+        return VV10_OK;
     vv10_status st = vv10::ensure_workspace(p);
     if (st != VV10_OK) return st;
     // the grid-term pass also produces the pair integrals E, U, W, A, B, C
@@ -469,15 +471,22 @@ vv10_status vv10_hessian_terms(vv10_plan *p, int32_t n_pert, const double *rho_x
     if (e == hipSuccess)
         e = stage(p, VV10_STAGE_PERT_PREP, [&] { return vv10::launch_pert_prep(p, p->ws, rho_x, grad_rho_x); });
     if (e == hipSuccess) e = stage(p, VV10_STAGE_CONTRACT, [&] { return vv10::launch_contract(p, p->ws); });
-    if (e == hipSuccess)
-        e = stage(p, VV10_STAGE_ASSEMBLE,
-                  [&] { return vv10::launch_assemble(p, hess, grad, resp_rho, resp_gamma); });
+    if (e == hipSuccess) e = stage(p, VV10_STAGE_ASSEMBLE, [&] { return vv10::launch_assemble(p, *out); });
     if (e != hipSuccess) {
         p->failed = true;
         (void)hipGetLastError();
         return VV10_E_HIP;
     }
     return VV10_OK;
+}
+
+vv10_status vv10_hessian_terms(vv10_plan *p, int32_t n_pert, const double *rho_x,
+                               const double *grad_rho_x, double *hess, double *grad,
+                               double *resp_rho, double *resp_gamma) {
+    if (!p) return VV10_E_STATE;
+    if (!hess) return VV10_E_ARG;
+    const vv10_nuclear_outputs out = {hess, grad, resp_rho, resp_gamma, nullptr, nullptr};
+    return vv10_nuclear_terms(p, n_pert, rho_x, grad_rho_x, &out);
 }
 
 vv10_status vv10_gradient(vv10_plan *p, int32_t n_pert, const double *rho_x,

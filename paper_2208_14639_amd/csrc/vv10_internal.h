@@ -159,8 +159,7 @@ hipError_t launch_grid_terms(vv10_plan *p);
 hipError_t launch_grid_grad(vv10_plan *p);
 hipError_t launch_gradient(vv10_plan *p, const double *rho_x, const double *grad_rho_x, double *grad);
 hipError_t launch_trial_response(vv10_plan *p, double *f_rho_t, double *f_gamma_t);
-hipError_t launch_assemble(vv10_plan *p, double *hess, double *grad, double *resp_rho,
-                           double *resp_gamma);
+hipError_t launch_assemble(vv10_plan *p, const vv10_nuclear_outputs &out);
 
 // Layout decisions shared by the host code.
 // n_cols: contraction columns (0 = the 3 n_atom nuclear perturbations).

@@ -40,6 +40,11 @@ class vv10_tiles(ctypes.Structure):
     _fields_ = [("jsplit", ctypes.c_int32), ("bgroups", ctypes.c_int32)]
 
 
+class vv10_nuclear_outputs(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in
+                ("hess", "grad", "resp_rho", "resp_gamma", "fock_rho", "fock_gamma")]
+
+
 class VV10Error(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -67,6 +72,8 @@ def load() -> ctypes.CDLL:
     lib.vv10_hessian_terms.argtypes = [P, i32, P, P, P, P, P, P]
     lib.vv10_footprint_bytes.restype = ctypes.c_size_t
     lib.vv10_footprint_bytes.argtypes = [i64, i32, st]
+    lib.vv10_nuclear_terms.restype = st
+    lib.vv10_nuclear_terms.argtypes = [P, i32, P, P, ctypes.POINTER(vv10_nuclear_outputs)]
     lib.vv10_gradient.restype = st
     lib.vv10_gradient.argtypes = [P, i32, P, P, P]
     lib.vv10_trial_response.restype = st
@@ -169,6 +176,15 @@ def vv10_hessian_terms(plan: int, n_pert: int, rho_x, grad_rho_x, hess, grad=Non
                                    _ptr(grad), _ptr(resp_rho), _ptr(resp_gamma))
     if st != VV10_OK:
         raise VV10Error(st, "vv10_hessian_terms")
+
+
+def vv10_nuclear_terms(plan: int, n_pert: int, rho_x, grad_rho_x, hess=None, grad=None,
+                       resp_rho=None, resp_gamma=None, fock_rho=None, fock_gamma=None) -> None:
+    out = vv10_nuclear_outputs(*(_ptr(t) for t in (hess, grad, resp_rho, resp_gamma, fock_rho,
+                                                    fock_gamma)))
+    st = load().vv10_nuclear_terms(plan, n_pert, _ptr(rho_x), _ptr(grad_rho_x), ctypes.byref(out))
+    if st != VV10_OK:
+        raise VV10Error(st, "vv10_nuclear_terms")
 
 
 def vv10_gradient(plan: int, n_pert: int, rho_x, grad_rho_x, grad) -> None:
@@ -338,6 +354,19 @@ class Plan:
         if resp:
             out["resp_rho"], out["resp_gamma"] = rr, rg
         return out
+
+    def nuclear_terms(self, rho_x, grad_rho_x, hess=True, grad=False, resp=False, fock=False):
+        """Any subset of the nuclear-perturbation outputs of one pass."""
+        t = self.torch
+        P = 3 * self.n_atom
+        rx = rho_x if isinstance(rho_x, t.Tensor) and rho_x.is_cuda else self._dev(rho_x)
+        gx = grad_rho_x if isinstance(grad_rho_x, t.Tensor) and grad_rho_x.is_cuda else self._dev(grad_rho_x)
+        mk = lambda on, shape: t.empty(shape, dtype=t.float64, device=self.device) if on else None
+        out = {"hess": mk(hess, (P, P)), "grad": mk(grad, P),
+               "resp_rho": mk(resp, (P, self.n)), "resp_gamma": mk(resp, (P, self.n)),
+               "fock_rho": mk(fock, (P, self.n)), "fock_gamma": mk(fock, (P, self.n))}
+        vv10_nuclear_terms(self.handle, P, rx, gx, **out)
+        return {k: v for k, v in out.items() if v is not None}
 
     def gradient(self, rho_x, grad_rho_x):
         """Nuclear gradient [3 n_atom] alone."""

@@ -1,0 +1,93 @@
+"""vv10_nuclear_terms: the grid-level coefficients of the Fock nuclear
+derivative (Section II.B, F^A_G + F^A_gr) against the FP64 oracle, and the
+output subsets against vv10_hessian_terms."""
+import functools
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import normwise, problem
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+FOCK_NORM = {"fp32": 1e-5, "bf16x3": 5e-5}
+CASES = [(1, 8, 11), (2, 37, 5), (2, 700, 1001)]
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+@functools.lru_cache(maxsize=8)
+def oracle_fock(n_water, n_pa, seed):
+    p = problem(n_water, n_pa, seed)
+    g, gx = oracle.problem_inputs(p)
+    return oracle.fock_nuclear_terms(p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b, p.C,
+                                     p.rho_x, gx)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("case", CASES)
+def test_fock_terms_vs_oracle(torch, case, prec):
+    from paper_2208_14639_amd import vv10
+    _say("fock terms", prec, case)
+    p = problem(*case)
+    with vv10.Plan(p, prec=prec) as pl:
+        out = pl.nuclear_terms(p.rho_x, p.grad_rho_x, hess=False, fock=True)
+        torch.cuda.synchronize()
+        vr, vg = out["fock_rho"].cpu().numpy(), out["fock_gamma"].cpu().numpy()
+    vr0, vg0 = oracle_fock(*case)
+    errs = (normwise(vr, vr0), normwise(vg, vg0))
+    _say("   normwise errors", errs)
+    assert max(errs) < (TOL64 if prec == "fp64" else FOCK_NORM[prec])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_output_subsets_agree(torch, prec):
+    """Every subset of outputs gives the same values, bitwise, as
+    vv10_hessian_terms (same launches, outputs only switched on or off); no
+    output at all is a no-op."""
+    from paper_2208_14639_amd import vv10
+    p = problem(2, 37, 5)
+    with vv10.Plan(p, prec=prec) as pl:
+        ref = pl.hessian_terms(p.rho_x, p.grad_rho_x, grad=True, resp=True)
+        full = pl.nuclear_terms(p.rho_x, p.grad_rho_x, hess=True, grad=True, resp=True, fock=True)
+        only_h = pl.nuclear_terms(p.rho_x, p.grad_rho_x, hess=True)
+        only_g = pl.nuclear_terms(p.rho_x, p.grad_rho_x, hess=False, grad=True)
+        only_f = pl.nuclear_terms(p.rho_x, p.grad_rho_x, hess=False, fock=True)
+        none = pl.nuclear_terms(p.rho_x, p.grad_rho_x, hess=False)
+        torch.cuda.synchronize()
+        c = lambda d, k: d[k].cpu().numpy()
+        for k in ("hess", "grad", "resp_rho", "resp_gamma"):
+            assert np.array_equal(c(full, k), c(ref, k)), k
+        assert np.array_equal(c(only_h, "hess"), c(ref, "hess"))
+        assert np.array_equal(c(only_g, "grad"), c(ref, "grad"))
+        assert np.array_equal(c(only_f, "fock_rho"), c(full, "fock_rho"))
+        assert np.array_equal(c(only_f, "fock_gamma"), c(full, "fock_gamma"))
+        assert none == {}
+
+
+def test_nuclear_terms_errors(torch):
+    from paper_2208_14639_amd import vv10
+    p = problem(1, 8, 11)
+    with vv10.Plan(p, prec="fp64") as pl:
+        rx = torch.as_tensor(p.rho_x, device="cuda")
+        gx = torch.as_tensor(p.grad_rho_x, device="cuda")
+        for n_pert, a in ((3 * p.n_atom + 1, rx), (3 * p.n_atom, None)):
+            with pytest.raises(vv10.VV10Error) as ei:
+                vv10.vv10_nuclear_terms(pl.handle, n_pert, a, gx,
+                                        hess=torch.empty((9, 9), dtype=torch.float64, device="cuda"))
+            assert ei.value.status == vv10.VV10_E_ARG
+        with pytest.raises(vv10.VV10Error) as ei:
+            vv10.vv10_hessian_terms(pl.handle, 3 * p.n_atom, rx, gx, None)
+        assert ei.value.status == vv10.VV10_E_ARG

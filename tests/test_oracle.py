@@ -354,6 +354,33 @@ def test_hessian_terms_fd(small_dimer):
     assert info["asym"] < 1e-12 * scale
 
 
+def test_fock_terms_are_potential_derivatives(small_dimer):
+    """The grid-level coefficients of the Fock nuclear derivative (Section II.B,
+    second line of F^A_G plus F^A_gr) are the derivatives of the potential
+    f^rho, f^gamma when nucleus A moves with its grid points: the oracle's
+    composition must match central differences of its potential on displaced
+    geometries (and the response rows alone must not)."""
+    p = small_dimer
+    g, gx = oracle.problem_inputs(p)
+    vr, vg = oracle.fock_nuclear_terms(p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b,
+                                       p.C, p.rho_x, gx)
+    Yr, _ = oracle.response_rows(0, p.n_grid, p.coords, p.weights, p.rho, g, p.b, p.C, p.rho_x, gx)
+    n = p.n_grid
+    for x in (0, 4, 11, 16):
+        A, a = divmod(x, 3)
+
+        def pot(h):
+            q = inputs.displaced(p, A, a, h)
+            _, fr, fgm = oracle.energy_potential(q.coords, q.weights, q.rho, oracle.gamma(q.grad_rho),
+                                                 q.b, q.C)
+            return np.concatenate([fr, fgm])
+
+        d = richardson(pot, 1e-3)
+        assert np.max(np.abs(d[:n] - vr[x])) <= 1e-9 * np.max(np.abs(vr[x]))
+        assert np.max(np.abs(d[n:] - vg[x])) <= 1e-9 * np.max(np.abs(vg[x]))
+        assert np.max(np.abs(d[:n] - Yr[x])) > 0.1 * np.max(np.abs(vr[x]))
+
+
 def test_hessian_invariances(small_dimer):
     p = small_dimer
     g, gx = oracle.problem_inputs(p)
