@@ -1,7 +1,10 @@
 """Continuous-batching server for VV10 Hessian-term requests.
 
 A request names a molecule (grid, density and perturbed densities) and asks
-for its energy and Hessian terms.  The scheduler keeps up to `n_slots`
+for its energy and Hessian terms (kind "hessian"), its energy and nuclear
+gradient ("gradient"), or the orbital-Hessian response of n_t trial
+densities ("response", the step a CPSCF or TDDFT iteration repeats on a
+resident grid).  The scheduler keeps up to `n_slots`
 requests in flight at once, each on its own HIP stream, and admits a
 waiting request as soon as a slot is free AND its device footprint fits in
 what is left of the HBM budget; requests that arrive while others run are
@@ -14,7 +17,9 @@ whole budget is rejected.
 Device state of a molecule (its plan, inputs and workspace) stays resident
 after its request completes, keyed by molecule id, and is reused by later
 requests for the same molecule; idle resident state is evicted least
-recently used when the budget needs room.
+recently used when the budget needs room.  A request of another kind on a
+resident molecule is charged only the memory its kind adds (for instance
+the response workspace for its n_t).
 
 The scheduler is independent of the device: `GpuExecutor` runs requests
 through the HIP library; `FakeExecutor` (for tests on machines without a
@@ -35,6 +40,8 @@ class Request:
     rid: int
     mol_id: str
     problem: object                 # inputs.Problem with derivatives
+    kind: str = "hessian"           # hessian, gradient or response
+    trial: tuple = None             # response: (rho_t [n_t, N], grad_rho_t [n_t, N, 3])
     arrival: float = 0.0            # seconds on the server clock
     # filled by the server
     admitted: float = None
@@ -43,13 +50,22 @@ class Request:
     error: str = None
 
     @property
+    def n_cols(self) -> int:
+        return int(self.trial[0].shape[0]) if self.kind == "response" else self.problem.n_pert
+
+    @property
     def pair_pert(self) -> float:
         n = float(self.problem.n_grid)
-        return n * n * self.problem.n_pert
+        return n * n * self.n_cols
 
     @property
     def latency(self) -> float:
         return None if self.finished is None else self.finished - self.arrival
+
+
+def as_request(x) -> Request:
+    """A Request as given, or a Hessian request for a bare problem."""
+    return x if isinstance(x, Request) else Request(rid=-1, mol_id="", problem=x)
 
 
 def percentile(values, q):
@@ -117,9 +133,11 @@ class Server:
 
     # -- memory ------------------------------------------------------------
     def _footprint(self, req) -> int:
+        """Bytes this request adds: its molecule's whole state, or what its kind
+        adds to the resident state."""
         if req.mol_id in self.resident:
-            return 0
-        return self.ex.footprint(req.problem)
+            return self.ex.extra_bytes(self.resident[req.mol_id][1], req)
+        return self.ex.footprint(req)
 
     def _make_room(self, need: int) -> bool:
         """Evict idle resident molecules (LRU) until `need` bytes fit."""
@@ -141,7 +159,7 @@ class Server:
                 break
             if self.pinned[req.mol_id] > 0:
                 continue                    # one request per molecule at a time (shared state)
-            total = self.ex.footprint(req.problem)
+            total = self.ex.footprint(req)
             if total > self.budget:
                 del self.queue[k]
                 req.status = "rejected"
@@ -159,14 +177,16 @@ class Server:
             try:
                 if req.mol_id in self.resident:
                     nbytes, state = self.resident.pop(req.mol_id)
-                    self.resident[req.mol_id] = (nbytes, state)     # most recently used
+                    self.resident[req.mol_id] = (nbytes + need, state)   # most recently used
+                    self.used += need
+                    self.peak_used = max(self.peak_used, self.used)
                 else:
                     state = self.ex.load(req.mol_id, req.problem)
                     self.resident[req.mol_id] = (need, state)
                     self.used += need
                     self.peak_used = max(self.peak_used, self.used)
                 self.pinned[req.mol_id] += 1
-                handle = self.ex.start(state, req.problem, slot)
+                handle = self.ex.start(state, req, slot)
             except Exception as e:          # the request fails; the server goes on
                 self.pinned[req.mol_id] -= 1 if self.pinned[req.mol_id] > 0 else 0
                 req.status, req.error, req.finished = "failed", repr(e), self.now()
@@ -277,10 +297,28 @@ class GpuExecutor:
         self.load_stream = torch.cuda.Stream(device=self.dev)   # uploads and preparation
         self.tiles = tiles
 
-    def footprint(self, problem) -> int:
+    def _resp_bytes(self, n, n_t) -> int:
+        prec = self.vv10.PRECISIONS[self.prec]
+        return self.vv10.vv10_response_footprint_bytes(n, n_t, prec) + 8 * n * n_t * (4 + 2)
+
+    def footprint(self, req) -> int:
+        """Device bytes of the molecule's state once it has served `req`: plan
+        and workspace (upper bound), inputs, and for a response the response
+        workspace, trial densities and outputs."""
+        req = as_request(req)
+        problem = req.problem
         n, na = int(problem.n_grid), int(problem.n_atom)
         inputs = 8 * n * (3 + 1 + 1 + 3) + 4 * n + 8 * 3 * na * n * 4
-        return self.vv10.vv10_footprint_bytes(n, na, self.vv10.PRECISIONS[self.prec]) + inputs
+        b = self.vv10.vv10_footprint_bytes(n, na, self.vv10.PRECISIONS[self.prec]) + inputs
+        if req.kind == "response":
+            b += self._resp_bytes(n, req.n_cols)
+        return b
+
+    def extra_bytes(self, state, req) -> int:
+        """Bytes `req` adds to a resident state (a larger response workspace)."""
+        if req.kind != "response":
+            return 0
+        return max(0, self._resp_bytes(int(req.problem.n_grid), req.n_cols) - state.get("resp_bytes", 0))
 
     def load(self, mol_id, problem):
         torch = self.torch
@@ -292,29 +330,49 @@ class GpuExecutor:
         self.load_stream.synchronize()
         return {"plan": plan, "rx": rx, "gx": gx}
 
-    def start(self, state, problem, slot):
+    def start(self, state, req, slot):
         torch, vv = self.torch, self.vv10
         s = self.streams[slot]
         plan = state["plan"]
         P = 3 * plan.n_atom
-        with torch.cuda.stream(s):
-            e = torch.empty(1, dtype=torch.float64, device=self.dev)
-            H = torch.empty((P, P), dtype=torch.float64, device=self.dev)
         # the plan's previous calls completed before this request was admitted
         # (one request per molecule at a time), so it can move to this slot
         vv.vv10_set_stream(plan.handle, s)
-        vv.vv10_energy_potential(plan.handle, e)
-        vv.vv10_hessian_terms(plan.handle, P, state["rx"], state["gx"], H)
+        out = {}
+        if req.kind == "response":
+            n = plan.n
+            state["resp_bytes"] = max(state.get("resp_bytes", 0), self._resp_bytes(n, req.n_cols))
+            with torch.cuda.stream(s):
+                rt = torch.as_tensor(req.trial[0], dtype=torch.float64).to(self.dev, non_blocking=False).contiguous()
+                gt = torch.as_tensor(req.trial[1], dtype=torch.float64).to(self.dev, non_blocking=False).contiguous()
+                fr = torch.empty((req.n_cols, n), dtype=torch.float64, device=self.dev)
+                fg = torch.empty_like(fr)
+            vv.vv10_trial_response(plan.handle, req.n_cols, rt, gt, fr, fg)
+            out.update(fr=fr, fg=fg, keep=(rt, gt))
+        else:
+            with torch.cuda.stream(s):
+                e = torch.empty(1, dtype=torch.float64, device=self.dev)
+                res = torch.empty((P, P) if req.kind == "hessian" else P, dtype=torch.float64,
+                                  device=self.dev)
+            vv.vv10_energy_potential(plan.handle, e)
+            if req.kind == "hessian":
+                vv.vv10_hessian_terms(plan.handle, P, state["rx"], state["gx"], res)
+            else:
+                vv.vv10_gradient(plan.handle, P, state["rx"], state["gx"], res)
+            out.update(e=e, res=res)
         done = torch.cuda.Event()
         done.record(s)
-        return {"done": done, "e": e, "H": H}
+        out.update(done=done, kind=req.kind)
+        return out
 
     def poll(self, handle) -> bool:
         return handle["done"].query()
 
     def result(self, handle):
         handle["done"].synchronize()
-        return handle["e"].item(), handle["H"].cpu().numpy()
+        if handle["kind"] == "response":
+            return handle["fr"].cpu().numpy(), handle["fg"].cpu().numpy()
+        return handle["e"].item(), handle["res"].cpu().numpy()
 
     def release(self, state):
         state["plan"].close()
@@ -333,27 +391,51 @@ class FakeExecutor:
         self.active = 0
         self.max_active = 0
 
-    def footprint(self, problem) -> int:
-        n, na = int(problem.n_grid), int(problem.n_atom)
-        return 8 * n * (20 + 8 * 3 * na)
+    def footprint(self, req) -> int:
+        req = as_request(req)
+        n, na = int(req.problem.n_grid), int(req.problem.n_atom)
+        b = 8 * n * (20 + 8 * 3 * na)
+        if req.kind == "response":
+            b += 8 * n * 10 * req.n_cols
+        return b
+
+    def extra_bytes(self, state, req) -> int:
+        if req.kind != "response":
+            return 0
+        return max(0, 8 * int(req.problem.n_grid) * 10 * req.n_cols - state.get("resp_bytes", 0))
 
     def load(self, mol_id, problem):
         if mol_id in self.fail_mol:
             raise RuntimeError(f"injected load failure for {mol_id}")
         return {"mol": mol_id}
 
-    def start(self, state, problem, slot):
+    def start(self, state, req, slot):
         import oracle
+        problem = req.problem
         g, gx = oracle.problem_inputs(problem)
-        e, _, _ = oracle.energy_potential(problem.coords, problem.weights, problem.rho, g,
-                                          problem.b, problem.C)
-        H, _ = oracle.hessian_terms(problem.atom_of, problem.n_atom, problem.coords,
+        if req.kind == "response":
+            state["resp_bytes"] = max(state.get("resp_bytes", 0),
+                                      8 * int(problem.n_grid) * 10 * req.n_cols)
+            rt, gt = req.trial
+            res = oracle.response_rows(0, problem.n_grid, problem.coords, problem.weights,
+                                       problem.rho, g, problem.b, problem.C, rt,
+                                       oracle.gamma_x(problem.grad_rho, gt))
+        else:
+            e, _, _ = oracle.energy_potential(problem.coords, problem.weights, problem.rho, g,
+                                              problem.b, problem.C)
+            if req.kind == "hessian":
+                H, _ = oracle.hessian_terms(problem.atom_of, problem.n_atom, problem.coords,
+                                            problem.weights, problem.rho, g, problem.b, problem.C,
+                                            problem.rho_x, gx)
+            else:
+                H = oracle.gradient(problem.atom_of, problem.n_atom, problem.coords,
                                     problem.weights, problem.rho, g, problem.b, problem.C,
                                     problem.rho_x, gx)
+            res = (e, H)
         n = float(problem.n_grid)
         self.active += 1
         self.max_active = max(self.max_active, self.active)
-        return {"t_done": self.clock() + self.spp * n * n * problem.n_pert, "res": (e, H)}
+        return {"t_done": self.clock() + self.spp * n * n * req.n_cols, "res": res}
 
     def poll(self, handle) -> bool:
         ready = self.clock() >= handle["t_done"]

@@ -42,3 +42,39 @@ def test_served_results_equal_alone():
     reqs = sorted(srv.done, key=lambda r: r.rid)
     assert any(b.admitted < a.finished and b.admitted > a.admitted for a in reqs for b in reqs)
     srv.close()
+
+
+def test_served_kinds_equal_alone():
+    """Gradient and response requests mixed with Hessian requests: every result
+    equals the same call made alone on a fresh plan, bitwise."""
+    import torch
+    from paper_2208_14639_amd import vv10
+    from paper_2208_14639_amd.serve import GpuExecutor, Request, Server
+    pool = [inputs.make_problem(k + 1, 150 + 50 * k, 700 + k) for k in range(3)]
+    trial = [inputs.trial_densities(p, 5 + 4 * k, 800 + k) for k, p in enumerate(pool)]
+    alone = {}
+    for m, p in enumerate(pool):
+        with vv10.Plan(p, prec="bf16x3", tiles="auto") as pl:
+            fr, fg = pl.trial_response(*trial[m])
+            alone[m, "response"] = (fr.cpu().numpy(), fg.cpu().numpy())
+        with vv10.Plan(p, prec="bf16x3", tiles="auto") as pl:
+            e, _, _ = pl.energy_potential()
+            g = pl.gradient(p.rho_x, p.grad_rho_x)
+            torch.cuda.synchronize()
+            alone[m, "gradient"] = (e.item(), g.cpu().numpy())
+    ex = GpuExecutor(prec="bf16x3", n_slots=3)
+    srv = Server(ex, 4 * max(ex.footprint(p) for p in pool), n_slots=3)
+    plan = [(0, "response"), (1, "gradient"), (2, "hessian"), (0, "gradient"), (2, "response"),
+            (1, "response"), (0, "response"), (2, "gradient")]
+    futs = [srv.submit(Request(k, f"m{m}", pool[m], kind=kind,
+                               trial=trial[m] if kind == "response" else None), at=0.0005 * k)
+            for k, (m, kind) in enumerate(plan)]
+    srv.run_until_idle(timeout_s=120)
+    for f, (m, kind) in zip(futs, plan):
+        if kind == "hessian":
+            continue
+        got = f.result()
+        for a, b in zip(got, alone[m, kind]):
+            assert np.array_equal(np.asarray(a), np.asarray(b)), (m, kind)
+    assert srv.stats()["completed"] == len(plan)
+    srv.close()

@@ -169,3 +169,46 @@ def test_background_thread_mode():
             f.result(timeout=60)
     finally:
         srv.stop()
+
+
+def test_request_kinds_and_incremental_accounting():
+    """Hessian, gradient and response requests on the same molecules: each
+    result matches the oracle for its kind, and a response on a resident
+    molecule is charged only its response workspace (once per n_t growth)."""
+    import oracle
+    ps = mols(2, seed=7)
+    ex = FakeExecutor(seconds_per_pair_pert=1e-8)
+    trial = {k: inputs.trial_densities(p, 3 + k, 40 + k) for k, p in enumerate(ps)}
+    srv = Server(ex, 10 * max(ex.footprint(p) for p in ps), n_slots=2)
+    plan = [(0, "hessian"), (1, "response"), (0, "response"), (1, "gradient"), (0, "response"),
+            (1, "hessian")]
+    futs = []
+    for k, (m, kind) in enumerate(plan):
+        req = Request(k, f"m{m}", ps[m], kind=kind, trial=trial[m] if kind == "response" else None)
+        futs.append((req, srv.submit(req, at=0.001 * k)))
+    srv.run_until_idle(timeout_s=60)
+    for (req, f), (m, kind) in zip(futs, plan):
+        p = ps[m]
+        g, gx = oracle.problem_inputs(p)
+        if kind == "response":
+            fr, fg = f.result()
+            rt, gt = trial[m]
+            Yr, Yg = oracle.response_rows(0, p.n_grid, p.coords, p.weights, p.rho, g, p.b, p.C, rt,
+                                          oracle.gamma_x(p.grad_rho, gt))
+            assert np.array_equal(fr, Yr) and np.array_equal(fg, Yg)
+            assert req.pair_pert == float(p.n_grid) ** 2 * rt.shape[0]
+        elif kind == "gradient":
+            e, G = f.result()
+            G0 = oracle.gradient(p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b, p.C,
+                                 p.rho_x, gx)
+            assert np.array_equal(G, G0)
+        else:
+            e, H = f.result()
+            assert H.shape == (p.n_pert, p.n_pert)
+    # each molecule: base state plus one response workspace, charged once
+    for m, p in enumerate(ps):
+        base = ex.footprint(p)
+        resp = ex.footprint(Request(0, "", p, kind="response", trial=trial[m])) - base
+        assert srv.resident[f"m{m}"][0] == base + resp
+    assert srv.used == sum(b for b, _ in srv.resident.values())
+    srv.close()
