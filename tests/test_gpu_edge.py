@@ -1,0 +1,104 @@
+"""Edge cases through the C ABI: an atom without grid points, grids of one to
+three points, and the largest configuration (the water 20-mer, N = 120000,
+P = 180: twelve 16-column blocks, the widest contraction) checked on rows
+the oracle evaluates one at a time and on properties that hold at any size."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import normwise
+from paper_2208_14639_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+def _oracle_all(p):
+    g, gx = oracle.problem_inputs(p)
+    e0, fr0, fg0 = oracle.energy_potential(p.coords, p.weights, p.rho, g, p.b, p.C)
+    H0, _ = oracle.hessian_terms(p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b, p.C,
+                                 p.rho_x, gx)
+    G0 = oracle.gradient(p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b, p.C, p.rho_x, gx)
+    return e0, fr0, fg0, H0, G0
+
+
+def _check(torch, p, prec="fp64"):
+    from paper_2208_14639_amd import vv10
+    e0, fr0, fg0, H0, G0 = _oracle_all(p)
+    with vv10.Plan(p, prec=prec) as pl:
+        e, fr, fg = pl.energy_potential()
+        out = pl.hessian_terms(p.rho_x, p.grad_rho_x, grad=True)
+        g = pl.gradient(p.rho_x, p.grad_rho_x)
+        torch.cuda.synchronize()
+        got = (e.item(), fr.cpu().numpy(), fg.cpu().numpy(), out["hess"].cpu().numpy(),
+               out["grad"].cpu().numpy(), g.cpu().numpy())
+    errs = dict(energy=abs(got[0] - e0) / abs(e0), f_rho=normwise(got[1], fr0),
+                f_gamma=normwise(got[2], fg0), hess=normwise(got[3], H0),
+                grad=normwise(got[4], G0), grad_only=normwise(got[5], G0))
+    _say("   ", prec, errs)
+    return errs
+
+
+def test_atom_without_points(torch):
+    """A water dimer whose second oxygen carries no grid points: its segment
+    is empty, its perturbations still move density at every other point."""
+    rng = np.random.default_rng(41)
+    mol = inputs.water_cluster(2, rng)
+    ao, off, r = inputs.atom_grid(mol.n_atom, 45, rng)
+    keep = ao != 3
+    p = inputs.build_problem(mol, ao[keep], off[keep], r[keep])
+    assert 3 not in set(p.atom_of.tolist()) and p.n_atom == 6
+    errs = _check(torch, p)
+    assert max(errs.values()) < TOL64
+    errs = _check(torch, p, "bf16x3")
+    assert errs["energy"] < 1e-6 and errs["hess"] < 1e-4 and errs["grad"] < 1e-5
+
+
+@pytest.mark.parametrize("n_pa", [1, 2, 3])
+def test_few_points(torch, n_pa):
+    """One water with n_pa points per atom (N = 3 n_pa): every tile and split
+    is mostly padding."""
+    p = inputs.make_problem(1, n_pa, 60 + n_pa)
+    errs = _check(torch, p)
+    assert max(errs.values()) < TOL64
+
+
+def test_water_20mer_full_size(torch):
+    """N = 120000, P = 180, split-BF16 as timed: response rows against the
+    oracle on sampled rows; the Hessian exactly symmetric and translationally
+    invariant (sum over B of H_{A,B} = 0) to the mixed bound."""
+    from paper_2208_14639_amd import vv10
+    p = inputs.make_workload("water_20mer")
+    with vv10.Plan(p, prec="bf16x3", tiles="auto") as pl:
+        out = pl.nuclear_terms(p.rho_x, p.grad_rho_x, hess=True, resp=True)
+        torch.cuda.synchronize()
+        H = out["hess"].cpu().numpy()
+        rr = out["resp_rho"].cpu().numpy()
+        rg = out["resp_gamma"].cpu().numpy()
+    assert np.array_equal(H, H.T)
+    P = p.n_pert
+    rows = H.reshape(P, p.n_atom, 3).sum(axis=1)
+    _say("   20-mer translational residual", np.max(np.abs(rows)), "of", np.max(np.abs(H)))
+    assert np.max(np.abs(rows)) <= 1e-5 * np.max(np.abs(H))
+    g, gx = oracle.problem_inputs(p)
+    sr, sg = np.max(np.abs(rr)), np.max(np.abs(rg))
+    for i0 in (0, 60007):                  # each oracle call repeats its O(N^2) integral pass
+        _say("   20-mer rows", i0)
+        Yr, Yg = oracle.response_rows(i0, i0 + 4, p.coords, p.weights, p.rho, g, p.b, p.C,
+                                      p.rho_x, gx)
+        assert np.max(np.abs(rr[:, i0:i0 + 4] - Yr)) <= 5e-5 * sr
+        assert np.max(np.abs(rg[:, i0:i0 + 4] - Yg)) <= 5e-5 * sg
