@@ -56,6 +56,7 @@ def _load():
         _lib.oracle_grid_D.argtypes = [i64, i32, i64, i32, P, P, P, P, P, d, d, P]
         _lib.oracle_gradient.restype = ctypes.c_int
         _lib.oracle_gradient.argtypes = [i64, i32, P, P, P, P, P, d, d, P, P, P, P]
+        _lib.oracle_weight_integrals.argtypes = [i64, P, P, P, d, d, i32, P, P, P, P]
         _lib.oracle_hessian_terms.restype = ctypes.c_int
         _lib.oracle_hessian_terms.argtypes = [i64, i32, P, P, P, P, P, d, d, i32, P, P,
                                               P, P, P, P, P]
@@ -168,7 +169,9 @@ def grid_D(i, B, atom_of, n_atom, coords, w, rho, gam, b, C):
     return D.reshape(3, 3)
 
 
-def gradient(atom_of, n_atom, coords, w, rho, gam, b, C, rho_x, gam_x, parts=False):
+def gradient(atom_of, n_atom, coords, w, rho, gam, b, C, rho_x, gam_x, parts=False, w_x=None):
+    """E^A = E^A_G + E^A_gr (+ E^A_w when the weight derivatives w_x [P, n] are
+    given; Section II.A).  parts: (E_G, E_gr[, E_w]) as rows."""
     c, w, r, g, rx, gx = map(_f64, (coords, w, rho, gam, rho_x, gam_x))
     ao = np.ascontiguousarray(atom_of, dtype=np.int32)
     n = w.shape[0]
@@ -179,15 +182,83 @@ def gradient(atom_of, n_atom, coords, w, rho, gam, b, C, rho_x, gam_x, parts=Fal
                                  b, C, _ptr(rx), _ptr(gx), _ptr(out), _ptr(pa))
     if rc:
         raise ValueError(f"oracle_gradient failed: {rc}")
+    if w_x is not None:
+        Ew = _f64(w_x) @ weight_coefficients(c, w, r, g, b, C)
+        out = out + Ew
+        pa = np.concatenate([pa, Ew[None]])
     return (out, pa) if parts else out
 
 
+def weight_coefficients(coords, w, rho, gam, b, C):
+    """rho_i (beta + E_i): the coefficient of w^A_i in E^A_w and of w^{AB}_i in
+    the first sum of E^{AB}_{w,w} (Sections II.A, II.B)."""
+    E = pair_integrals(coords, w, rho, gam, b, C)[0]
+    return _f64(rho) * (beta(b) + E)
+
+
+def weight_integrals(coords, rho, gam, b, C, w_x):
+    """E^{xw}_i, U^{xw}_i, W^{xw}_i for every column x of w_x, each [P, n]
+    (Section II.B)."""
+    c, r, g, wx = map(_f64, (coords, rho, gam, w_x))
+    n = r.shape[0]
+    P = wx.shape[0]
+    Ew, Uw, Ww = (np.zeros((P, n)) for _ in range(3))
+    _load().oracle_weight_integrals(n, _ptr(c), _ptr(r), _ptr(g), b, C, P, _ptr(wx),
+                                    _ptr(Ew), _ptr(Uw), _ptr(Ww))
+    return Ew, Uw, Ww
+
+
+def _partials(b, C, rho, gam):
+    n = len(rho)
+    kr, orr, og = np.zeros(n), np.zeros(n), np.zeros(n)
+    for i in range(n):
+        pt = point(b, C, float(rho[i]), float(gam[i]))
+        kr[i], orr[i], og[i] = pt["kappa_r"], pt["omega_r"], pt["omega_g"]
+    return kr, orr, og
+
+
+def hessian_weight_terms(atom_of, n_atom, coords, w, rho, gam, b, C, rho_x, gam_x, w_x):
+    """The weight terms of the nine-term Hessian split (Section II.B) other
+    than the caller's sum_i w^{AB}_i rho_i (beta + E_i):
+      E_ww  = sum_i w^A_i rho_i E^{Bw}_i                    (second sum of E_{w,w})
+      E_Gw  = sum_i w^B_i (f^rho_i rho^A_i + f^gamma_i gamma^A_i)
+            + sum_i w_i rho^A_i (E^{Bw}_i + rho_i (kappa_r U^{Bw}_i + omega_r W^{Bw}_i))
+            + sum_i w_i gamma^A_i rho_i omega_g W^{Bw}_i
+      E_wgr = sum_i w^A_i rho_i E^{Bgr}_i
+    returned as E_ww + E_Gw + E_Gw^T + E_wgr + E_wgr^T, with the parts."""
+    rho, w, wx = _f64(rho), _f64(w), _f64(w_x)
+    n = len(w)
+    P = wx.shape[0]
+    _, fr, fg = energy_potential(coords, w, rho, gam, b, C)
+    Ew, Uw, Ww = weight_integrals(coords, rho, gam, b, C, wx)
+    Egr, _, _ = grid_vectors(atom_of, n_atom, coords, w, rho, gam, b, C)
+    Egr_x = Egr.reshape(n, P).T                      # [x = (B, a), i]
+    kr, orr, og = _partials(b, C, rho, gam)
+    rx, gx = _f64(rho_x), _f64(gam_x)
+    Eww = (wx * rho) @ Ew.T
+    EGw = ((fr * rx + fg * gx) @ wx.T
+           + (w * rx) @ (Ew + rho * (kr * Uw + orr * Ww)).T
+           + (w * gx) @ (rho * og * Ww).T)
+    Ewgr = (wx * rho) @ Egr_x.T
+    return Eww + EGw + EGw.T + Ewgr + Ewgr.T, (Eww, EGw, Ewgr)
+
+
+def weight_second_term(w_xy, coef):
+    """sum_i w^{AB}_i rho_i (beta + E_i): the first sum of E_{w,w} (Section II.B),
+    from the second nuclear derivatives of the weights [P, P, n] and
+    weight_coefficients."""
+    return _f64(w_xy) @ _f64(coef)
+
+
 def hessian_terms(atom_of, n_atom, coords, w, rho, gam, b, C, rho_x, gam_x,
-                  parts=False, resp=False):
-    """H_nl = E_GG (no rho^{AB} term) + E_Ggr + E_Ggr^T + E_grgr, symmetrised.
+                  parts=False, resp=False, w_x=None):
+    """H_nl = E_GG (no rho^{AB} term) + E_Ggr + E_Ggr^T + E_grgr, symmetrised,
+    plus, when the weight derivatives w_x [P, n] are given, the weight terms
+    of hessian_weight_terms (no w^{AB} term).
 
     Returns (H, info) where info has 'asym' and optionally 'parts'
-    ([3, P, P]: GG, Ggr + Ggr^T, grgr) and 'resp' (Yr, Yg as [P, n])."""
+    ([3, P, P]: GG, Ggr + Ggr^T, grgr; with w_x also 'wparts': E_ww, E_Gw,
+    E_wgr) and 'resp' (Yr, Yg as [P, n])."""
     c, w, r, g, rx, gx = map(_f64, (coords, w, rho, gam, rho_x, gam_x))
     ao = np.ascontiguousarray(atom_of, dtype=np.int32)
     n = w.shape[0]
@@ -203,6 +274,12 @@ def hessian_terms(atom_of, n_atom, coords, w, rho, gam, b, C, rho_x, gam_x,
     if rc:
         raise ValueError(f"oracle_hessian_terms failed: {rc}")
     info = {"asym": float(asym[0])}
+    if w_x is not None:
+        HW, wparts = hessian_weight_terms(atom_of, n_atom, coords, w, rho, gam, b, C, rho_x,
+                                          gam_x, w_x)
+        H = H + 0.5 * (HW + HW.T)
+        if parts:
+            info["wparts"] = wparts
     if parts:
         info["parts"] = pa
     if resp:
@@ -210,7 +287,7 @@ def hessian_terms(atom_of, n_atom, coords, w, rho, gam, b, C, rho_x, gam_x,
     return H, info
 
 
-def fock_nuclear_terms(atom_of, n_atom, coords, w, rho, gam, b, C, rho_x, gam_x):
+def fock_nuclear_terms(atom_of, n_atom, coords, w, rho, gam, b, C, rho_x, gam_x, w_x=None):
     """Grid-level coefficients of the VV10 Fock nuclear derivative (Section II.B,
     the second line of F^A_{mu nu,G} and F^A_{mu nu,gr}; weight terms zero): for
     perturbation x = 3 B + a and point i,
@@ -219,20 +296,26 @@ def fock_nuclear_terms(atom_of, n_atom, coords, w, rho, gam, b, C, rho_x, gam_x)
       v_gamma[x][i] = sum_j w_j (f^{gamma rho}_ij rho^x_j + f^{gamma gamma}_ij gamma^x_j)
                       + rho_i omega_g W^{Bgr}_{i,a}
     (the coefficients of w_i phi_mu phi_nu and of 2 w_i grad rho . grad(phi_mu phi_nu)),
-    with the own-atom slot of E/U/W^{Bgr} from translational invariance."""
+    with the own-atom slot of E/U/W^{Bgr} from translational invariance.
+    With the weight derivatives w_x, the F^A_w coefficients of the same two
+    products are added (its second and third lines):
+      v_rho   += E^{xw}_i + rho_i (kappa_r U^{xw}_i + omega_r W^{xw}_i)
+      v_gamma += rho_i omega_g W^{xw}_i
+    (its first line, w^x_i times f^rho_i and f^gamma_i, belongs to the caller)."""
     n = len(w)
     Yr, Yg = response_rows(0, n, coords, w, rho, gam, b, C, rho_x, gam_x)
     E, U, W = grid_vectors(atom_of, n_atom, coords, w, rho, gam, b, C)
-    kr, orr, og = np.zeros(n), np.zeros(n), np.zeros(n)
-    for i in range(n):
-        pt = point(b, C, float(rho[i]), float(gam[i]))
-        kr[i], orr[i], og[i] = pt["kappa_r"], pt["omega_r"], pt["omega_g"]
+    kr, orr, og = _partials(b, C, rho, gam)
     P = 3 * n_atom
     vr, vg = Yr.copy(), Yg.copy()
     for x in range(P):
         B, a = divmod(x, 3)
         vr[x] += E[:, B, a] + rho * (kr * U[:, B, a] + orr * W[:, B, a])
         vg[x] += rho * og * W[:, B, a]
+    if w_x is not None:
+        Ew, Uw, Ww = weight_integrals(coords, rho, gam, b, C, w_x)
+        vr += Ew + rho * (kr * Uw + orr * Ww)
+        vg += rho * og * Ww
     return vr, vg
 
 

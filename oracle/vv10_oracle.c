@@ -14,9 +14,11 @@
  *  - rho^x_i, gamma^x_i are total derivatives with the grid point moving with
  *    its owner atom, and gamma^x = 2 grad(rho) . grad(rho)^x;
  *  - f^{xy}_{ij} is normalised so that d2E/dx_i dy_j = w_i w_j f^{xy}_{ij};
- *  - quadrature weights do not depend on nuclear positions (they depend only
- *    on the distance to the owner atom), so all weight-derivative terms of
- *    the gradient and Hessian are identically zero and are not evaluated;
+ *  - the weight-derivative terms (E_w, E_{w,w}, E_{G,w}, E_{w,gr}) are zero
+ *    for weights that depend only on the distance to the owner atom; for
+ *    position-dependent weights the C functions here provide the
+ *    weight-perturbed inner integrals E^{Bw}, U^{Bw}, W^{Bw}, and the
+ *    Python wrapper composes the terms from them;
  *  - the returned "Hessian terms" exclude the caller's
  *    sum_i w_i (f^rho_i rho^{AB}_i + f^gamma_i gamma^{AB}_i).
  *  - No density cutoff and no screening.
@@ -594,6 +596,46 @@ int oracle_hessian_terms(int64_t n, int32_t n_atom, const int32_t *atom_of,
     if (!resp_gamma) free(Yg);
     free(I); free(pt); free(seg);
     return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Weight-perturbed inner integrals (Section II.B), for every column x   */
+/* of w_x (the nuclear derivatives of the weights, [P][n]):             */
+/*   E^{xw}_i = sum_j w^x_j rho_j Phi_ij                                 */
+/*   U^{xw}_i = -sum_j w^x_j rho_j Phi_ij (1/(g + g') + 1/g)              */
+/*   W^{xw}_i = -sum_j w^x_j rho_j Phi_ij R^2 (1/(g + g') + 1/g)          */
+/* Ew, Uw, Ww are [P][n].                                               */
+/* ------------------------------------------------------------------ */
+void oracle_weight_integrals(int64_t n, const double *coords, const double *rho,
+                             const double *gamma, double b, double C, int32_t n_pert,
+                             const double *w_x, double *Ew, double *Uw, double *Ww)
+{
+    double *pt = all_points(n, rho, gamma, b, C);
+#pragma omp parallel
+    {
+        double *e = (double *)malloc(sizeof(double) * (size_t)n_pert * 3);
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            memset(e, 0, sizeof(double) * (size_t)n_pert * 3);
+            for (int64_t j = 0; j < n; ++j) {
+                pair_t p = pair_terms(coords + 3 * i, coords + 3 * j, pt + PT_N * i, pt + PT_N * j);
+                double h = 1.0 / p.s + 1.0 / p.g;
+                for (int32_t x = 0; x < n_pert; ++x) {
+                    double wr = w_x[(size_t)x * n + j] * rho[j];
+                    e[3 * x + 0] += wr * p.phi;
+                    e[3 * x + 1] += -wr * p.phi * h;
+                    e[3 * x + 2] += -wr * p.phi * p.R2 * h;
+                }
+            }
+            for (int32_t x = 0; x < n_pert; ++x) {
+                Ew[(size_t)x * n + i] = e[3 * x + 0];
+                Uw[(size_t)x * n + i] = e[3 * x + 1];
+                Ww[(size_t)x * n + i] = e[3 * x + 2];
+            }
+        }
+        free(e);
+    }
+    free(pt);
 }
 
 int oracle_num_threads(void)

@@ -17,10 +17,21 @@ Recipe (atomic units, bohr):
   * grid: n_pa points per atom at R_A + r u with ln r uniform on
     [ln 0.05, ln 10] and u uniform on the unit sphere; points are stored
     grouped by owning atom (atom_of is nondecreasing);
-  * weights: w = 1/(N q(r)) with q(r) = 1/(4 pi r^3 ln(10/0.05)) the
-    three-dimensional density of one atom's sampler and N the total number of
-    points, so each atom's point set is an unbiased estimate of the
-    whole-space integral and the sets are averaged;
+  * weights, two kinds:
+    - "atomic" (default): w = 1/(N q(r)) with q(r) = 1/(4 pi r^3 ln(10/0.05))
+      the three-dimensional density of one atom's sampler and N the total
+      number of points, so each atom's point set is an unbiased estimate of
+      the whole-space integral and the sets are averaged.  w depends only on
+      the distance to the owner atom, so it has no nuclear derivatives;
+    - "becke": Becke's fuzzy-cell partition (A. D. Becke, J. Chem. Phys. 88,
+      2547 (1988), equal atomic sizes): w_i = 1/(n_A q(r)) P_A(r_i) /
+      sum_C P_C(r_i) for a point of atom A with n_A points, where
+      P_C(r) = prod_{D != C} s(mu_CD), mu_CD = (|r - R_C| - |r - R_D|)/|R_C - R_D|,
+      s(mu) = (1 - f(f(f(mu))))/2 and f(x) = 3x/2 - x^3/2.  Each atom's set
+      integrates its own cell.  These weights move with every nucleus; their
+      first and second nuclear derivatives (grid points moving with their
+      owner atoms) come from a forward-mode evaluation of the same formula
+      that carries exact derivatives through every operation;
   * density: rho(r) = sum_A Z_A zeta_A^3/pi exp(-2 zeta_A |r - R_A|) with
     zeta_O = 2, zeta_H = 1 and analytic gradient;
   * nuclear derivatives: the total derivative of rho(r_i) and grad rho(r_i)
@@ -74,6 +85,9 @@ class Problem:
     radii: np.ndarray       # [N] distance of each point to its owner atom
     rho_x: np.ndarray | None = None       # [P, N]
     grad_rho_x: np.ndarray | None = None  # [P, N, 3]
+    weight_kind: str = "atomic"
+    w_x: np.ndarray | None = None         # [P, N] weight derivatives (becke only)
+    w_xy: np.ndarray | None = None        # [P, P, N] second derivatives (on request)
     b: float = VV10_B
     C: float = VV10_C
     seed: int = 0
@@ -155,6 +169,180 @@ def grid_weights(radii: np.ndarray) -> np.ndarray:
     return 4.0 * math.pi * radii ** 3 * math.log(R_MAX / R_MIN) / n
 
 
+class _Jet:
+    """A field over the grid points with its derivatives with respect to the
+    3 n_atom nuclear coordinates: value v [N], gradient g [N, P] (order >= 1)
+    and Hessian h [N, P, P] (order 2).  A leading dimension of 1 broadcasts
+    over the points (quantities that do not depend on the point)."""
+
+    __slots__ = ("v", "g", "h")
+
+    def __init__(self, v, g=None, h=None):
+        self.v, self.g, self.h = v, g, h
+
+    def __add__(self, o):
+        return _Jet(self.v + o.v, None if self.g is None else self.g + o.g,
+                    None if self.h is None else self.h + o.h)
+
+    def __sub__(self, o):
+        return _Jet(self.v - o.v, None if self.g is None else self.g - o.g,
+                    None if self.h is None else self.h - o.h)
+
+    def __mul__(self, o):
+        v = self.v * o.v
+        g = h = None
+        if self.g is not None:
+            g = self.v[:, None] * o.g + o.v[:, None] * self.g
+        if self.h is not None:
+            h = (self.v[:, None, None] * o.h + o.v[:, None, None] * self.h
+                 + self.g[:, :, None] * o.g[:, None, :] + o.g[:, :, None] * self.g[:, None, :])
+        return _Jet(v, g, h)
+
+    def chain(self, f, fp, fpp):
+        """F(self) for a scalar function with values f, F' = fp, F'' = fpp at self.v."""
+        g = h = None
+        if self.g is not None:
+            g = fp[:, None] * self.g
+        if self.h is not None:
+            h = fp[:, None, None] * self.h + fpp[:, None, None] * (self.g[:, :, None] * self.g[:, None, :])
+        return _Jet(f, g, h)
+
+    def recip(self):
+        iv = 1.0 / self.v
+        return self.chain(iv, -iv * iv, 2.0 * iv * iv * iv)
+
+    def rows(self, idx):
+        return _Jet(self.v[idx], None if self.g is None else self.g[idx],
+                    None if self.h is None else self.h[idx])
+
+
+def _distance_jet(d: np.ndarray, sel: np.ndarray, order: int) -> _Jet:
+    """|d| for d = X - Y with dX/dR_A - dY/dR_A = sel[:, A] I: d [K, 3],
+    sel [K, n_atom] in {-1, 0, 1}."""
+    u = np.sqrt(np.einsum("ka,ka->k", d, d))
+    if order == 0:
+        return _Jet(u)
+    e = d / u[:, None]
+    K, M = sel.shape
+    g = (sel[:, :, None] * e[:, None, :]).reshape(K, 3 * M)
+    h = None
+    if order >= 2:
+        T = (np.eye(3)[None] - e[:, :, None] * e[:, None, :]) / u[:, None, None]
+        h = np.einsum("ka,kb,kxy->kaxby", sel, sel, T).reshape(K, 3 * M, 3 * M)
+    return _Jet(u, g, h)
+
+
+def _becke_step(mu: np.ndarray):
+    """s(mu) = (1 - f(f(f(mu))))/2 with f(x) = 3x/2 - x^3/2, and s', s''."""
+    f = lambda x: 1.5 * x - 0.5 * x ** 3
+    fp = lambda x: 1.5 - 1.5 * x * x
+    fpp = lambda x: -3.0 * x
+    x1 = f(mu)
+    x2 = f(x1)
+    x3 = f(x2)
+    d1 = fp(x2) * fp(x1) * fp(mu)
+    d2 = fpp(x2) * (fp(x1) * fp(mu)) ** 2 + fp(x2) * (fpp(x1) * fp(mu) ** 2 + fp(x1) * fpp(mu))
+    return 0.5 * (1.0 - x3), -0.5 * d1, -0.5 * d2
+
+
+def _becke_cells_order1(mol: Molecule, atom_of: np.ndarray, pts: np.ndarray):
+    """Cell functions P_C (values [M][N]) with first derivatives ([M][N, M, 3]),
+    exploiting that mu_CD depends only on R_{O(i)}, R_C and R_D."""
+    M = mol.n_atom
+    N = atom_of.shape[0]
+    ar = np.arange(N)
+    d = [pts - mol.R[C] for C in range(M)]
+    u = [np.sqrt(np.einsum("ka,ka->k", x, x)) for x in d]
+    e = [d[C] / u[C][:, None] for C in range(M)]
+    vals, grads = [], []
+    for C in range(M):
+        v = np.ones(N)
+        g = np.zeros((N, M, 3))
+        for D in range(M):
+            if D == C:
+                continue
+            dd = mol.R[C] - mol.R[D]
+            dist = math.sqrt(float(dd @ dd))
+            nCD = dd / dist
+            mu = (u[C] - u[D]) / dist
+            s, sp, _ = _becke_step(mu)
+            c = (v * sp / dist)[:, None]
+            g *= s[:, None, None]
+            # d mu / dR_A = (sel_C[A] e_C - sel_D[A] e_D)/|R_CD| - mu (delta_AC - delta_AD) n_CD/|R_CD|
+            # with sel_X[A] = delta_{A,O(i)} - delta_{A,X}
+            g[ar, atom_of, :] += c * (e[C] - e[D])
+            g[:, C, :] -= c * (e[C] + mu[:, None] * nCD)
+            g[:, D, :] += c * (e[D] + mu[:, None] * nCD)
+            v = v * s
+        vals.append(v)
+        grads.append(g)
+    return vals, grads
+
+
+def becke_weights(mol: Molecule, atom_of: np.ndarray, offsets: np.ndarray,
+                  radii: np.ndarray, order: int = 0, jets: bool = False):
+    """Becke-partitioned weights of points r_i = R_{O(i)} + offsets_i and their
+    total nuclear derivatives: (w [N], w_x [P, N] or None, w_xy [P, P, N] or None)
+    for order 0, 1, 2.  Order 1 uses the sparse structure of mu_CD unless
+    jets is set (then the general forward-mode path, as for order 2)."""
+    M = mol.n_atom
+    N = atom_of.shape[0]
+    pts = mol.R[atom_of] + offsets
+    counts = np.bincount(atom_of, minlength=M)
+    w_rad = 4.0 * math.pi * radii ** 3 * math.log(R_MAX / R_MIN) / counts[atom_of]
+    if order == 1 and not jets:
+        vals, grads = _becke_cells_order1(mol, atom_of, pts)
+        cell = [_Jet(vals[C], grads[C].reshape(N, 3 * M)) for C in range(M)]
+        Z = cell[0]
+        for C in range(1, M):
+            Z = Z + cell[C]
+        own = _Jet(np.empty(N), np.empty((N, 3 * M)))
+        for C in range(M):
+            idx = np.nonzero(atom_of == C)[0]
+            own.v[idx] = vals[C][idx]
+            own.g[idx] = cell[C].g[idx]
+        wj = own * Z.recip()
+        return w_rad * wj.v, np.ascontiguousarray((w_rad[:, None] * wj.g).T), None
+    owner = np.zeros((N, M))
+    owner[np.arange(N), atom_of] = 1.0
+    u = []
+    for C in range(M):
+        sel = owner.copy()
+        sel[:, C] -= 1.0
+        u.append(_distance_jet(pts - mol.R[C], sel, order))
+    cell = []
+    for C in range(M):
+        PC = _Jet(np.ones(N), np.zeros((N, 3 * M)) if order >= 1 else None,
+                  np.zeros((N, 3 * M, 3 * M)) if order >= 2 else None)
+        for D in range(M):
+            if D == C:
+                continue
+            sel = np.zeros((1, M))
+            sel[0, C], sel[0, D] = 1.0, -1.0
+            dCD = _distance_jet((mol.R[C] - mol.R[D])[None], sel, order)
+            mu = (u[C] - u[D]) * dCD.recip()
+            PC = PC * mu.chain(*_becke_step(mu.v))
+        cell.append(PC)
+    Z = cell[0]
+    for C in range(1, M):
+        Z = Z + cell[C]
+    own = _Jet(np.empty(N), np.empty((N, 3 * M)) if order >= 1 else None,
+               np.empty((N, 3 * M, 3 * M)) if order >= 2 else None)
+    for C in range(M):
+        idx = np.nonzero(atom_of == C)[0]
+        r = cell[C].rows(idx)
+        own.v[idx] = r.v
+        if order >= 1:
+            own.g[idx] = r.g
+        if order >= 2:
+            own.h[idx] = r.h
+    wj = (own * Z.recip())
+    w = w_rad * wj.v
+    w_x = None if order < 1 else np.ascontiguousarray((w_rad[:, None] * wj.g).T)
+    w_xy = None if order < 2 else np.ascontiguousarray(np.moveaxis(w_rad[:, None, None] * wj.h, 0, 2))
+    return w, w_x, w_xy
+
+
 def _slater_terms(mol: Molecule, A: int, pts: np.ndarray, order: int):
     """Value, gradient and (order >= 2) Hessian of f_A(r) = Z z^3/pi e^{-2 z |r - R_A|}."""
     z = mol.zeta[A]
@@ -206,13 +394,24 @@ def density_derivatives(mol: Molecule, atom_of: np.ndarray, pts: np.ndarray):
 
 
 def build_problem(mol: Molecule, atom_of, offsets, radii, with_derivatives=True,
-                  seed=0) -> Problem:
+                  seed=0, weights: str = "atomic", weight_hessian: bool = False) -> Problem:
+    """weights = "atomic" or "becke"; for "becke" with derivatives, w_x (and,
+    with weight_hessian, w_xy) are filled."""
     coords = mol.R[atom_of] + offsets
-    w = grid_weights(radii)
+    atom_of = np.ascontiguousarray(atom_of, dtype=np.int32)
+    w_x = w_xy = None
+    if weights == "atomic":
+        w = grid_weights(radii)
+    elif weights == "becke":
+        order = 0 if not with_derivatives else (2 if weight_hessian else 1)
+        w, w_x, w_xy = becke_weights(mol, atom_of, offsets, radii, order)
+    else:
+        raise ValueError(f"unknown weight kind {weights!r}")
     rho, grad, _ = model_density(mol, coords)
-    p = Problem(mol=mol, atom_of=np.ascontiguousarray(atom_of, dtype=np.int32),
+    p = Problem(mol=mol, atom_of=atom_of,
                 offsets=offsets, coords=np.ascontiguousarray(coords), weights=w,
-                rho=rho, grad_rho=np.ascontiguousarray(grad), radii=radii, seed=seed)
+                rho=rho, grad_rho=np.ascontiguousarray(grad), radii=radii, seed=seed,
+                weight_kind=weights, w_x=w_x, w_xy=w_xy)
     if with_derivatives:
         rx, gx = density_derivatives(mol, p.atom_of, coords)
         p.rho_x = np.ascontiguousarray(rx)
@@ -220,25 +419,29 @@ def build_problem(mol: Molecule, atom_of, offsets, radii, with_derivatives=True,
     return p
 
 
-def make_problem(n_water: int, n_pa: int, seed: int, with_derivatives=True) -> Problem:
+def make_problem(n_water: int, n_pa: int, seed: int, with_derivatives=True,
+                 weights: str = "atomic", weight_hessian: bool = False) -> Problem:
     rng = np.random.default_rng(seed)
     mol = water_cluster(n_water, rng)
     atom_of, offsets, radii = atom_grid(mol.n_atom, n_pa, rng)
-    return build_problem(mol, atom_of, offsets, radii, with_derivatives, seed)
+    return build_problem(mol, atom_of, offsets, radii, with_derivatives, seed, weights,
+                         weight_hessian)
 
 
-def make_workload(name: str, with_derivatives=True) -> Problem:
+def make_workload(name: str, with_derivatives=True, weights: str = "atomic") -> Problem:
     cfg = WORKLOADS[name]
-    return make_problem(cfg["n_water"], cfg["n_pa"], cfg["seed"], with_derivatives)
+    return make_problem(cfg["n_water"], cfg["n_pa"], cfg["seed"], with_derivatives, weights)
 
 
 def displaced(p: Problem, atom: int, axis: int, h: float, with_derivatives=False) -> Problem:
     """The same problem with nucleus `atom` moved by h along `axis`; its grid
-    points move with it and every weight stays the same."""
+    points move with it.  Atomic weights stay the same; Becke weights are
+    re-evaluated at the new geometry."""
     R = p.mol.R.copy()
     R[atom, axis] += h
     mol = Molecule(Z=p.mol.Z, zeta=p.mol.zeta, R=R)
-    return build_problem(mol, p.atom_of, p.offsets, p.radii, with_derivatives, p.seed)
+    return build_problem(mol, p.atom_of, p.offsets, p.radii, with_derivatives, p.seed,
+                         p.weight_kind)
 
 
 def trial_densities(p: Problem, n_t: int, seed: int, scale: float = 0.2):

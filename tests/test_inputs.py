@@ -105,3 +105,80 @@ def test_trial_densities_gradient_and_seed():
             q2.coords[k, ax] -= h
             d = (inputs.trial_densities(q1, 3, 9)[0][:, k] - inputs.trial_densities(q2, 3, 9)[0][:, k]) / (2 * h)
             assert np.allclose(d, gt[:, k, ax], rtol=1e-6, atol=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# Becke-partitioned weights
+# ---------------------------------------------------------------------------
+def test_becke_step_function_values():
+    """s(-1) = 1, s(0) = 1/2, s(1) = 0, s(mu) + s(-mu) = 1, and s', s'' against
+    central differences."""
+    mu = np.linspace(-1.0, 1.0, 41)
+    s, sp, spp = inputs._becke_step(mu)
+    assert s[0] == 1.0 and s[20] == 0.5 and s[-1] == 0.0
+    assert np.max(np.abs(s + s[::-1] - 1.0)) < 1e-15
+    h = 1e-5
+    sph = (inputs._becke_step(mu + h)[0] - inputs._becke_step(mu - h)[0]) / (2 * h)
+    spph = (inputs._becke_step(mu + h)[1] - inputs._becke_step(mu - h)[1]) / (2 * h)
+    assert np.max(np.abs(sph - sp)) < 1e-8 and np.max(np.abs(spph - spp)) < 1e-7
+
+
+def test_becke_partition_of_unity():
+    """Summed over the owner atom, the partition weights P_A / sum_C P_C of any
+    point are 1: the same point offered to every atom gets weights that add up
+    to the radial weight."""
+    rng = np.random.default_rng(3)
+    mol = inputs.water_cluster(2, rng)
+    pts = rng.standard_normal((50, 3)) * 3.0
+    M = mol.n_atom
+    tot = np.zeros(50)
+    for A in range(M):
+        ao = np.full(50, A, dtype=np.int32)
+        off = pts - mol.R[A]
+        r = np.linalg.norm(off, axis=1)
+        w, _, _ = inputs.becke_weights(mol, ao, off, r)
+        tot += w / (4 * np.pi * r ** 3 * np.log(inputs.R_MAX / inputs.R_MIN) / 50)
+    assert np.max(np.abs(tot - 1.0)) < 1e-14
+
+
+def test_becke_weights_integrate_density():
+    """Each atom integrates its own cell: sum_i w_i rho_i is close to the 20
+    electrons of a water dimer (closer than the averaged atomic sets)."""
+    p = inputs.make_workload("water_dimer", with_derivatives=False, weights="becke")
+    n_el = float(np.dot(p.weights, p.rho))
+    assert 18.0 < n_el < 22.0
+
+
+def test_becke_weight_derivatives_fd(becke_dimer):
+    """w_x and w_xy are total derivatives with the grid moving with its owner:
+    central differences of the weights and of w_x on displaced geometries."""
+    p = becke_dimer
+    h = 1e-4
+    for x in range(p.n_pert):
+        A, a = divmod(x, 3)
+        qp = inputs.displaced(p, A, a, h, with_derivatives=True)
+        qm = inputs.displaced(p, A, a, -h, with_derivatives=True)
+        fd = (qp.weights - qm.weights) / (2 * h)
+        assert np.max(np.abs(fd - p.w_x[x])) < 1e-6 * np.max(np.abs(p.w_x))
+        fd2 = (qp.w_x - qm.w_x) / (2 * h)
+        assert np.max(np.abs(fd2 - p.w_xy[:, x])) < 1e-5 * np.max(np.abs(p.w_xy))
+    assert np.max(np.abs(p.w_xy - p.w_xy.transpose(1, 0, 2))) < 1e-12 * np.max(np.abs(p.w_xy))
+
+
+def test_becke_weight_invariances(becke_dimer):
+    """A rigid translation of molecule and grid leaves every weight unchanged:
+    sum over atoms of w^{(B,a)}_i and of w^{(B,a)(C,b)}_i vanish."""
+    p = becke_dimer
+    s = p.w_x.reshape(p.n_atom, 3, -1).sum(axis=0)
+    assert np.max(np.abs(s)) < 1e-12 * np.max(np.abs(p.w_x))
+    s2 = p.w_xy.reshape(p.n_atom, 3, p.n_pert, -1).sum(axis=0)
+    assert np.max(np.abs(s2)) < 1e-12 * np.max(np.abs(p.w_xy))
+
+
+def test_becke_sparse_and_general_paths_agree(becke_dimer):
+    p = becke_dimer
+    w1, wx1, _ = inputs.becke_weights(p.mol, p.atom_of, p.offsets, p.radii, 1)
+    w2, wx2, _ = inputs.becke_weights(p.mol, p.atom_of, p.offsets, p.radii, 1, jets=True)
+    assert np.max(np.abs(w1 - w2)) <= 1e-14 * np.max(np.abs(w2))
+    assert np.max(np.abs(wx1 - wx2)) <= 1e-13 * np.max(np.abs(wx2))
+    assert np.array_equal(wx2, p.w_x) or np.max(np.abs(wx2 - p.w_x)) <= 1e-13 * np.max(np.abs(wx2))

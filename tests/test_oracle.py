@@ -416,3 +416,124 @@ def test_unsorted_grid_rejected(tiny_problem):
     ao = p.atom_of.copy()[::-1].copy()
     with pytest.raises(ValueError):
         oracle.hessian_terms(ao, p.n_atom, p.coords, p.weights, p.rho, g, p.b, p.C, p.rho_x, gx)
+
+
+# ---------------------------------------------------------------------------
+# Position-dependent (Becke) weights: the weight terms of Sections II.A, II.B
+# ---------------------------------------------------------------------------
+def test_weight_integrals_special_case(small_dimer):
+    """With w^x = w the weight-perturbed integrals are the plain E_i, U_i, W_i."""
+    p = small_dimer
+    g = oracle.gamma(p.grad_rho)
+    Ew, Uw, Ww = oracle.weight_integrals(p.coords, p.rho, g, p.b, p.C, p.weights[None])
+    I = oracle.pair_integrals(p.coords, p.weights, p.rho, g, p.b, p.C)
+    for got, want in ((Ew, I[0]), (Uw, I[1]), (Ww, I[2])):
+        assert np.max(np.abs(got[0] - want)) < 1e-13 * np.max(np.abs(want))
+
+
+def test_weight_integrals_are_weight_derivatives(becke_dimer):
+    """E^{xw}_i, U^{xw}_i, W^{xw}_i are the derivatives of E_i, U_i, W_i along
+    w + h w^x with everything else fixed."""
+    p = becke_dimer
+    g = oracle.gamma(p.grad_rho)
+    Ew, Uw, Ww = oracle.weight_integrals(p.coords, p.rho, g, p.b, p.C, p.w_x)
+    for x in (0, 7, 16):
+        d = richardson(lambda h: oracle.pair_integrals(p.coords, p.weights + h * p.w_x[x], p.rho,
+                                                       g, p.b, p.C)[:3], 1e-2)
+        for k, got in enumerate((Ew, Uw, Ww)):
+            assert np.max(np.abs(d[k] - got[x])) < 1e-11 * np.max(np.abs(got[x]))
+
+
+def test_gradient_fd_becke(becke_dimer):
+    """With Becke weights E_w is nonzero, and E_G + E_w + E_gr matches central
+    differences of E (weights re-evaluated on each displaced geometry); the
+    gradient without E_w does not."""
+    p = becke_dimer
+    g, gx = oracle.problem_inputs(p)
+    G, parts = oracle.gradient(p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b, p.C,
+                               p.rho_x, gx, parts=True, w_x=p.w_x)
+    scale = np.max(np.abs(G))
+    assert np.max(np.abs(parts[2])) > 0.01 * scale
+    for x in range(p.n_pert):
+        A, a = divmod(x, 3)
+        d = richardson(lambda h: _ep(inputs.displaced(p, A, a, h))[0], 1e-3)
+        assert abs(d - G[x]) < 1e-9 * scale
+        assert abs(d - parts[0][x] - parts[1][x]) > 1e-6 * scale or abs(parts[2][x]) < 1e-6 * scale
+    assert np.max(np.abs(G.reshape(-1, 3).sum(0))) < 1e-12 * scale
+
+
+def _frozen_gradient_w(p, q, gx, w_x):
+    gq = oracle.gamma(q.grad_rho)
+    return oracle.gradient(q.atom_of, q.n_atom, q.coords, q.weights, q.rho, gq, q.b, q.C,
+                           p.rho_x, gx, w_x=w_x)
+
+
+def test_hessian_terms_fd_becke_frozen(becke_dimer):
+    """With rho^x, gamma^x and w^x frozen, the derivative of the gradient is
+    H_nl with the weight terms (E_ww second sum, E_Gw + E_Gw^T,
+    E_wgr + E_wgr^T) and without the w^{AB} and rho^{AB} sums."""
+    p = becke_dimer
+    g, gx = oracle.problem_inputs(p)
+    H, info = oracle.hessian_terms(p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b,
+                                   p.C, p.rho_x, gx, w_x=p.w_x, parts=True)
+    H0, _ = oracle.hessian_terms(p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b,
+                                 p.C, p.rho_x, gx)
+    scale = np.max(np.abs(H))
+    assert np.max(np.abs(H - H0)) > 0.01 * scale
+    for y in range(p.n_pert):
+        B, b = divmod(y, 3)
+        d = richardson(lambda h: _frozen_gradient_w(p, inputs.displaced(p, B, b, h), gx, p.w_x),
+                       1e-3)
+        assert np.max(np.abs(d - H[:, y])) < 1e-9 * scale
+    Eww = info["wparts"][0]
+    assert np.max(np.abs(Eww - Eww.T)) < 1e-12 * np.max(np.abs(Eww))
+    s = H.reshape(p.n_pert, p.n_atom, 3).sum(axis=1)
+    assert np.max(np.abs(s)) < 1e-11 * scale
+
+
+def test_hessian_weight_second_term_fd(becke_dimer):
+    """With w^x re-evaluated on the displaced geometry (rho^x, gamma^x still
+    frozen), the derivative adds sum_i w^{AB}_i rho_i (beta + E_i)."""
+    p = becke_dimer
+    g, gx = oracle.problem_inputs(p)
+    H, _ = oracle.hessian_terms(p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b,
+                                p.C, p.rho_x, gx, w_x=p.w_x)
+    coef = oracle.weight_coefficients(p.coords, p.weights, p.rho, g, p.b, p.C)
+    W1 = oracle.weight_second_term(p.w_xy, coef)
+    scale = np.max(np.abs(H + W1))
+    assert np.max(np.abs(W1)) > 0.01 * scale
+    for y in (0, 5, 9, 13):
+        B, b = divmod(y, 3)
+
+        def grad_w(h):
+            q = inputs.displaced(p, B, b, h, with_derivatives=True)
+            return _frozen_gradient_w(p, q, gx, q.w_x)
+
+        d = richardson(grad_w, 1e-3)
+        assert np.max(np.abs(d - (H + W1)[:, y])) < 1e-8 * scale
+
+
+def test_fock_terms_fd_becke(becke_dimer):
+    """The Fock grid coefficients with the weight terms are the derivatives of
+    the potential when nucleus A moves with its grid and the Becke weights
+    follow; without them they are not."""
+    p = becke_dimer
+    g, gx = oracle.problem_inputs(p)
+    vr, vg = oracle.fock_nuclear_terms(p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b,
+                                       p.C, p.rho_x, gx, w_x=p.w_x)
+    vr0, _ = oracle.fock_nuclear_terms(p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b,
+                                       p.C, p.rho_x, gx)
+    n = p.n_grid
+    for x in (1, 6, 14):
+        A, a = divmod(x, 3)
+
+        def pot(h):
+            q = inputs.displaced(p, A, a, h)
+            _, fr, fgm = oracle.energy_potential(q.coords, q.weights, q.rho, oracle.gamma(q.grad_rho),
+                                                 q.b, q.C)
+            return np.concatenate([fr, fgm])
+
+        d = richardson(pot, 1e-3)
+        assert np.max(np.abs(d[:n] - vr[x])) <= 1e-9 * np.max(np.abs(vr[x]))
+        assert np.max(np.abs(d[n:] - vg[x])) <= 1e-9 * np.max(np.abs(vg[x]))
+        assert np.max(np.abs(d[:n] - vr0[x])) > 1e-4 * np.max(np.abs(vr[x]))
