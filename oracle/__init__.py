@@ -56,7 +56,7 @@ def _load():
         _lib.oracle_grid_D.argtypes = [i64, i32, i64, i32, P, P, P, P, P, d, d, P]
         _lib.oracle_gradient.restype = ctypes.c_int
         _lib.oracle_gradient.argtypes = [i64, i32, P, P, P, P, P, d, d, P, P, P, P]
-        _lib.oracle_weight_integrals.argtypes = [i64, P, P, P, d, d, i32, P, P, P, P]
+        _lib.oracle_weight_integrals.argtypes = [i64, i64, i64, P, P, P, d, d, i32, P, P, P, P]
         _lib.oracle_hessian_terms.restype = ctypes.c_int
         _lib.oracle_hessian_terms.argtypes = [i64, i32, P, P, P, P, P, d, d, i32, P, P,
                                               P, P, P, P, P]
@@ -196,14 +196,15 @@ def weight_coefficients(coords, w, rho, gam, b, C):
     return _f64(rho) * (beta(b) + E)
 
 
-def weight_integrals(coords, rho, gam, b, C, w_x):
-    """E^{xw}_i, U^{xw}_i, W^{xw}_i for every column x of w_x, each [P, n]
-    (Section II.B)."""
+def weight_integrals(coords, rho, gam, b, C, w_x, i0=0, i1=None):
+    """E^{xw}_i, U^{xw}_i, W^{xw}_i for every column x of w_x and the rows
+    i0 <= i < i1 (default all), each [P, i1 - i0] (Section II.B)."""
     c, r, g, wx = map(_f64, (coords, rho, gam, w_x))
     n = r.shape[0]
+    i1 = n if i1 is None else i1
     P = wx.shape[0]
-    Ew, Uw, Ww = (np.zeros((P, n)) for _ in range(3))
-    _load().oracle_weight_integrals(n, _ptr(c), _ptr(r), _ptr(g), b, C, P, _ptr(wx),
+    Ew, Uw, Ww = (np.zeros((P, i1 - i0)) for _ in range(3))
+    _load().oracle_weight_integrals(i0, i1, n, _ptr(c), _ptr(r), _ptr(g), b, C, P, _ptr(wx),
                                     _ptr(Ew), _ptr(Uw), _ptr(Ww))
     return Ew, Uw, Ww
 

@@ -210,11 +210,14 @@ void oracle_energy_potential(int64_t n, const double *coords, const double *w,
 /* f^{rho rho}_{ij}, f^{gamma rho}_{ij}, f^{rho gamma}_{ij},              */
 /* f^{gamma gamma}_{ij}: the pair expression for every j (j = i too),    */
 /* plus delta_ij/w_i times the local bracket built from U, W, A, B, C.   */
-/* I is [6][n] from pair_integrals_pt.                                   */
+/* I is [6][n] from pair_integrals_pt.  The bracket of the delta_ij/w_i  */
+/* term goes to loc[3] = (rho rho, gamma rho = rho gamma, gamma gamma)  */
+/* when loc is given (the caller then multiplies it by w_i itself, so a  */
+/* zero weight needs no division), else it is added over w_i.            */
 /* ------------------------------------------------------------------ */
 static void second_row(int64_t i, int64_t n, const double *coords, const double *w,
                        const double *rho, const double *pt, const double *I,
-                       double *frr, double *fgr, double *frg, double *fgg)
+                       double *frr, double *fgr, double *frg, double *fgg, double *loc)
 {
     const double *pi_ = pt + PT_N * i;
     const double wkr_i = pi_[PT_KAPPA_R], wor_i = pi_[PT_OMEGA_R], wog_i = pi_[PT_OMEGA_G];
@@ -239,6 +242,10 @@ static void second_row(int64_t i, int64_t n, const double *coords, const double 
     double loc_gr = wog_i * W + r * pi_[PT_OMEGA_RG] * W + r * wog_i * wkr_i * B
         + r * wog_i * wor_i * Cc;
     double loc_gg = r * (pi_[PT_OMEGA_GG] * W + wog_i * wog_i * Cc);
+    if (loc) {
+        loc[0] = loc_rr; loc[1] = loc_gr; loc[2] = loc_gg;
+        return;
+    }
     frr[i] += loc_rr / w[i];
     fgr[i] += loc_gr / w[i];
     frg[i] += loc_gr / w[i];
@@ -254,7 +261,8 @@ void oracle_second_matrices(int64_t n, const double *coords, const double *w,
     double *I = (double *)malloc(sizeof(double) * 6 * (size_t)n);
     pair_integrals_pt(n, coords, w, rho, pt, I);
     for (int64_t i = 0; i < n; ++i)
-        second_row(i, n, coords, w, rho, pt, I, frr + i * n, fgr + i * n, frg + i * n, fgg + i * n);
+        second_row(i, n, coords, w, rho, pt, I, frr + i * n, fgr + i * n, frg + i * n, fgg + i * n,
+                   NULL);
     free(I);
     free(pt);
 }
@@ -264,6 +272,8 @@ void oracle_second_matrices(int64_t n, const double *coords, const double *w,
 /*   Yr_{x i} = sum_j w_j (f^{rho rho}_{ij} rho^x_j + f^{rho gamma}_{ij} gamma^x_j) */
 /*   Yg_{x i} = sum_j w_j (f^{gamma rho}_{ij} rho^x_j + f^{gamma gamma}_{ij} gamma^x_j) */
 /* for rows i in [i0, i1); Yr, Yg are [n_pert][n] (only those rows set). */
+/* The j = i term w_i (delta_ii/w_i) loc is taken as loc itself (exact   */
+/* cancellation), which keeps points of zero weight finite.             */
 /* This is the dominant O(N^2 P) step of the oracle.                     */
 /* ------------------------------------------------------------------ */
 static void response_rows(int64_t i0, int64_t i1, int64_t n, const double *coords,
@@ -277,7 +287,8 @@ static void response_rows(int64_t i0, int64_t i1, int64_t n, const double *coord
         double *fgr = frr + n, *frg = frr + 2 * n, *fgg = frr + 3 * n;
 #pragma omp for schedule(static)
         for (int64_t i = i0; i < i1; ++i) {
-            second_row(i, n, coords, w, rho, pt, I, frr, fgr, frg, fgg);
+            double loc[3];
+            second_row(i, n, coords, w, rho, pt, I, frr, fgr, frg, fgg, loc);
             for (int32_t x = 0; x < n_pert; ++x) {
                 const double *rx = rho_x + (size_t)x * n, *gx = gamma_x + (size_t)x * n;
                 double yr = 0.0, yg = 0.0;
@@ -285,6 +296,8 @@ static void response_rows(int64_t i0, int64_t i1, int64_t n, const double *coord
                     yr += w[j] * (frr[j] * rx[j] + frg[j] * gx[j]);
                     yg += w[j] * (fgr[j] * rx[j] + fgg[j] * gx[j]);
                 }
+                yr += loc[0] * rx[i] + loc[1] * gx[i];
+                yg += loc[1] * rx[i] + loc[2] * gx[i];
                 Yr[(size_t)x * n + i] = yr;
                 Yg[(size_t)x * n + i] = yg;
             }
@@ -604,18 +617,20 @@ int oracle_hessian_terms(int64_t n, int32_t n_atom, const int32_t *atom_of,
 /*   E^{xw}_i = sum_j w^x_j rho_j Phi_ij                                 */
 /*   U^{xw}_i = -sum_j w^x_j rho_j Phi_ij (1/(g + g') + 1/g)              */
 /*   W^{xw}_i = -sum_j w^x_j rho_j Phi_ij R^2 (1/(g + g') + 1/g)          */
-/* Ew, Uw, Ww are [P][n].                                               */
+/* Rows i0 <= i < i1 only; Ew, Uw, Ww are [P][i1 - i0].                */
 /* ------------------------------------------------------------------ */
-void oracle_weight_integrals(int64_t n, const double *coords, const double *rho,
-                             const double *gamma, double b, double C, int32_t n_pert,
-                             const double *w_x, double *Ew, double *Uw, double *Ww)
+void oracle_weight_integrals(int64_t i0, int64_t i1, int64_t n, const double *coords,
+                             const double *rho, const double *gamma, double b, double C,
+                             int32_t n_pert, const double *w_x, double *Ew, double *Uw,
+                             double *Ww)
 {
     double *pt = all_points(n, rho, gamma, b, C);
+    int64_t m = i1 - i0;
 #pragma omp parallel
     {
         double *e = (double *)malloc(sizeof(double) * (size_t)n_pert * 3);
 #pragma omp for schedule(static)
-        for (int64_t i = 0; i < n; ++i) {
+        for (int64_t i = i0; i < i1; ++i) {
             memset(e, 0, sizeof(double) * (size_t)n_pert * 3);
             for (int64_t j = 0; j < n; ++j) {
                 pair_t p = pair_terms(coords + 3 * i, coords + 3 * j, pt + PT_N * i, pt + PT_N * j);
@@ -628,9 +643,9 @@ void oracle_weight_integrals(int64_t n, const double *coords, const double *rho,
                 }
             }
             for (int32_t x = 0; x < n_pert; ++x) {
-                Ew[(size_t)x * n + i] = e[3 * x + 0];
-                Uw[(size_t)x * n + i] = e[3 * x + 1];
-                Ww[(size_t)x * n + i] = e[3 * x + 2];
+                Ew[(size_t)x * m + (i - i0)] = e[3 * x + 0];
+                Uw[(size_t)x * m + (i - i0)] = e[3 * x + 1];
+                Ww[(size_t)x * m + (i - i0)] = e[3 * x + 2];
             }
         }
         free(e);

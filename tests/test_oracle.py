@@ -537,3 +537,30 @@ def test_fock_terms_fd_becke(becke_dimer):
         assert np.max(np.abs(d[:n] - vr[x])) <= 1e-9 * np.max(np.abs(vr[x]))
         assert np.max(np.abs(d[n:] - vg[x])) <= 1e-9 * np.max(np.abs(vg[x]))
         assert np.max(np.abs(d[:n] - vr0[x])) > 1e-4 * np.max(np.abs(vr[x]))
+
+
+def test_response_rows_zero_weight_point(tiny_problem):
+    """A point of zero weight (a Becke cell function can vanish) keeps finite
+    response rows: the delta_ij/w_i bracket of the f matrices enters
+    sum_j w_j f_ij x_j times w_i, and the rows are continuous as w_i -> 0."""
+    p = tiny_problem
+    g, gx = oracle.problem_inputs(p)
+    w0 = p.weights.copy()
+    w0[5] = 0.0
+    w1 = p.weights.copy()
+    w1[5] *= 1e-9
+    Y0 = oracle.response_rows(0, p.n_grid, p.coords, w0, p.rho, g, p.b, p.C, p.rho_x, gx)
+    Y1 = oracle.response_rows(0, p.n_grid, p.coords, w1, p.rho, g, p.b, p.C, p.rho_x, gx)
+    for a, b in zip(Y0, Y1):
+        assert np.all(np.isfinite(a))
+        assert np.max(np.abs(a - b)) < 1e-7 * np.max(np.abs(b))
+
+
+def test_weight_integrals_row_range(small_dimer):
+    p = small_dimer
+    g = oracle.gamma(p.grad_rho)
+    wx = np.random.default_rng(2).standard_normal((3, p.n_grid)) * p.weights
+    full = oracle.weight_integrals(p.coords, p.rho, g, p.b, p.C, wx)
+    part = oracle.weight_integrals(p.coords, p.rho, g, p.b, p.C, wx, 17, 40)
+    for a, b in zip(full, part):
+        assert np.array_equal(a[:, 17:40], b)
