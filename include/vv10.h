@@ -111,32 +111,52 @@ vv10_status vv10_energy_potential(vv10_plan *plan, double *energy, double *f_rho
                                   double *f_gamma);
 
 /* Outputs of vv10_nuclear_terms: each is DEVICE memory, FP64, or NULL (not
- * formed); P = 3 n_atom, perturbation x = 3 A + alpha. */
+ * formed); P = 3 n_atom, perturbation x = 3 A + alpha.  The bracketed terms
+ * are present only when weight derivatives w_x are passed. */
 typedef struct {
-    double *hess;        /* [P][P] E_{G,G} + E_{G,gr} + E_{G,gr}^T + E_{gr,gr}, symmetrised */
-    double *grad;        /* [P] nuclear gradient E_G + E_gr (Section II.A) */
+    double *hess;        /* [P][P] E_{G,G} + E_{G,gr} + E_{G,gr}^T + E_{gr,gr}
+                            [+ E_{w,w} (its second sum) + E_{G,w} + E_{G,w}^T
+                             + E_{w,gr} + E_{w,gr}^T], symmetrised */
+    double *grad;        /* [P] nuclear gradient E_G + E_gr [+ E_w] (Section II.A) */
     double *resp_rho;    /* [P][N] sum_j w_j (f^{rho rho}_ij rho^x_j + f^{rho gamma}_ij gamma^x_j) */
     double *resp_gamma;  /* [P][N] sum_j w_j (f^{gamma rho}_ij rho^x_j + f^{gamma gamma}_ij gamma^x_j) */
-    double *fock_rho;    /* [P][N] resp_rho + E^{Agr}_i + rho_i (kappa_r U^{Agr}_i + omega_r W^{Agr}_i) */
-    double *fock_gamma;  /* [P][N] resp_gamma + rho_i omega_g W^{Agr}_i */
+    double *fock_rho;    /* [P][N] resp_rho + E^{Agr}_i + rho_i (kappa_r U^{Agr}_i + omega_r W^{Agr}_i)
+                            [+ E^{Aw}_i + rho_i (kappa_r U^{Aw}_i + omega_r W^{Aw}_i)] */
+    double *fock_gamma;  /* [P][N] resp_gamma + rho_i omega_g W^{Agr}_i [+ rho_i omega_g W^{Aw}_i] */
+    double *w_coef;      /* [N] rho_i (beta + E_i): the coefficient of w^A_i in E^A_w and of
+                            w^{AB}_i in the first sum of E^{AB}_{w,w}, which the caller forms
+                            from its weights' second derivatives */
 } vv10_nuclear_outputs;
 
 /*
  * vv10_nuclear_terms -- every nuclear-perturbation output of one pass over
  * the pairs (Section II.B): the Hessian terms (below), the gradient, the
  * response rows, and the grid-level coefficients of the Fock nuclear
- * derivative F^A_{mu nu} = F^A_G + F^A_gr (weight terms zero): fock_rho
- * multiplies w_i phi_mu phi_nu and fock_gamma multiplies
- * 2 w_i grad rho . grad(phi_mu phi_nu) in the second line of F^A_G plus
- * F^A_gr; the first line of F^A_G (f^rho, f^gamma times basis-function
- * derivatives) belongs to the caller.  fock_rho/fock_gamma equal the
- * derivative of the potential f^rho, f^gamma when nucleus A moves with its
- * grid points.  Outputs set to NULL are not formed (no output: no work).
- *  n_pert, rho_x, grad_rho_x as for vv10_hessian_terms; out non-NULL.
+ * derivative F^A_{mu nu} = F^A_G + F^A_w + F^A_gr: fock_rho multiplies
+ * w_i phi_mu phi_nu and fock_gamma multiplies 2 w_i grad rho . grad(phi_mu phi_nu)
+ * in the second line of F^A_G, in F^A_gr and in the second and third lines
+ * of F^A_w; the first lines of F^A_G and F^A_w (f^rho, f^gamma times
+ * basis-function or weight derivatives) belong to the caller.
+ * fock_rho/fock_gamma equal the derivative of the potential f^rho, f^gamma
+ * when nucleus A moves with its grid points (and, with w_x, its weights).
+ * Outputs set to NULL are not formed (no output: no work).
+ *  n_pert, rho_x, grad_rho_x as for vv10_hessian_terms.
+ *  w_x   [n_pert][N] DEVICE, or NULL for weights that do not depend on the
+ *        nuclear positions: w^x_i = dw_i/dX_x with grid points moving with
+ *        their owner atoms (Section II.A, w^A_i; Becke-partitioned weights,
+ *        for example).  The entries of the owner atom (x/3 == atom_of[i]) are
+ *        not read: the library takes them from translational invariance,
+ *        w^{(O(i),b)}_i = -sum_{B != O(i)} w^{(B,b)}_i.  With w_x the Hessian
+ *        adds the weight terms of the nine-term split except
+ *        sum_i w^{AB}_i rho_i (beta + E_i), which needs the weights' second
+ *        derivatives (w_coef is its coefficient).  The first call with w_x
+ *        adds a weight workspace of about (5 + 3 jsplit) N P doubles.
+ *  out   non-NULL.
  * Errors: VV10_E_ARG, VV10_E_OOM (workspace), VV10_E_STATE, VV10_E_HIP.
  */
 vv10_status vv10_nuclear_terms(vv10_plan *plan, int32_t n_pert, const double *rho_x,
-                               const double *grad_rho_x, const vv10_nuclear_outputs *out);
+                               const double *grad_rho_x, const double *w_x,
+                               const vv10_nuclear_outputs *out);
 
 /*
  * vv10_hessian_terms -- nuclear-Hessian grid terms for all 3 n_atom
@@ -164,20 +184,23 @@ vv10_status vv10_hessian_terms(vv10_plan *plan, int32_t n_pert, const double *rh
 
 /*
  * vv10_gradient -- VV10 nuclear gradient alone (Section II.A):
- *   grad[x] = E^x_G + E^x_gr,
+ *   grad[x] = E^x_G + E^x_gr [+ E^x_w],
  *   E^x_G  = sum_i w_i (f^rho_i rho^x_i + f^gamma_i gamma^x_i),  gamma^x = 2 grad rho . grad rho^x,
- *   E^A_gr = sum_{i in A} w_i rho_i E^{Agr}_i = -sum_{B != A} sum_{i in A} w_i rho_i E^{Bgr}_i
- * (the first form; weight derivatives zero).  Costs one pass over the pairs
- * for E, U, W and the E^{Bgr} sums, without the Hessian contraction; the
- * same value as the grad output of vv10_hessian_terms.
+ *   E^A_gr = sum_{i in A} w_i rho_i E^{Agr}_i = -sum_{B != A} sum_{i in A} w_i rho_i E^{Bgr}_i,
+ *   E^x_w  = sum_i w^x_i rho_i (beta + E_i)   (only with w_x).
+ * Costs one pass over the pairs for E, U, W and the E^{Bgr} sums, without
+ * the Hessian contraction; the same value as the grad output of
+ * vv10_nuclear_terms.
  *  n_pert      must equal 3 n_atom.
  *  rho_x       [n_pert][N] DEVICE, FP64 (as for vv10_hessian_terms).
  *  grad_rho_x  [n_pert][N][3] DEVICE, FP64.
+ *  w_x         [n_pert][N] DEVICE, FP64, or NULL: weight derivatives as for
+ *              vv10_nuclear_terms (owner-atom entries not read).
  *  grad        [n_pert] DEVICE, FP64 output.
  * Errors: VV10_E_ARG, VV10_E_OOM, VV10_E_STATE, VV10_E_HIP.
  */
 vv10_status vv10_gradient(vv10_plan *plan, int32_t n_pert, const double *rho_x,
-                          const double *grad_rho_x, double *grad);
+                          const double *grad_rho_x, const double *w_x, double *grad);
 
 /* Largest n_t accepted by vv10_trial_response. */
 #define VV10_MAX_TRIAL 65536
@@ -219,7 +242,8 @@ typedef enum {
     VV10_STAGE_GRID = 4,      /* grid-position intermediates fused with the pair
                                  integrals E, U, W, A, B, C of vv10_hessian_terms */
     VV10_STAGE_ASSEMBLE = 5,  /* Hessian assembly (and gradient) */
-    VV10_NUM_STAGES = 6
+    VV10_STAGE_WEIGHTS = 6,   /* weight-derivative packing and contraction */
+    VV10_NUM_STAGES = 7
 } vv10_stage;
 
 /* Rebind the plan to another HIP stream: later calls enqueue on `stream`.

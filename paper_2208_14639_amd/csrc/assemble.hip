@@ -1,5 +1,4 @@
-// Hessian assembly (Section II.B, nine-term split with the weight terms
-// zero).  All FP64.
+// Hessian assembly (Section II.B, nine-term split).  All FP64.
 //
 // 1. k_resp, one wave per point i, lanes over the perturbations x:
 //      Y = sum of the contraction's j-split partials (split order, FP64)
@@ -18,11 +17,24 @@
 //    the other atoms' slots), and R = w (Yr + 2 Zr, Yg + 2 Zg), written over Y.
 //    Optional outputs: Yr, Yg (response rows) and Yr + Zr, Yg + Zg (the
 //    grid-level coefficients of the Fock nuclear derivative).
+//    With weight derivatives w^x (weights that move with the nuclei) the
+//    weight contraction's (Y_pv, Y_qv, Y_vv) and the grid channel
+//    Ze = E^{xgr} (own slot by invariance again) add
+//      Wr = Y_pv + rho omega_r Y_qv,  Wg = rho omega_g Y_qv
+//      R += (2 w Wr + 2 w^x f^rho, 2 w Wg + 2 w^x f^gamma),
+//      Rw = rho (Y_vv + 2 Ze)     (right factor of the w^x rows),
+//    and Wr, Wg to the Fock coefficients (F^A_w without its first line).
 // 2. k_gemm: per slice s of points, Hpart[s][l][m] = sum_i L_i^T R_i with
 //    L = (rho^x, gamma^x) on FP64 MFMA, so that sum_s Hpart[s] = E_GG + 2 E_{G,gr}
 //    (E_GG without the rho^{AB} term); row Pp of each slice holds the gradient
-//    part E_G = sum_i w_i (f^rho_i rho^x_i + f^gamma_i gamma^x_i).
-// 3. k_hsum: Hsum = sum_s Hpart[s] in a fixed order.
+//    part E_G = sum_i w_i (f^rho_i rho^x_i + f^gamma_i gamma^x_i).  With
+//    weight derivatives a second GEMM over the rows L = w^x, R = Rw adds
+//    E_ww + 2 E_{w,gr} (E_ww = sum_i w^A_i rho_i E^{Bw}_i, symmetric) and, in
+//    row Pp, E_w = sum_i w^x_i rho_i (beta + E_i); the R terms above add
+//    2 E_{G,w}.  Symmetrised, this is the nine-term split without the
+//    caller's rho^{AB} and w^{AB} sums.
+// 3. k_hsum: Hsum = sum_s Hpart[s] in a fixed order (the w^x slices after
+//    the others).
 // 4. k_dsum: E_{gr,gr} tile sums of a_i D^B_i reduced per atom pair.
 // 5. k_finish: H = sym(Hsum) + sym(E_{gr,gr}), sym(M) = (M + M^T)/2, with the
 //    diagonal blocks of E_{gr,gr} from translational invariance, and the
@@ -76,32 +88,45 @@ __device__ __forceinline__ void point_response(const PointFields &f, double rx, 
     Yg = f.r * f.omg * yq + loc_g;
 }
 
+// Inputs of the weight-derivative terms (all null without weight derivatives).
+template <typename T>
+struct WeightIn {
+    const T *Ypart;        // [S][npad][3][Pp] (Y_pv, Y_qv, Y_vv) partials
+    const double *Lw;      // [npad][Pp] w^x
+    const double *Ze;      // [npad][Pp] E^{xgr} (own slot not written)
+    double *Rw;            // [npad][Pp] output
+};
+
 // One wave per point; the partials are FP64 or FP32 ([S][npad][2][Pp]; for
 // FP64 with one split they alias Y, read before R is written in place).
-template <typename T>
+template <typename T, bool WT>
 __global__ __launch_bounds__(256) void k_resp(
     int64_t n, int64_t npad, int32_t P, int32_t Pp, int32_t S, const int32_t *__restrict__ atom_of,
     const double *__restrict__ F, const double *__restrict__ I, const double *__restrict__ L,
-    const T *Ypart, double *Y, const double *__restrict__ Z, double *__restrict__ resp_rho,
-    double *__restrict__ resp_gamma, double *__restrict__ fock_rho, double *__restrict__ fock_gamma) {
+    const T *Ypart, double *Y, const double *__restrict__ Z, WeightIn<T> wt,
+    double *__restrict__ resp_rho, double *__restrict__ resp_gamma, double *__restrict__ fock_rho,
+    double *__restrict__ fock_gamma) {
     const int lane = threadIdx.x & 63;
     const int64_t i = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (i >= n) return;
     const PointFields f = point_fields(F, I, npad, i);
     const int A = atom_of[i];
     const double *z0 = Z + (i * 2 + 0) * Pp, *z1 = Z + (i * 2 + 1) * Pp;
+    const double *ze = WT ? wt.Ze + i * Pp : nullptr;
 
     // own-atom slot: -sum over the other atoms' slots of the same direction
-    double own0[3] = {0.0, 0.0, 0.0}, own1[3] = {0.0, 0.0, 0.0};
+    double own0[3] = {0.0, 0.0, 0.0}, own1[3] = {0.0, 0.0, 0.0}, own2[3] = {0.0, 0.0, 0.0};
     for (int x0 = 0; x0 < P; x0 += 64) {
         const int x = x0 + lane;
         const bool use = x < P && x / 3 != A;
         const double v0 = use ? z0[x] : 0.0, v1 = use ? z1[x] : 0.0;
+        const double v2 = (WT && use) ? ze[x] : 0.0;
         const int a = x % 3;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             own0[d] -= wave_sum(a == d ? v0 : 0.0);
             own1[d] -= wave_sum(a == d ? v1 : 0.0);
+            if (WT) own2[d] -= wave_sum(a == d ? v2 : 0.0);
         }
     }
 
@@ -112,6 +137,7 @@ __global__ __launch_bounds__(256) void k_resp(
         if (x >= P) {
             *y0 = 0.0;
             *y1 = 0.0;
+            if (WT) wt.Rw[i * Pp + x] = 0.0;
             continue;
         }
         const int64_t o = (i * 2) * Pp + x;
@@ -129,12 +155,32 @@ __global__ __launch_bounds__(256) void k_resp(
         const double zp = self ? o0 : z0[x];
         const double zq = self ? o1 : z1[x];
         const double Zr = zp + f.r * f.omr * zq, Zg = f.r * f.omg * zq;
-        *y0 = f.w * (Yr + 2.0 * Zr);
-        *y1 = f.w * (Yg + 2.0 * Zg);
+        double Wr = 0.0, Wg = 0.0;
+        if (WT) {
+            const int64_t lw = npad * 3 * Pp, ow = (i * 3) * Pp + x;
+            double ypv = (double)wt.Ypart[ow], yqv = (double)wt.Ypart[ow + Pp];
+            double yvv = (double)wt.Ypart[ow + 2 * Pp];
+            for (int s = 1; s < S; ++s) {
+                ypv += (double)wt.Ypart[s * lw + ow];
+                yqv += (double)wt.Ypart[s * lw + ow + Pp];
+                yvv += (double)wt.Ypart[s * lw + ow + 2 * Pp];
+            }
+            const double o2 = a == 0 ? own2[0] : (a == 1 ? own2[1] : own2[2]);
+            const double zev = self ? o2 : ze[x];
+            const double wx = wt.Lw[i * Pp + x];
+            Wr = ypv + f.r * f.omr * yqv;
+            Wg = f.r * f.omg * yqv;
+            *y0 = f.w * (Yr + 2.0 * Zr + 2.0 * Wr) + 2.0 * wx * F[F_FR * npad + i];
+            *y1 = f.w * (Yg + 2.0 * Zg + 2.0 * Wg) + 2.0 * wx * F[F_FG * npad + i];
+            wt.Rw[i * Pp + x] = f.r * (yvv + 2.0 * zev);
+        } else {
+            *y0 = f.w * (Yr + 2.0 * Zr);
+            *y1 = f.w * (Yg + 2.0 * Zg);
+        }
         if (resp_rho) resp_rho[(int64_t)x * n + i] = Yr;
         if (resp_gamma) resp_gamma[(int64_t)x * n + i] = Yg;
-        if (fock_rho) fock_rho[(int64_t)x * n + i] = Yr + Zr;
-        if (fock_gamma) fock_gamma[(int64_t)x * n + i] = Yg + Zg;
+        if (fock_rho) fock_rho[(int64_t)x * n + i] = Yr + Zr + Wr;
+        if (fock_gamma) fock_gamma[(int64_t)x * n + i] = Yg + Zg + Wg;
     }
 }
 
@@ -181,12 +227,15 @@ __global__ __launch_bounds__(256) void k_trial_resp(
     }
 }
 
-// Hpart[s] (rows 0..Pp-1) = sum over the rows k = 2 i + c of slice s of
-// L[k][l] R[k][m]; row Pp = sum_k L[k][l] wf[k], wf[2i + c] = w_i (f^rho_i, f^gamma_i).
+// Hpart[s] (rows 0..Pp-1) = sum over the rows k of slice s of L[k][l] R[k][m];
+// row Pp = sum_k L[k][l] wf[k].  NCH = 2: rows k = 2 i + c of (rho^x, gamma^x)
+// with wf[2i + c] = w_i (f^rho_i, f^gamma_i); NCH = 1: rows k = i of w^x with
+// wf[i] = rho_i (beta + E_i).
 // Workgroup (tl, tm, s): output tile rows 64 tl.., columns 64 tm..; its four
 // waves take consecutive quarters of the slice, each on v_mfma_f64_16x16x4
 // with L and R read straight from memory (A = L^T, B = R, K over rows), and
 // are added in wave order through LDS.
+template <int NCH>
 __global__ __launch_bounds__(256, 2) void k_gemm(int64_t n, int64_t npad, int64_t slice,
                                                  int32_t Pp, const double *__restrict__ F,
                                                  const double *__restrict__ L,
@@ -198,8 +247,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm(int64_t n, int64_t npad, int64_
     const int l0 = blockIdx.x * 64, m0 = blockIdx.y * 64;
     const bool grad = blockIdx.y == 0;
     const int nlb = min(4, (Pp - l0) / 16), nmb = min(4, (Pp - m0) / 16);   // Pp % 16 == 0
-    const int64_t rows = 2 * n;
-    const int64_t sb = min(rows, (int64_t)blockIdx.z * slice * 2), se = min(rows, sb + slice * 2);
+    const int64_t rows = NCH * n;
+    const int64_t sb = min(rows, (int64_t)blockIdx.z * slice * NCH), se = min(rows, sb + slice * NCH);
     const int64_t q = (se - sb + 3) / 4;
     const int64_t rb = min(se, sb + wave * q), re = min(se, rb + q);
     v4d acc[4][4];
@@ -223,8 +272,13 @@ __global__ __launch_bounds__(256, 2) void k_gemm(int64_t n, int64_t npad, int64_
             for (int b = 0; b < 4; ++b)
                 acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
         if (grad) {
-            const int64_t pt = kr >> 1;
-            const double wf = ok ? F[F_W * npad + pt] * F[((kr & 1) ? F_FG : F_FR) * npad + pt] : 0.0;
+            double wf = 0.0;
+            if (NCH == 2) {
+                const int64_t pt = kr >> 1;
+                wf = ok ? F[F_W * npad + pt] * F[((kr & 1) ? F_FG : F_FR) * npad + pt] : 0.0;
+            } else {
+                wf = ok ? F[F_F0 * npad + kr] : 0.0;
+            }
 #pragma unroll
             for (int a = 0; a < 4; ++a) gacc[a] = __builtin_fma(av[a], wf, gacc[a]);
         }
@@ -265,19 +319,23 @@ __global__ __launch_bounds__(256, 2) void k_gemm(int64_t n, int64_t npad, int64_
     if (grad && tid < 64 && l0 + tid < Pp) H[(int64_t)Pp * Pp + l0 + tid] = sT[64 * 64 + tid];
 }
 
-// Hsum[e] = sum_s Hpart[s][e], e < (Pp + 1) Pp: 64 entries per workgroup,
-// the four waves sum consecutive quarters of the slices, added in wave order.
+// Hsum[e] = sum_s Hpart[s][e], e < (Pp + 1) Pp, over the S slices of Hpart
+// and then the S2 slices of H2: 64 entries per workgroup, the four waves sum
+// consecutive quarters of the slices, added in wave order.
 __global__ __launch_bounds__(256) void k_hsum(int64_t len, int S, const double *__restrict__ Hpart,
+                                              int S2, const double *__restrict__ H2,
                                               double *__restrict__ Hsum) {
     __shared__ double part[4][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t e = (int64_t)blockIdx.x * 64 + lane;
-    const int q = (S + 3) / 4;
-    const int sb = min(S, wave * q), se = min(S, sb + q);
+    const int St = S + S2;
+    const int q = (St + 3) / 4;
+    const int sb = min(St, wave * q), se = min(St, sb + q);
     double a = 0.0;
     if (e < len)
 #pragma unroll 16
-        for (int s = sb; s < se; ++s) a += Hpart[(int64_t)s * len + e];
+        for (int s = sb; s < se; ++s)
+            a += s < S ? Hpart[(int64_t)s * len + e] : H2[(int64_t)(s - S) * len + e];
     part[wave][lane] = a;
     __syncthreads();
     if (wave == 0 && e < len) Hsum[e] = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
@@ -349,14 +407,19 @@ __global__ __launch_bounds__(256) void k_finish(int32_t n_atom, int32_t P, int32
 
 // Gradient (Section II.A, first form of the grid part): for x = 3 A + a,
 //   grad[x] = sum_i w_i (f^rho_i rho^x_i + f^gamma_i gamma^x_i)
+//           [+ sum_i w^x_i rho_i (beta + E_i)]
 //           - sum_{B != A} sum_{tiles t of A} Gpart[t][B][a],
-// gamma^x = 2 grad rho . grad rho^x.  One workgroup per x; both sums are
-// fixed-order tree reductions, added at the end.
+// gamma^x = 2 grad rho . grad rho^x; w^x (optional) with the owner slot from
+// Wown.  One workgroup per x; both sums are fixed-order tree reductions,
+// added at the end.
 __global__ __launch_bounds__(256) void k_gradient(int64_t n, int64_t npad, int32_t n_atom,
                                                   const int32_t *__restrict__ tile_first,
+                                                  const int32_t *__restrict__ atom_of,
                                                   const double *__restrict__ F,
                                                   const double *__restrict__ rho_x,
                                                   const double *__restrict__ grad_rho_x,
+                                                  const double *__restrict__ w_x,
+                                                  const double *__restrict__ Wown,
                                                   const double *__restrict__ Gpart,
                                                   double *__restrict__ grad) {
     __shared__ double sg[256], sr[256];
@@ -368,6 +431,10 @@ __global__ __launch_bounds__(256) void k_gradient(int64_t n, int64_t npad, int32
         const double gam = 2.0 * (F[F_GX * npad + i] * gx[3 * i] + F[F_GY * npad + i] * gx[3 * i + 1] +
                                   F[F_GZ * npad + i] * gx[3 * i + 2]);
         eg += F[F_W * npad + i] * (F[F_FR * npad + i] * rx[i] + F[F_FG * npad + i] * gam);
+        if (w_x) {
+            const double wx = atom_of[i] == A ? Wown[i * 3 + a] : w_x[(int64_t)x * n + i];
+            eg += wx * F[F_F0 * npad + i];
+        }
     }
     const int t0 = tile_first[A], nt = tile_first[A + 1] - t0;
     double gr = 0.0;
@@ -388,10 +455,15 @@ __global__ __launch_bounds__(256) void k_gradient(int64_t n, int64_t npad, int32
     if (tid == 0) grad[x] = sg[0] + sr[0];
 }
 
-hipError_t launch_gradient(vv10_plan *p, const double *rho_x, const double *grad_rho_x, double *grad) {
-    k_gradient<<<(unsigned)(3 * p->n_atom), 256, 0, p->stream>>>(p->n, p->npad, p->n_atom,
-                                                                 p->d_tile_first, p->F, rho_x,
-                                                                 grad_rho_x, p->gw.Gpart, grad);
+hipError_t launch_gradient(vv10_plan *p, const double *rho_x, const double *grad_rho_x,
+                           const double *w_x, double *grad) {
+    if (w_x) {
+        const hipError_t e = launch_weight_own(p, w_x, p->wown);
+        if (e != hipSuccess) return e;
+    }
+    k_gradient<<<(unsigned)(3 * p->n_atom), 256, 0, p->stream>>>(
+        p->n, p->npad, p->n_atom, p->d_tile_first, p->atom_of, p->F, rho_x, grad_rho_x, w_x,
+        p->wown, p->gw.Gpart, grad);
     return hipGetLastError();
 }
 
@@ -409,33 +481,53 @@ hipError_t launch_trial_response(vv10_plan *p, double *f_rho_t, double *f_gamma_
     return hipGetLastError();
 }
 
-hipError_t launch_assemble(vv10_plan *p, const vv10_nuclear_outputs &out) {
+hipError_t launch_assemble(vv10_plan *p, const vv10_nuclear_outputs &out, bool weighted) {
     const Workspace &ws = p->ws;
+    const WeightWork &ww = p->ww;
     const int64_t n = p->n;
     double *hess = out.hess, *grad = out.grad;
     {
         const unsigned nb = (unsigned)((n + 3) / 4);
-        if (p->prec == VV10_FP64)
-            k_resp<double><<<nb, 256, 0, p->stream>>>(
-                n, p->npad, ws.P, ws.Pp, ws.jsplit, p->atom_of, p->F, p->I, ws.L,
-                static_cast<const double *>(ws.Ypart), ws.Y, ws.Z, out.resp_rho, out.resp_gamma,
-                out.fock_rho, out.fock_gamma);
-        else
-            k_resp<float><<<nb, 256, 0, p->stream>>>(
-                n, p->npad, ws.P, ws.Pp, ws.jsplit, p->atom_of, p->F, p->I, ws.L,
-                static_cast<const float *>(ws.Ypart), ws.Y, ws.Z, out.resp_rho, out.resp_gamma,
-                out.fock_rho, out.fock_gamma);
+        if (p->prec == VV10_FP64) {
+            const WeightIn<double> wt = {static_cast<const double *>(ww.Ypart), ww.Lw, ww.Ze, ww.Rw};
+            if (weighted)
+                k_resp<double, true><<<nb, 256, 0, p->stream>>>(
+                    n, p->npad, ws.P, ws.Pp, ws.jsplit, p->atom_of, p->F, p->I, ws.L,
+                    static_cast<const double *>(ws.Ypart), ws.Y, ws.Z, wt, out.resp_rho,
+                    out.resp_gamma, out.fock_rho, out.fock_gamma);
+            else
+                k_resp<double, false><<<nb, 256, 0, p->stream>>>(
+                    n, p->npad, ws.P, ws.Pp, ws.jsplit, p->atom_of, p->F, p->I, ws.L,
+                    static_cast<const double *>(ws.Ypart), ws.Y, ws.Z, wt, out.resp_rho,
+                    out.resp_gamma, out.fock_rho, out.fock_gamma);
+        } else {
+            const WeightIn<float> wt = {static_cast<const float *>(ww.Ypart), ww.Lw, ww.Ze, ww.Rw};
+            if (weighted)
+                k_resp<float, true><<<nb, 256, 0, p->stream>>>(
+                    n, p->npad, ws.P, ws.Pp, ws.jsplit, p->atom_of, p->F, p->I, ws.L,
+                    static_cast<const float *>(ws.Ypart), ws.Y, ws.Z, wt, out.resp_rho,
+                    out.resp_gamma, out.fock_rho, out.fock_gamma);
+            else
+                k_resp<float, false><<<nb, 256, 0, p->stream>>>(
+                    n, p->npad, ws.P, ws.Pp, ws.jsplit, p->atom_of, p->F, p->I, ws.L,
+                    static_cast<const float *>(ws.Ypart), ws.Y, ws.Z, wt, out.resp_rho,
+                    out.resp_gamma, out.fock_rho, out.fock_gamma);
+        }
     }
     if (!hess && !grad) return hipGetLastError();
+    const int64_t slice = (n + ws.gsplit - 1) / ws.gsplit;
+    const unsigned tiles = (unsigned)((ws.Pp + 63) / 64);
     {
-        const int64_t slice = (n + ws.gsplit - 1) / ws.gsplit;
-        const unsigned tiles = (unsigned)((ws.Pp + 63) / 64);
         dim3 grid(tiles, tiles, (unsigned)ws.gsplit);
-        k_gemm<<<grid, 256, 0, p->stream>>>(n, p->npad, slice, ws.Pp, p->F, ws.L, ws.Y, ws.Hpart);
+        k_gemm<2><<<grid, 256, 0, p->stream>>>(n, p->npad, slice, ws.Pp, p->F, ws.L, ws.Y, ws.Hpart);
+        if (weighted)
+            k_gemm<1><<<grid, 256, 0, p->stream>>>(n, p->npad, slice, ws.Pp, p->F, ww.Lw, ww.Rw,
+                                                   ww.Hpart);
     }
     {
         const int64_t len = (int64_t)(ws.Pp + 1) * ws.Pp;
-        k_hsum<<<(unsigned)((len + 63) / 64), 256, 0, p->stream>>>(len, ws.gsplit, ws.Hpart, ws.Hsum);
+        k_hsum<<<(unsigned)((len + 63) / 64), 256, 0, p->stream>>>(
+            len, ws.gsplit, ws.Hpart, weighted ? ws.gsplit : 0, ww.Hpart, ws.Hsum);
     }
     const int64_t nds = (int64_t)p->n_atom * p->n_atom * 9;
     k_dsum<<<(unsigned)((nds + 255) / 256), 256, 0, p->stream>>>(p->n_atom, p->d_tile_first,

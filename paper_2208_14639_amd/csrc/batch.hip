@@ -68,7 +68,7 @@ hipError_t enqueue_batch(vv10_batch *b, const double *rho_x, const double *grad_
     for (size_t m = 0; m < nm && e == hipSuccess; ++m) {
         vv10_plan *p = b->plans[m];
         p->stream = b->side[m % K];
-        e = vv10::launch_grid_terms(p);
+        e = vv10::launch_grid_terms(p, nullptr);
         if (e == hipSuccess) e = vv10::launch_potential(p, energy + m, nullptr, nullptr);
         if (e == hipSuccess) e = vv10::launch_pert_prep(p, p->ws, rho_x + b->rx_off[m], grad_rho_x + b->gx_off[m]);
     }
@@ -84,8 +84,8 @@ hipError_t enqueue_batch(vv10_batch *b, const double *rho_x, const double *grad_
     for (size_t m = 0; m < nm && e == hipSuccess; ++m) {
         vv10_plan *p = b->plans[m];
         p->stream = b->side[m % K];
-        const vv10_nuclear_outputs out = {hess + b->h_off[m], nullptr, nullptr, nullptr, nullptr, nullptr};
-        e = vv10::launch_assemble(p, out);
+        const vv10_nuclear_outputs out = {hess + b->h_off[m], nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+        e = vv10::launch_assemble(p, out, false);
     }
     for (int k = 0; k < K && e == hipSuccess; ++k) {
         e = hipEventRecord(b->ev[2 + K + k], b->side[k]);

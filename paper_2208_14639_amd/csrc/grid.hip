@@ -10,7 +10,8 @@
 //
 // Outputs, per outer point i and atom B != O(i):
 //   Z[i][0][3B+a] = E^{Bgr}_{i,a} + c_i U^{Bgr}_{i,a},  Z[i][1][3B+a] = W^{Bgr}_{i,a}
-// (the two channels that multiply p and q in E_{G,gr}), and per tile t of
+// (the two channels that multiply p and q in E_{G,gr}), optionally
+//   Ze[i][3B+a] = E^{Bgr}_{i,a}   (the channel of E_{w,gr}), and per tile t of
 // outer points (all in one atom A) the sums
 //   Dpart[t][B][0..5] = sum_{i in t} a_i D^B_i   (xx, yy, zz, xy, xz, yz; B > A only,
 //                                                  zero for B < A)
@@ -134,8 +135,8 @@ __global__ __launch_bounds__(64) void k_grid(
     int32_t n_atom, int32_t Pp, int32_t bgroups, int64_t npad, const int64_t *__restrict__ seg,
     const int32_t *__restrict__ tile_i0, const int32_t *__restrict__ tile_n,
     const int32_t *__restrict__ tile_atom, const T4 *__restrict__ P0,
-    const T4 *__restrict__ P1, double *__restrict__ Z, double *__restrict__ Dpart,
-    double *__restrict__ Ipart) {
+    const T4 *__restrict__ P1, double *__restrict__ Z, double *__restrict__ Ze,
+    double *__restrict__ Dpart, double *__restrict__ Ipart) {
     __shared__ T4 sA[TG], sB[TG];
     const int t = blockIdx.x, grp = blockIdx.y, lane = threadIdx.x;
     const int A = tile_atom[t];
@@ -185,6 +186,12 @@ __global__ __launch_bounds__(64) void k_grid(
             z1[0] = -3.0 * acc[6];
             z1[1] = -3.0 * acc[7];
             z1[2] = -3.0 * acc[8];
+            if (Ze) {
+                double *ze = Ze + i * Pp + 3 * B;
+                ze[0] = 3.0 * acc[0];
+                ze[1] = 3.0 * acc[1];
+                ze[2] = 3.0 * acc[2];
+            }
         }
         const double di = -3.0 * acc[15];
         const double red[9] = {ai * (6.0 * acc[9] + di), ai * (6.0 * acc[10] + di),
@@ -300,17 +307,17 @@ __global__ __launch_bounds__(64) void k_grid_grad(
 
 }  // namespace
 
-hipError_t launch_grid_terms(vv10_plan *p) {
+hipError_t launch_grid_terms(vv10_plan *p, double *Ze) {
     const Workspace &ws = p->ws;
     dim3 grid((unsigned)p->ntiles, (unsigned)ws.bgroups);
     if (p->prec == VV10_FP64)
         k_grid<double, double4><<<grid, TG, 0, p->stream>>>(
             p->n_atom, ws.Pp, ws.bgroups, p->npad, p->d_seg, p->d_tile_i0, p->d_tile_n,
-            p->d_tile_atom, p->P0, p->P1, ws.Z, ws.Dpart, ws.Igrp);
+            p->d_tile_atom, p->P0, p->P1, ws.Z, Ze, ws.Dpart, ws.Igrp);
     else
         k_grid<float, float4><<<grid, TG, 0, p->stream>>>(
             p->n_atom, ws.Pp, ws.bgroups, p->npad, p->d_seg, p->d_tile_i0, p->d_tile_n,
-            p->d_tile_atom, p->P0f, p->P1f, ws.Z, ws.Dpart, ws.Igrp);
+            p->d_tile_atom, p->P0f, p->P1f, ws.Z, Ze, ws.Dpart, ws.Igrp);
     const int64_t tot = (int64_t)NI * p->n;
     k_sum_groups<<<(unsigned)((tot + 255) / 256), 256, 0, p->stream>>>(p->n, p->npad, ws.bgroups, NI,
                                                                        ws.Igrp, p->I);

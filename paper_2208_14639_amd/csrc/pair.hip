@@ -130,6 +130,7 @@ __global__ __launch_bounds__(256) void k_potential(int64_t n, int64_t npad, doub
         const double fg = r * F[F_OMG * npad + i] * Wi;
         F[F_FR * npad + i] = fr;
         F[F_FG * npad + i] = fg;
+        F[F_F0 * npad + i] = r * (beta + Ei);
         if (f_rho) f_rho[i] = fr;
         if (f_gamma) f_gamma[i] = fg;
         e = P1[i].y * (beta + 0.5 * Ei);

@@ -125,6 +125,7 @@ __global__ __launch_bounds__(256) void k_prep(
     F[F_KARR * npad + i] = karr;
     F[F_FR * npad + i] = 0.0;
     F[F_FG * npad + i] = 0.0;
+    F[F_F0 * npad + i] = 0.0;
     ao_out[i] = A;
 }
 

@@ -150,8 +150,21 @@ void free_workspace(Workspace &ws) {
     ws = Workspace{};
 }
 
+void free_weight_work(vv10::WeightWork &ww) {
+    dfree(ww.Wown);
+    dfree(ww.Xv);
+    dfree(ww.Lw);
+    dfree(ww.Ypart);
+    dfree(ww.Ze);
+    dfree(ww.Rw);
+    dfree(ww.Hpart);
+    ww = vv10::WeightWork{};
+}
+
 void free_plan(vv10_plan *p) {
     if (!p) return;
+    free_weight_work(p->ww);
+    dfree(p->wown);
     for (auto &ev : p->ev)
         if (ev) give_event(p->device, ev);
     free_workspace(p->ws);
@@ -279,6 +292,39 @@ static vv10_status ensure_gradient_work(vv10_plan *p) {
         return hip_status(e);
     }
     p->gw = gw;
+    return VV10_OK;
+}
+
+// Allocate the weight-derivative buffers (once per plan, after the Hessian
+// workspace whose shape they follow).
+static vv10_status ensure_weight_work(vv10_plan *p) {
+    if (p->ww.Xv) return VV10_OK;
+    const Workspace &ws = p->ws;
+    vv10::WeightWork ww;
+    vv10::weight_shape(ws.Pp, p->prec, ww);
+    if (injected_alloc_failure()) return VV10_E_OOM;
+    const size_t ch = (size_t)p->npad * ws.Pp;
+    char *xv = nullptr, *yp = nullptr;
+    hipError_t e = dalloc(&ww.Wown, (size_t)p->npad * 3);
+    if (e == hipSuccess) e = dalloc(&xv, ch * (p->prec == VV10_FP64 ? 8 : 4));
+    ww.Xv = xv;
+    if (e == hipSuccess) e = dalloc(&ww.Lw, ch);
+    if (e == hipSuccess) e = dalloc(&yp, ch * 3 * ws.jsplit * vv10::partial_elem(p->prec));
+    ww.Ypart = yp;
+    if (e == hipSuccess) e = dalloc(&ww.Ze, ch);
+    if (e == hipSuccess) e = dalloc(&ww.Rw, ch);
+    if (e == hipSuccess) e = dalloc(&ww.Hpart, (size_t)ws.gsplit * (ws.Pp + 1) * ws.Pp);
+    if (e != hipSuccess) {
+        free_weight_work(ww);
+        (void)hipGetLastError();
+        return hip_status(e);
+    }
+    ww.bytes = (size_t)p->npad * 3 * sizeof(double)                    // Wown
+             + ch * (p->prec == VV10_FP64 ? 8 : 4)                      // Xv
+             + 3 * ch * sizeof(double)                                  // Lw, Ze, Rw
+             + ch * 3 * ws.jsplit * vv10::partial_elem(p->prec)         // partials
+             + (size_t)ws.gsplit * (ws.Pp + 1) * ws.Pp * sizeof(double); // GEMM slices
+    p->ww = ww;
     return VV10_OK;
 }
 
@@ -455,23 +501,42 @@ vv10_status vv10_energy_potential(vv10_plan *p, double *energy, double *f_rho, d
 }
 
 vv10_status vv10_nuclear_terms(vv10_plan *p, int32_t n_pert, const double *rho_x,
-                               const double *grad_rho_x, const vv10_nuclear_outputs *out) {
+                               const double *grad_rho_x, const double *w_x,
+                               const vv10_nuclear_outputs *out) {
     if (!p) return VV10_E_STATE;
     if (p->failed) return VV10_E_STATE;
     if (n_pert != 3 * p->n_atom || !rho_x || !grad_rho_x || !out) return VV10_E_ARG;
     if (!out->hess && !out->grad && !out->resp_rho && !out->resp_gamma && !out->fock_rho &&
-        !out->fock_gamma)
+        !out->fock_gamma && !out->w_coef)
         return VV10_OK;
     vv10_status st = vv10::ensure_workspace(p);
     if (st != VV10_OK) return st;
+    // weight terms only where an output needs them
+    const bool weighted = w_x && (out->hess || out->grad || out->fock_rho || out->fock_gamma);
+    if (weighted) {
+        st = ensure_weight_work(p);
+        if (st != VV10_OK) return st;
+    }
     // the grid-term pass also produces the pair integrals E, U, W, A, B, C
-    hipError_t e = stage(p, VV10_STAGE_GRID, [&] { return vv10::launch_grid_terms(p); });
+    hipError_t e = stage(p, VV10_STAGE_GRID, [&] {
+        return vv10::launch_grid_terms(p, weighted ? p->ww.Ze : nullptr);
+    });
     if (e == hipSuccess)
         e = stage(p, VV10_STAGE_POTENTIAL, [&] { return vv10::launch_potential(p, nullptr, nullptr, nullptr); });
+    if (e == hipSuccess && out->w_coef)
+        e = hipMemcpyAsync(out->w_coef, p->F + (size_t)vv10::F_F0 * p->npad,
+                           (size_t)p->n * sizeof(double), hipMemcpyDeviceToDevice, p->stream);
     if (e == hipSuccess)
         e = stage(p, VV10_STAGE_PERT_PREP, [&] { return vv10::launch_pert_prep(p, p->ws, rho_x, grad_rho_x); });
     if (e == hipSuccess) e = stage(p, VV10_STAGE_CONTRACT, [&] { return vv10::launch_contract(p, p->ws); });
-    if (e == hipSuccess) e = stage(p, VV10_STAGE_ASSEMBLE, [&] { return vv10::launch_assemble(p, *out); });
+    if (e == hipSuccess && weighted)
+        e = stage(p, VV10_STAGE_WEIGHTS, [&] {
+            hipError_t r = vv10::launch_weight_prep(p, w_x);
+            if (r == hipSuccess) r = vv10::launch_weight_contract(p);
+            return r;
+        });
+    if (e == hipSuccess)
+        e = stage(p, VV10_STAGE_ASSEMBLE, [&] { return vv10::launch_assemble(p, *out, weighted); });
     if (e != hipSuccess) {
         p->failed = true;
         (void)hipGetLastError();
@@ -485,22 +550,28 @@ vv10_status vv10_hessian_terms(vv10_plan *p, int32_t n_pert, const double *rho_x
                                double *resp_rho, double *resp_gamma) {
     if (!p) return VV10_E_STATE;
     if (!hess) return VV10_E_ARG;
-    const vv10_nuclear_outputs out = {hess, grad, resp_rho, resp_gamma, nullptr, nullptr};
-    return vv10_nuclear_terms(p, n_pert, rho_x, grad_rho_x, &out);
+    const vv10_nuclear_outputs out = {hess, grad, resp_rho, resp_gamma, nullptr, nullptr, nullptr};
+    return vv10_nuclear_terms(p, n_pert, rho_x, grad_rho_x, nullptr, &out);
 }
 
 vv10_status vv10_gradient(vv10_plan *p, int32_t n_pert, const double *rho_x,
-                          const double *grad_rho_x, double *grad) {
+                          const double *grad_rho_x, const double *w_x, double *grad) {
     if (!p) return VV10_E_STATE;
     if (p->failed) return VV10_E_STATE;
     if (n_pert != 3 * p->n_atom || !rho_x || !grad_rho_x || !grad) return VV10_E_ARG;
-    const vv10_status st = ensure_gradient_work(p);
+    vv10_status st = ensure_gradient_work(p);
     if (st != VV10_OK) return st;
+    if (w_x && !p->wown) {
+        if (dalloc(&p->wown, (size_t)p->npad * 3) != hipSuccess) {
+            (void)hipGetLastError();
+            return VV10_E_OOM;
+        }
+    }
     hipError_t e = stage(p, VV10_STAGE_GRID, [&] { return vv10::launch_grid_grad(p); });
     if (e == hipSuccess)
         e = stage(p, VV10_STAGE_POTENTIAL, [&] { return vv10::launch_potential(p, nullptr, nullptr, nullptr); });
     if (e == hipSuccess)
-        e = stage(p, VV10_STAGE_ASSEMBLE, [&] { return vv10::launch_gradient(p, rho_x, grad_rho_x, grad); });
+        e = stage(p, VV10_STAGE_ASSEMBLE, [&] { return vv10::launch_gradient(p, rho_x, grad_rho_x, w_x, grad); });
     if (e != hipSuccess) {
         p->failed = true;
         (void)hipGetLastError();

@@ -25,6 +25,7 @@ enum Field {
     F_KARR,      // d2 kappa / d rho2
     F_FR,        // potential f^rho (filled by the pair-integral finalisation)
     F_FG,        // potential f^gamma
+    F_F0,        // rho (beta + E): coefficient of the weight derivatives
     NF
 };
 
@@ -60,6 +61,20 @@ struct GradWork {
     int32_t bgroups = 0;
     double *Gpart = nullptr;     // [ntiles][n_atom][3] tile sums of a_i E^{Bgr}_i
     double *Igrp = nullptr;      // [bgroups][3][npad] E, U, W per atom group
+};
+
+// Buffers of the weight-derivative terms (allocated by the first call with
+// weight derivatives).
+struct WeightWork {
+    int32_t ncb = 0, groups = 0; // 16-column blocks per weight-contraction group, groups
+    double *Wown = nullptr;      // [npad][3] owner-atom slot of w^x
+    void *Xv = nullptr;          // v = w^x rho: FP64/FP32 [npad][Pp]; BF16X3 hi, lo [npad/32][Pp][32]
+    double *Lw = nullptr;        // [npad][Pp] w^x with the owner slot filled
+    void *Ypart = nullptr;       // [jsplit][npad][3][Pp] (Y_pv, Y_qv, Y_vv) partials
+    double *Ze = nullptr;        // [npad][Pp] E^{Bgr}_i (grid pass)
+    double *Rw = nullptr;        // [npad][Pp] right factor of the w^x rows of the GEMM
+    double *Hpart = nullptr;     // [gsplit][Pp + 1][Pp] GEMM slices of the w^x rows
+    size_t bytes = 0;
 };
 
 }  // namespace vv10
@@ -116,6 +131,10 @@ struct vv10_plan {
 
     // gradient-only pass (vv10_gradient)
     vv10::GradWork gw;
+
+    // weight-derivative terms (vv10_nuclear_terms / vv10_gradient with w_x)
+    vv10::WeightWork ww;
+    double *wown = nullptr;  // [npad][3] owner slot of w^x for the gradient-only pass
 };
 
 namespace vv10 {
@@ -155,11 +174,18 @@ hipError_t launch_potential(vv10_plan *p, double *energy, double *f_rho, double 
 hipError_t launch_pert_prep(vv10_plan *p, const Workspace &ws, const double *rho_x,
                             const double *grad_rho_x);
 hipError_t launch_contract(vv10_plan *p, const Workspace &ws);
-hipError_t launch_grid_terms(vv10_plan *p);
+hipError_t launch_grid_terms(vv10_plan *p, double *Ze);
 hipError_t launch_grid_grad(vv10_plan *p);
-hipError_t launch_gradient(vv10_plan *p, const double *rho_x, const double *grad_rho_x, double *grad);
+hipError_t launch_gradient(vv10_plan *p, const double *rho_x, const double *grad_rho_x,
+                           const double *w_x, double *grad);
+// Weight-derivative terms: owner slots, packing, contraction.
+void weight_shape(int32_t Pp, vv10_precision prec, WeightWork &ww);
+hipError_t launch_weight_own(vv10_plan *p, const double *w_x, double *Wown);
+hipError_t launch_weight_prep(vv10_plan *p, const double *w_x);
+hipError_t launch_weight_contract(vv10_plan *p);
 hipError_t launch_trial_response(vv10_plan *p, double *f_rho_t, double *f_gamma_t);
-hipError_t launch_assemble(vv10_plan *p, const vv10_nuclear_outputs &out);
+// weighted: also the weight-derivative terms (p->ww filled by the weight stages)
+hipError_t launch_assemble(vv10_plan *p, const vv10_nuclear_outputs &out, bool weighted);
 
 // Layout decisions shared by the host code.
 // n_cols: contraction columns (0 = the 3 n_atom nuclear perturbations).
@@ -177,6 +203,8 @@ size_t workspace_bytes(int64_t npad, int32_t n_atom, int32_t ntiles, vv10_precis
 int contract_blocks_per_cu(vv10_precision prec, int ncb);
 // Max 16-column blocks per contraction workgroup.
 inline int max_ncb(vv10_precision prec) { return prec == VV10_FP64 ? 8 : 12; }
+// Max 16-column blocks per weight-contraction workgroup (three outputs).
+inline int max_wncb(vv10_precision prec) { return prec == VV10_FP64 ? 4 : 8; }
 // Bytes of one element of the contraction partials / operand.
 inline size_t partial_elem(vv10_precision prec) { return prec == VV10_FP64 ? 8 : 4; }
 

@@ -29,7 +29,7 @@ VV10_MIXED_FP32 = 1
 VV10_MIXED_BF16X3 = 2
 PRECISIONS = {"fp64": VV10_FP64, "fp32": VV10_MIXED_FP32, "bf16x3": VV10_MIXED_BF16X3}
 
-STAGES = ("pair", "potential", "pert_prep", "contract", "grid", "assemble")
+STAGES = ("pair", "potential", "pert_prep", "contract", "grid", "assemble", "weights")
 
 
 class vv10_params(ctypes.Structure):
@@ -42,7 +42,7 @@ class vv10_tiles(ctypes.Structure):
 
 class vv10_nuclear_outputs(ctypes.Structure):
     _fields_ = [(k, ctypes.c_void_p) for k in
-                ("hess", "grad", "resp_rho", "resp_gamma", "fock_rho", "fock_gamma")]
+                ("hess", "grad", "resp_rho", "resp_gamma", "fock_rho", "fock_gamma", "w_coef")]
 
 
 class VV10Error(RuntimeError):
@@ -73,9 +73,9 @@ def load() -> ctypes.CDLL:
     lib.vv10_footprint_bytes.restype = ctypes.c_size_t
     lib.vv10_footprint_bytes.argtypes = [i64, i32, st]
     lib.vv10_nuclear_terms.restype = st
-    lib.vv10_nuclear_terms.argtypes = [P, i32, P, P, ctypes.POINTER(vv10_nuclear_outputs)]
+    lib.vv10_nuclear_terms.argtypes = [P, i32, P, P, P, ctypes.POINTER(vv10_nuclear_outputs)]
     lib.vv10_gradient.restype = st
-    lib.vv10_gradient.argtypes = [P, i32, P, P, P]
+    lib.vv10_gradient.argtypes = [P, i32, P, P, P, P]
     lib.vv10_trial_response.restype = st
     lib.vv10_trial_response.argtypes = [P, i32, P, P, P, P]
     lib.vv10_response_footprint_bytes.restype = ctypes.c_size_t
@@ -179,16 +179,18 @@ def vv10_hessian_terms(plan: int, n_pert: int, rho_x, grad_rho_x, hess, grad=Non
 
 
 def vv10_nuclear_terms(plan: int, n_pert: int, rho_x, grad_rho_x, hess=None, grad=None,
-                       resp_rho=None, resp_gamma=None, fock_rho=None, fock_gamma=None) -> None:
+                       resp_rho=None, resp_gamma=None, fock_rho=None, fock_gamma=None,
+                       w_x=None, w_coef=None) -> None:
     out = vv10_nuclear_outputs(*(_ptr(t) for t in (hess, grad, resp_rho, resp_gamma, fock_rho,
-                                                    fock_gamma)))
-    st = load().vv10_nuclear_terms(plan, n_pert, _ptr(rho_x), _ptr(grad_rho_x), ctypes.byref(out))
+                                                    fock_gamma, w_coef)))
+    st = load().vv10_nuclear_terms(plan, n_pert, _ptr(rho_x), _ptr(grad_rho_x), _ptr(w_x),
+                                   ctypes.byref(out))
     if st != VV10_OK:
         raise VV10Error(st, "vv10_nuclear_terms")
 
 
-def vv10_gradient(plan: int, n_pert: int, rho_x, grad_rho_x, grad) -> None:
-    st = load().vv10_gradient(plan, n_pert, _ptr(rho_x), _ptr(grad_rho_x), _ptr(grad))
+def vv10_gradient(plan: int, n_pert: int, rho_x, grad_rho_x, grad, w_x=None) -> None:
+    st = load().vv10_gradient(plan, n_pert, _ptr(rho_x), _ptr(grad_rho_x), _ptr(w_x), _ptr(grad))
     if st != VV10_OK:
         raise VV10Error(st, "vv10_gradient")
 
@@ -355,27 +357,34 @@ class Plan:
             out["resp_rho"], out["resp_gamma"] = rr, rg
         return out
 
-    def nuclear_terms(self, rho_x, grad_rho_x, hess=True, grad=False, resp=False, fock=False):
-        """Any subset of the nuclear-perturbation outputs of one pass."""
+    def _in(self, a):
+        t = self.torch
+        if a is None:
+            return None
+        return a if isinstance(a, t.Tensor) and a.is_cuda else self._dev(a)
+
+    def nuclear_terms(self, rho_x, grad_rho_x, hess=True, grad=False, resp=False, fock=False,
+                      w_x=None, w_coef=False):
+        """Any subset of the nuclear-perturbation outputs of one pass; w_x
+        ([3 n_atom, N], or None) are the weights' nuclear derivatives."""
         t = self.torch
         P = 3 * self.n_atom
-        rx = rho_x if isinstance(rho_x, t.Tensor) and rho_x.is_cuda else self._dev(rho_x)
-        gx = grad_rho_x if isinstance(grad_rho_x, t.Tensor) and grad_rho_x.is_cuda else self._dev(grad_rho_x)
+        rx, gx, wx = self._in(rho_x), self._in(grad_rho_x), self._in(w_x)
         mk = lambda on, shape: t.empty(shape, dtype=t.float64, device=self.device) if on else None
         out = {"hess": mk(hess, (P, P)), "grad": mk(grad, P),
                "resp_rho": mk(resp, (P, self.n)), "resp_gamma": mk(resp, (P, self.n)),
-               "fock_rho": mk(fock, (P, self.n)), "fock_gamma": mk(fock, (P, self.n))}
-        vv10_nuclear_terms(self.handle, P, rx, gx, **out)
+               "fock_rho": mk(fock, (P, self.n)), "fock_gamma": mk(fock, (P, self.n)),
+               "w_coef": mk(w_coef, self.n)}
+        vv10_nuclear_terms(self.handle, P, rx, gx, w_x=wx, **out)
         return {k: v for k, v in out.items() if v is not None}
 
-    def gradient(self, rho_x, grad_rho_x):
-        """Nuclear gradient [3 n_atom] alone."""
+    def gradient(self, rho_x, grad_rho_x, w_x=None):
+        """Nuclear gradient [3 n_atom] alone (with E_w when w_x is given)."""
         t = self.torch
         P = 3 * self.n_atom
-        rx = rho_x if isinstance(rho_x, t.Tensor) and rho_x.is_cuda else self._dev(rho_x)
-        gx = grad_rho_x if isinstance(grad_rho_x, t.Tensor) and grad_rho_x.is_cuda else self._dev(grad_rho_x)
+        rx, gx, wx = self._in(rho_x), self._in(grad_rho_x), self._in(w_x)
         g = t.empty(P, dtype=t.float64, device=self.device)
-        vv10_gradient(self.handle, P, rx, gx, g)
+        vv10_gradient(self.handle, P, rx, gx, g, w_x=wx)
         return g
 
     def trial_response(self, rho_t, grad_rho_t):

@@ -1,0 +1,191 @@
+"""Weight-derivative terms (Section II.A E^A_w; Section II.B E_{w,w}, E_{G,w},
+E_{w,gr}, F^A_w) through the C ABI, for Becke-partitioned weights that move
+with the nuclei, against the FP64 oracle."""
+import functools
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import normwise, relerr
+from paper_2208_14639_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+# mixed modes: Hessian elements <= 1e-5 au absolute, gradient <= 1e-5
+# normwise, the weight coefficient rho (beta + E) <= 1e-6 relative (it carries
+# the energy-like sum E_i), Fock coefficients as without weights
+H_ABS, V_NORM, COEF_NORM = 1e-5, 1e-5, 1e-6
+FOCK_NORM = {"fp32": 1e-5, "bf16x3": 5e-5}
+# (n_water, n_pa, seed): one water (N = 24, every tile mostly padding); a
+# dimer with a ragged tail (N = 222); several 64-point tiles and 32-point
+# j blocks (N = 900); the dimer workload size (N = 4200)
+CASES = [(1, 8, 11), (2, 37, 5), (2, 150, 21), (2, 700, 1001)]
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+@functools.lru_cache(maxsize=8)
+def becke(n_water, n_pa, seed):
+    return inputs.make_problem(n_water, n_pa, seed, weights="becke")
+
+
+@functools.lru_cache(maxsize=8)
+def oracle_weighted(n_water, n_pa, seed):
+    p = becke(n_water, n_pa, seed)
+    g, gx = oracle.problem_inputs(p)
+    args = (p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b, p.C, p.rho_x, gx)
+    H, _ = oracle.hessian_terms(*args, w_x=p.w_x)
+    G = oracle.gradient(*args, w_x=p.w_x)
+    vr, vg = oracle.fock_nuclear_terms(*args, w_x=p.w_x)
+    coef = oracle.weight_coefficients(p.coords, p.weights, p.rho, g, p.b, p.C)
+    return H, G, vr, vg, coef
+
+
+def _run(torch, p, prec, w_x):
+    from paper_2208_14639_amd import vv10
+    with vv10.Plan(p, prec=prec) as pl:
+        out = pl.nuclear_terms(p.rho_x, p.grad_rho_x, hess=True, grad=True, fock=True,
+                               w_x=w_x, w_coef=True)
+        g = pl.gradient(p.rho_x, p.grad_rho_x, w_x=w_x)
+        torch.cuda.synchronize()
+        res = {k: v.cpu().numpy() for k, v in out.items()}
+        res["grad_only"] = g.cpu().numpy()
+    return res
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("case", CASES)
+def test_weighted_terms_vs_oracle(torch, case, prec):
+    _say("weighted terms", prec, case)
+    p = becke(*case)
+    H0, G0, vr0, vg0, coef0 = oracle_weighted(*case)
+    r = _run(torch, p, prec, p.w_x)
+    errs = dict(hess=normwise(r["hess"], H0), hess_abs=float(np.max(np.abs(r["hess"] - H0))),
+                grad=normwise(r["grad"], G0), grad_only=normwise(r["grad_only"], G0),
+                fock_rho=normwise(r["fock_rho"], vr0), fock_gamma=normwise(r["fock_gamma"], vg0),
+                w_coef=normwise(r["w_coef"], coef0))
+    _say("   errors", errs)
+    assert np.array_equal(r["hess"], r["hess"].T)
+    if prec == "fp64":
+        for k in ("hess", "grad", "grad_only", "fock_rho", "fock_gamma", "w_coef"):
+            assert errs[k] < TOL64, (k, errs[k])
+    else:
+        assert errs["hess_abs"] <= H_ABS
+        assert errs["grad"] <= V_NORM and errs["grad_only"] <= V_NORM
+        assert errs["w_coef"] <= COEF_NORM
+        assert errs["fock_rho"] <= FOCK_NORM[prec] and errs["fock_gamma"] <= FOCK_NORM[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_owner_entries_not_read(torch, prec):
+    """The owner-atom entries of w_x come from translational invariance: any
+    values there give bitwise the same outputs."""
+    p = becke(2, 37, 5)
+    wx = p.w_x.copy()
+    own = (np.arange(p.n_pert)[:, None] // 3) == p.atom_of[None, :]
+    wx[own] = np.random.default_rng(3).standard_normal(int(own.sum())) * 1e3
+    a = _run(torch, p, prec, p.w_x)
+    b = _run(torch, p, prec, wx)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_zero_weight_derivatives_match_fixed_weights(torch, prec):
+    """w_x = 0 reproduces the fixed-weight outputs (up to the order in which
+    the extra zero slices are summed), and a weighted call leaves the plan's
+    later fixed-weight calls unchanged."""
+    from paper_2208_14639_amd import vv10
+    p = becke(2, 37, 5)
+    z = np.zeros_like(p.w_x)
+    with vv10.Plan(p, prec=prec) as pl:
+        base = pl.nuclear_terms(p.rho_x, p.grad_rho_x, hess=True, grad=True, fock=True)
+        zero = pl.nuclear_terms(p.rho_x, p.grad_rho_x, hess=True, grad=True, fock=True, w_x=z)
+        pl.nuclear_terms(p.rho_x, p.grad_rho_x, hess=True, grad=True, fock=True, w_x=p.w_x)
+        again = pl.nuclear_terms(p.rho_x, p.grad_rho_x, hess=True, grad=True, fock=True)
+        torch.cuda.synchronize()
+        c = lambda d, k: d[k].cpu().numpy()
+        for k in ("hess", "grad", "fock_rho", "fock_gamma"):
+            assert normwise(c(zero, k), c(base, k)) < 1e-14, k
+            assert np.array_equal(c(again, k), c(base, k)), k
+
+
+def test_weighted_gradient_fd_consistency(torch):
+    """The GPU gradient with weights equals the oracle's, which central
+    differences of the energy pin; without w_x it misses E_w."""
+    p = becke(2, 150, 21)
+    _, G0, _, _, _ = oracle_weighted(2, 150, 21)
+    from paper_2208_14639_amd import vv10
+    with vv10.Plan(p, prec="fp64") as pl:
+        gw = pl.gradient(p.rho_x, p.grad_rho_x, w_x=p.w_x).cpu().numpy()
+        g0 = pl.gradient(p.rho_x, p.grad_rho_x).cpu().numpy()
+    assert normwise(gw, G0) < TOL64
+    assert normwise(g0, G0) > 1e-3
+
+
+def test_weighted_errors(torch):
+    from paper_2208_14639_amd import vv10
+    p = becke(1, 8, 11)
+    with vv10.Plan(p, prec="fp64") as pl:
+        wx = torch.as_tensor(p.w_x, device="cuda")
+        rx = torch.as_tensor(p.rho_x, device="cuda")
+        gx = torch.as_tensor(p.grad_rho_x, device="cuda")
+        c = torch.empty(p.n_grid, dtype=torch.float64, device="cuda")
+        # w_coef alone: no weight work, the coefficient still formed
+        vv10.vv10_nuclear_terms(pl.handle, p.n_pert, rx, gx, w_x=wx, w_coef=c)
+        torch.cuda.synchronize()
+        g = oracle.gamma(p.grad_rho)
+        coef0 = oracle.weight_coefficients(p.coords, p.weights, p.rho, g, p.b, p.C)
+        assert normwise(c.cpu().numpy(), coef0) < TOL64
+        with pytest.raises(vv10.VV10Error) as ei:
+            vv10.vv10_gradient(pl.handle, p.n_pert - 1, rx, gx, c, w_x=wx)
+        assert ei.value.status == vv10.VV10_E_ARG
+
+
+def test_hexamer_becke_full_size(torch):
+    """Water hexamer (N = 27000, P = 54) with Becke weights, split-BF16 as
+    timed: the Hessian exactly symmetric and translationally invariant to the
+    mixed bound; the weight part of the Fock coefficients (weighted minus
+    fixed-weight call) against the oracle's E^{xw}, U^{xw}, W^{xw} on sampled
+    rows."""
+    from paper_2208_14639_amd import vv10
+    p = inputs.make_workload("water_hexamer", weights="becke")
+    with vv10.Plan(p, prec="bf16x3", tiles="auto") as pl:
+        w = pl.nuclear_terms(p.rho_x, p.grad_rho_x, hess=True, fock=True, w_x=p.w_x)
+        f = pl.nuclear_terms(p.rho_x, p.grad_rho_x, hess=False, fock=True)
+        torch.cuda.synchronize()
+        H = w["hess"].cpu().numpy()
+        dr = (w["fock_rho"] - f["fock_rho"]).cpu().numpy()
+        dg = (w["fock_gamma"] - f["fock_gamma"]).cpu().numpy()
+    assert np.array_equal(H, H.T)
+    rows = H.reshape(p.n_pert, p.n_atom, 3).sum(axis=1)
+    _say("   hexamer translational residual", np.max(np.abs(rows)), "of", np.max(np.abs(H)))
+    assert np.max(np.abs(rows)) <= 1e-5 * np.max(np.abs(H))
+    g = oracle.gamma(p.grad_rho)
+    kr = np.zeros(p.n_grid)
+    sr, sg = np.max(np.abs(dr)), np.max(np.abs(dg))
+    for i0 in (0, 13511, p.n_grid - 5):
+        i1 = i0 + 5
+        _say("   hexamer weight rows", i0)
+        Ew, Uw, Ww = oracle.weight_integrals(p.coords, p.rho, g, p.b, p.C, p.w_x, i0, i1)
+        pr = [oracle.point(p.b, p.C, float(p.rho[i]), float(g[i])) for i in range(i0, i1)]
+        kr = np.array([q["kappa_r"] for q in pr])
+        orr = np.array([q["omega_r"] for q in pr])
+        og = np.array([q["omega_g"] for q in pr])
+        rho = p.rho[i0:i1]
+        wr = Ew + rho * (kr * Uw + orr * Ww)
+        wg = rho * og * Ww
+        assert np.max(np.abs(dr[:, i0:i1] - wr)) <= FOCK_NORM["bf16x3"] * sr
+        assert np.max(np.abs(dg[:, i0:i1] - wg)) <= FOCK_NORM["bf16x3"] * sg
