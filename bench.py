@@ -32,6 +32,7 @@ PEAKS_TFLOPS = {"mfma_f64": 78.6, "mfma_f32": 157.3, "mfma_bf16": 2500.0, "valu_
 HBM_GBS = 8000.0
 # algorithmic work per unit
 FLOPS_PER_PAIR_PERT = 8          # contraction: 4 FMAs per pair and perturbation
+FLOPS_PER_PAIR_PERT_W = 6        # weight contraction: 3 FMAs per pair and perturbation
 FLOPS_PER_PAIR_INTEGRALS = 38    # E, U, W (26) + A, B, C (12)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
@@ -61,13 +62,41 @@ def measured_traffic(kernel_key, workload, prec):
     return rec["bytes_per_launch"]
 
 
+def row_sample(fn, n, target_s=10.0):
+    """Rows 0..k of a row-wise oracle step fn(k), k sized so that the timed
+    call takes about target_s: its fixed cost (a full pair-integral pass) and
+    per-row cost come from calls on 16 and 48 rows.  Returns (k, seconds, result)."""
+    t0 = time.perf_counter()
+    fn(16)
+    ta = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    fn(48)
+    tb = time.perf_counter() - t0
+    per = max((tb - ta) / 32, 1e-7)
+    fixed = max(ta - 16 * per, 0.0)
+    k = int(max(16, min(n, (target_s - fixed) / per)))
+    t0 = time.perf_counter()
+    res = fn(k)
+    return k, time.perf_counter() - t0, res
+
+
 def cpu_baseline(p, budget_s=30.0):
     """FP64 oracle on the host.  Full workload when it fits the budget, else
-    the dominant O(N^2 P) step (response rows) on a row sample."""
+    the dominant O(N^2 P) step (response rows, and with weight derivatives the
+    weight integrals of the same rows) on a row sample."""
     import oracle
     g, gx = oracle.problem_inputs(p)
     n, P = p.n_grid, p.n_pert
     est_rate = 3e9 * oracle.num_threads() / 8      # pair*pert/s, measured order of magnitude
+    if p.w_x is not None:
+        def rows(k):
+            oracle.response_rows(0, k, p.coords, p.weights, p.rho, g, p.b, p.C, p.rho_x, gx)
+            oracle.weight_integrals(p.coords, p.rho, g, p.b, p.C, p.w_x, 0, k)
+        k, dt, _ = row_sample(rows, n)
+        return dict(value=k * n * P / dt, unit="pair*pert/s", cores=oracle.num_threads(),
+                    kind="oracle", seconds=dt,
+                    sample=f"response rows and weight integrals of rows 0..{k} of N={n}, P={P} "
+                           f"(dominant N^2 P steps incl. one full pair-integral pass)"), None
     if n * n * P / est_rate <= budget_s:
         t0 = time.perf_counter()
         H, _ = oracle.hessian_terms(p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b, p.C,
@@ -78,14 +107,8 @@ def cpu_baseline(p, budget_s=30.0):
                     kind="oracle", seconds=dt,
                     sample=f"whole workload: energy, potential and Hessian terms, N={n}, P={P}"), \
             dict(H=H, E=e0, f_rho=fr0, f_gamma=fg0)
-    # row sample: calibrate on 16 rows, then size to ~10 s
-    t0 = time.perf_counter()
-    oracle.response_rows(0, 16, p.coords, p.weights, p.rho, g, p.b, p.C, p.rho_x, gx)
-    t16 = time.perf_counter() - t0
-    k = max(16, min(n, int(16 * 10.0 / max(t16, 1e-3))))
-    t0 = time.perf_counter()
-    oracle.response_rows(0, k, p.coords, p.weights, p.rho, g, p.b, p.C, p.rho_x, gx)
-    dt = time.perf_counter() - t0
+    k, dt, _ = row_sample(
+        lambda k: oracle.response_rows(0, k, p.coords, p.weights, p.rho, g, p.b, p.C, p.rho_x, gx), n)
     return dict(value=k * n * P / dt, unit="pair*pert/s", cores=oracle.num_threads(),
                 kind="oracle", seconds=dt,
                 sample=f"response rows 0..{k} of N={n}, P={P} (dominant N^2 P step incl. one "
@@ -267,14 +290,9 @@ def bench_trial_response(args, torch, np, inputs, vv10, n_t=54):
         g = oracle.gamma(p.grad_rho)
         gam_t = oracle.gamma_x(p.grad_rho, gt)
         # rows 0..k of the oracle's response (one pair-integral pass per call),
-        # k calibrated on 16 rows to about 10 s
-        t0 = time.perf_counter()
-        oracle.response_rows(0, 16, p.coords, p.weights, p.rho, g, p.b, p.C, rt, gam_t)
-        t16 = time.perf_counter() - t0
-        k = max(16, min(n, int(16 * 10.0 / max(t16, 1e-3))))
-        t0 = time.perf_counter()
-        Yr, Yg = oracle.response_rows(0, k, p.coords, p.weights, p.rho, g, p.b, p.C, rt, gam_t)
-        dtc = time.perf_counter() - t0
+        # k sized to about 10 s
+        k, dtc, (Yr, Yg) = row_sample(
+            lambda k: oracle.response_rows(0, k, p.coords, p.weights, p.rho, g, p.b, p.C, rt, gam_t), n)
         err = max(float(np.max(np.abs(fr[:, :k] - Yr)) / np.max(np.abs(fr))),
                   float(np.max(np.abs(fg[:, :k] - Yg)) / np.max(np.abs(fg))))
         out["cpu_baseline"] = dict(value=k * n * n_t / dtc, unit="pair*pert/s",
@@ -355,7 +373,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="water_hexamer",
                     choices=["water_dimer", "water_hexamer", "water_20mer", "batch64", "served",
-                             "trial_response", "gradient"],
+                             "trial_response", "gradient", "becke_hexamer"],
                     help="batch64: 64 random clusters of 1-30 waters, 1500 points/atom, "
                          "one graph launch per step")
     ap.add_argument("--prec", default="bf16x3", choices=["fp64", "fp32", "bf16x3"],
@@ -392,7 +410,11 @@ def main():
         return bench_gradient(args, torch, np, inputs, vv10)
 
     from paper_2208_14639_amd import autotune
-    p = inputs.make_workload(args.workload)
+    weighted = args.workload == "becke_hexamer"
+    if weighted:
+        p = inputs.make_workload("water_hexamer", weights="becke")
+    else:
+        p = inputs.make_workload(args.workload)
     n, na, P = p.n_grid, p.n_atom, p.n_pert
     tuned = {name: autotune.lookup(n, na, name) for name in ("fp64", "fp32", "bf16x3")}
     log(f"workload {args.workload}: N={n} atoms={na} P={P} prec={args.prec}")
@@ -400,6 +422,8 @@ def main():
     coords, w, rho, grad = f64(p.coords), f64(p.weights), f64(p.rho), f64(p.grad_rho)
     atom_of = torch.as_tensor(p.atom_of, dtype=torch.int32).to(dev).contiguous()
     rho_x, grad_x = f64(p.rho_x), f64(p.grad_rho_x)
+    w_x = f64(p.w_x) if weighted else None
+    w_coef = torch.empty(n, dtype=torch.float64, device=dev) if weighted else None
     energy = torch.empty(1, dtype=torch.float64, device=dev)
     f_rho = torch.empty(n, dtype=torch.float64, device=dev)
     f_gamma = torch.empty(n, dtype=torch.float64, device=dev)
@@ -423,7 +447,11 @@ def main():
                 vv10.vv10_set_tiles(h, *tiles)
             vv10.vv10_set_timing(h, True)
             vv10.vv10_energy_potential(h, energy, f_rho, f_gamma)
-            vv10.vv10_hessian_terms(h, P, rho_x, grad_x, hess, gradient, None, None)
+            if weighted:
+                vv10.vv10_nuclear_terms(h, P, rho_x, grad_x, hess=hess, grad=gradient, w_x=w_x,
+                                        w_coef=w_coef)
+            else:
+                vv10.vv10_hessian_terms(h, P, rho_x, grad_x, hess, gradient, None, None)
             # each stage's latest run: the pair pass is the energy call's; read
             # once, where vv10_destroy would wait for the stream anyway
             st = vv10.vv10_stage_times(h)
@@ -452,7 +480,8 @@ def main():
     t_con = stage_ms["contract"] * 1e-3
     mfma_key = {"fp64": "mfma_f64", "fp32": "mfma_f32", "bf16x3": "mfma_bf16"}[args.prec]
     achieved = FLOPS_PER_PAIR_PERT * pair_pert / t_con / 1e12
-    traffic = measured_traffic("contract", args.workload, args.prec)
+    # the weighted workload runs the same main contraction launch on the same grid
+    traffic = measured_traffic("contract", "water_hexamer" if weighted else args.workload, args.prec)
     roofline = dict(bound="mfma", kernel=f"k_contract_{args.prec}", achieved=achieved,
                     peak=PEAKS_TFLOPS[mfma_key], unit="TFLOP/s",
                     frac=achieved / PEAKS_TFLOPS[mfma_key], traffic=traffic)
@@ -480,6 +509,13 @@ def main():
                         "valu_tflops": 26 * n * n / (stage_ms["pair"] * 1e-3) / 1e12},
         "footprint_bytes": vv10.vv10_footprint_bytes(n, na, prec),
     }
+    if weighted:
+        t_w = stage_ms["weights"] * 1e-3
+        aw = FLOPS_PER_PAIR_PERT_W * pair_pert / t_w / 1e12
+        out["config"]["weights"] = "becke"
+        out["weights_kernel"] = dict(bound="mfma", kernel=f"k_wcontract_{args.prec}", achieved=aw,
+                                     peak=PEAKS_TFLOPS[mfma_key], unit="TFLOP/s",
+                                     frac=aw / PEAKS_TFLOPS[mfma_key], stage_ms=stage_ms["weights"])
 
     cmp = None
     if args.compare != "none" and args.compare != args.prec:
