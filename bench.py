@@ -380,6 +380,11 @@ def main():
                     help="arithmetic of the headline path (default: split-BF16 mixed)")
     ap.add_argument("--compare", default="fp64", choices=["fp64", "fp32", "bf16x3", "none"],
                     help="also time this precision on the same workload (the 'vs FP64' ratio)")
+    ap.add_argument("--shells", action="store_true",
+                    help="store each atom's points in radial-shell order (same sample)")
+    ap.add_argument("--screen", type=float, default=0.0,
+                    help="contraction screening threshold tau (vv10_set_screening); with tau > 0 "
+                         "the comparison leg is the same precision unscreened")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one device copy of 256 MiB first (HBM counter calibration)")
@@ -412,9 +417,11 @@ def main():
     from paper_2208_14639_amd import autotune
     weighted = args.workload == "becke_hexamer"
     if weighted:
-        p = inputs.make_workload("water_hexamer", weights="becke")
+        p = inputs.make_workload("water_hexamer", weights="becke", radial_order=args.shells)
     else:
-        p = inputs.make_workload(args.workload)
+        p = inputs.make_workload(args.workload, radial_order=args.shells)
+    if args.screen > 0:
+        args.compare = args.prec          # the comparison leg: unscreened
     n, na, P = p.n_grid, p.n_atom, p.n_pert
     tuned = {name: autotune.lookup(n, na, name) for name in ("fp64", "fp32", "bf16x3")}
     log(f"workload {args.workload}: N={n} atoms={na} P={P} prec={args.prec}")
@@ -439,12 +446,17 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    def step(prec=prec, hess=hess, gradient=gradient, energy=energy, f_rho=f_rho, f_gamma=f_gamma):
+    screen_stats = []
+
+    def step(prec=prec, hess=hess, gradient=gradient, energy=energy, f_rho=f_rho, f_gamma=f_gamma,
+             tau=args.screen):
         h = vv10.vv10_prepare(p.b, p.C, n, na, coords, w, atom_of, rho, grad, prec, stream)
         try:
             tiles = tuned[vv10._prec_name(prec)]
             if tiles is not None:
                 vv10.vv10_set_tiles(h, *tiles)
+            if tau > 0:
+                vv10.vv10_set_screening(h, tau)
             vv10.vv10_set_timing(h, True)
             vv10.vv10_energy_potential(h, energy, f_rho, f_gamma)
             if weighted:
@@ -455,6 +467,8 @@ def main():
             # each stage's latest run: the pair pass is the energy call's; read
             # once, where vv10_destroy would wait for the stream anyway
             st = vv10.vv10_stage_times(h)
+            if tau > 0:
+                screen_stats.append(vv10.vv10_screening_stats(h))
         finally:
             vv10.vv10_destroy(h)
         return st
@@ -517,8 +531,31 @@ def main():
                                      peak=PEAKS_TFLOPS[mfma_key], unit="TFLOP/s",
                                      frac=aw / PEAKS_TFLOPS[mfma_key], stage_ms=stage_ms["weights"])
 
+    if args.shells:
+        out["config"]["point_order"] = "radial shells"
+    if args.screen > 0:
+        act, tot = screen_stats[-1]
+        out["config"]["screening_tau"] = args.screen
+        out["screening"] = {"active_blocks": act, "total_blocks": tot,
+                            "computed_fraction": act / tot,
+                            "computed_pair_pert_per_s": value * act / tot,
+                            "note": "value counts every pair; the contraction computed "
+                                    "computed_fraction of its (16-point, 16-column) blocks"}
+        hs = hess.clone()
     cmp = None
-    if args.compare != "none" and args.compare != args.prec:
+    if args.screen > 0:
+        h2 = torch.empty_like(hess)
+        g2 = torch.empty_like(gradient)
+        e2 = torch.empty_like(energy)
+        fr2, fg2 = torch.empty_like(f_rho), torch.empty_like(f_gamma)
+        dt2, st2 = timed("unscreened", hess=h2, gradient=g2, energy=e2, f_rho=fr2, f_gamma=fg2, tau=0.0)
+        Hu = h2.cpu().numpy()
+        out["vs_unscreened"] = {"ms_per_step": dt2 * 1e3, "value": pair_pert / dt2,
+                                "speedup": dt2 / dt, "contract_ms": st2["contract"],
+                                "screened_contract_ms": stage_ms["contract"],
+                                "hess_change_normwise": float(np.max(np.abs(hs.cpu().numpy() - Hu))
+                                                              / np.max(np.abs(Hu)))}
+    elif args.compare != "none" and args.compare != args.prec:
         h2 = torch.empty_like(hess)
         g2 = torch.empty_like(gradient)
         e2 = torch.empty_like(energy)

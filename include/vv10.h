@@ -282,6 +282,33 @@ vv10_status vv10_set_tiles(vv10_plan *plan, const vv10_tiles *tiles);
  * Errors: VV10_E_STATE (NULL plan), VV10_E_ARG (tiles NULL), VV10_E_OOM. */
 vv10_status vv10_get_tiles(vv10_plan *plan, vv10_tiles *tiles);
 
+/*
+ * vv10_set_screening -- grid screening of the perturbation contraction
+ * (Section II.B, last paragraph: sums over a batch of j are skipped where the
+ * perturbed densities are below a precision threshold; the paper gives no
+ * threshold).  With tau > 0, later vv10_nuclear_terms, vv10_hessian_terms
+ * and vv10_trial_response calls on this plan skip the MFMA work of every
+ * (16-point j block, 16-column block) whose channels all satisfy
+ *   max_{j in block} max(|p^x_j|, |q^x_j|) <= tau * max_j max(|p^x_j|, |q^x_j|)
+ * for each column x of the block (p = w rho^x, q = w rho (omega_r rho^x +
+ * omega_g gamma^x), the contraction's two channels).  The skipped terms are
+ * dropped: each is below tau of its column's largest block, and their sum
+ * over a row changes the contraction's outputs by a few tens of tau relative
+ * to the column's largest (4e-7 at tau = 1e-8 on a 5400-point water
+ * hexamer); tau = 0 (the default) computes every block and gives bitwise the
+ * unscreened results.  The saving is largest when the points of
+ * each atom are stored in radial-shell order.  Batches (vv10_batch_*) do not
+ * screen.  Adds (N/16) P bytes plus (N/16 + 1) P floats per workspace.
+ * Errors: VV10_E_STATE (NULL plan), VV10_E_ARG (tau negative or not finite).
+ */
+vv10_status vv10_set_screening(vv10_plan *plan, double tau);
+
+/* Active and total (16-point, 16-column) blocks of the plan's most recent
+ * screened contraction (waits for the plan's stream).  active, total HOST.
+ * Errors: VV10_E_STATE (NULL plan or no screened contraction yet),
+ * VV10_E_ARG (NULL outputs), VV10_E_HIP. */
+vv10_status vv10_screening_stats(vv10_plan *plan, int64_t *active, int64_t *total);
+
 /* ------------------------------------------------------------------------ */
 /* Batches: many molecules (grids) of uneven size evaluated together.        */
 /* ------------------------------------------------------------------------ */

@@ -54,12 +54,13 @@ constexpr int kJC = 32;   // j points per LDS stage
 template <int NCB>
 constexpr int smem_f64() { return 2 * kJC * (int)sizeof(double4) + kJC * 2 * NCB * 16 * (int)sizeof(double); }
 
-template <int NCB>
+template <int NCB, bool SCR = false>
 __device__ __forceinline__ void tile_f64(int64_t npad, int64_t jlen, int32_t Pp,
                                          const double4 *__restrict__ P0,
                                          const double4 *__restrict__ P1,
                                          const double *__restrict__ X, double *__restrict__ Yout,
-                                         int64_t itile, int grp, int split, char *smem) {
+                                         int64_t itile, int grp, int split, char *smem,
+                                         const uint32_t *__restrict__ mask = nullptr) {
     constexpr int NC = NCB * 16;
     double4 *sA = reinterpret_cast<double4 *>(smem);
     double4 *sB = sA + kJC;
@@ -70,6 +71,7 @@ __device__ __forceinline__ void tile_f64(int64_t npad, int64_t jlen, int32_t Pp,
     const int col0 = grp * NC;
     const int64_t jbeg = (int64_t)split * jlen;
     const int64_t jend = min(npad, jbeg + jlen);
+    constexpr int kJJUnroll = SCR ? 1 : 2;   // screened: fewer live registers
     const double4 a0 = P0[ibase + m], a1 = P1[ibase + m];
     const double ci = a1.z;
     v4d accp[NCB], accq[NCB];
@@ -92,7 +94,7 @@ __device__ __forceinline__ void tile_f64(int64_t npad, int64_t jlen, int32_t Pp,
             *reinterpret_cast<double2 *>(sX + row * NC + 2 * cc) = v;
         }
         __syncthreads();
-#pragma unroll 2
+#pragma unroll kJJUnroll
         for (int jj = 0; jj < kJC; jj += 4) {
             const int jl = jj + kq;
             const double4 b0 = sA[jl], b1 = sB[jl];
@@ -113,14 +115,17 @@ __device__ __forceinline__ void tile_f64(int64_t npad, int64_t jlen, int32_t Pp,
             const double kqp = R2 * __builtin_fma(cj, Pgg, Pg);
             const double kqq = R2 * R2 * Pgg;
             const double *xr = sX + (jl * 2) * NC + m;
+            const uint32_t mw = SCR ? mask[((j0 + jj) >> 4) * ((Pp >> 4) / NCB) + grp] : 0u;
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) {
+                if (SCR && !((mw >> cb) & 1u)) continue;
                 const double xp = xr[cb * 16];
                 accp[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(kpp, xp, accp[cb], 0, 0, 0);
                 accq[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(kqp, xp, accq[cb], 0, 0, 0);
             }
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) {
+                if (SCR && !((mw >> cb) & 1u)) continue;
                 const double xq = xr[NC + cb * 16];
                 accp[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(kpq, xq, accp[cb], 0, 0, 0);
                 accq[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(kqq, xq, accq[cb], 0, 0, 0);
@@ -171,12 +176,13 @@ __device__ __forceinline__ void pair_K(const float4 a0, const float4 a1, const f
 template <int NCB>
 constexpr int smem_f32() { return 2 * kJC * (int)sizeof(float4) + kJC * 2 * NCB * 16 * (int)sizeof(float); }
 
-template <int NCB>
+template <int NCB, bool SCR = false>
 __device__ __forceinline__ void tile_f32(int64_t npad, int64_t jlen, int32_t Pp,
                                          const float4 *__restrict__ P0,
                                          const float4 *__restrict__ P1,
                                          const float *__restrict__ X, float *__restrict__ Yout,
-                                         int64_t itile, int grp, int split, char *smem) {
+                                         int64_t itile, int grp, int split, char *smem,
+                                         const uint32_t *__restrict__ mask = nullptr) {
     constexpr int NC = NCB * 16;
     float4 *sA = reinterpret_cast<float4 *>(smem);
     float4 *sB = sA + kJC;
@@ -187,6 +193,7 @@ __device__ __forceinline__ void tile_f32(int64_t npad, int64_t jlen, int32_t Pp,
     const int col0 = grp * NC;
     const int64_t jbeg = (int64_t)split * jlen;
     const int64_t jend = min(npad, jbeg + jlen);
+    constexpr int kJJUnroll = SCR ? 1 : 2;   // screened: fewer live registers
     const float4 a0 = P0[ibase + m], a1 = P1[ibase + m];
     v4f accp[NCB], accq[NCB];
 #pragma unroll
@@ -207,20 +214,23 @@ __device__ __forceinline__ void tile_f32(int64_t npad, int64_t jlen, int32_t Pp,
             *reinterpret_cast<float4 *>(sX + row * NC + 4 * cc) = v;
         }
         __syncthreads();
-#pragma unroll 2
+#pragma unroll kJJUnroll
         for (int jj = 0; jj < kJC; jj += 4) {
             const int jl = jj + kq;
             float kpp, kpq, kqp, kqq;
             pair_K(a0, a1, sA[jl], sB[jl], kpp, kpq, kqp, kqq);
             const float *xr = sX + (jl * 2) * NC + m;
+            const uint32_t mw = SCR ? mask[((j0 + jj) >> 4) * ((Pp >> 4) / NCB) + grp] : 0u;
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) {
+                if (SCR && !((mw >> cb) & 1u)) continue;
                 const float xp = xr[cb * 16];
                 accp[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(kpp, xp, accp[cb], 0, 0, 0);
                 accq[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(kqp, xp, accq[cb], 0, 0, 0);
             }
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) {
+                if (SCR && !((mw >> cb) & 1u)) continue;
                 const float xq = xr[NC + cb * 16];
                 accp[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(kpq, xq, accp[cb], 0, 0, 0);
                 accq[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(kqq, xq, accq[cb], 0, 0, 0);
@@ -299,14 +309,15 @@ __device__ __forceinline__ Aops form_A(const float4 a0, const float4 a1, const f
 template <int NCB>
 constexpr int smem_bf16x3() { return 2 * 2 * NCB * 16 * 4 * (int)sizeof(bf16x8); }
 
-template <int NCB>
+template <int NCB, bool SCR = false>
 __device__ __forceinline__ void tile_bf16x3(int64_t npad, int64_t jlen, int32_t Pp,
                                             const float4 *__restrict__ P0,
                                             const float4 *__restrict__ P1,
                                             const bf16x8 *__restrict__ Xhi,
                                             const bf16x8 *__restrict__ Xlo,
                                             float *__restrict__ Yout, int64_t itile, int grp,
-                                            int split, char *smem) {
+                                            int split, char *smem,
+                                            const uint32_t *__restrict__ mask = nullptr) {
     constexpr int NC = NCB * 16;
     constexpr int UNITS = NC * 4;                       // 8-bf16 units per block and array
     constexpr int PER = (UNITS + 255) / 256;            // units per thread and array
@@ -369,19 +380,59 @@ __device__ __forceinline__ void tile_bf16x3(int64_t npad, int64_t jlen, int32_t 
     for (int64_t j0 = jbeg; j0 < jend; j0 += 16) {
         const bool more = j0 + 16 < jend;
         if (more) load_x(j0 + 16);
-        const Aops nxt = form_A(a0, a1, n0, n1);
-        load_pts(j0 + 32);
         const bf16x8 *hp = sH[buf] + m * 4 + g;
         const bf16x8 *lp = sL[buf] + m * 4 + g;
+        Aops nxt;
+        if constexpr (!SCR) {
+            nxt = form_A(a0, a1, n0, n1);
+            load_pts(j0 + 32);
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) {
-            const bf16x8 bh = hp[cb * 64], bl = lp[cb * 64];
-            accp[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.ph, bh, accp[cb], 0, 0, 0);
-            accq[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.qh, bh, accq[cb], 0, 0, 0);
-            accp[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.pl, bh, accp[cb], 0, 0, 0);
-            accq[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.ql, bh, accq[cb], 0, 0, 0);
-            accp[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.ph, bl, accp[cb], 0, 0, 0);
-            accq[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.qh, bl, accq[cb], 0, 0, 0);
+            for (int cb = 0; cb < NCB; ++cb) {
+                const bf16x8 bh = hp[cb * 64], bl = lp[cb * 64];
+                accp[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.ph, bh, accp[cb], 0, 0, 0);
+                accq[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.qh, bh, accq[cb], 0, 0, 0);
+                accp[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.pl, bh, accp[cb], 0, 0, 0);
+                accq[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.ql, bh, accq[cb], 0, 0, 0);
+                accp[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.ph, bl, accp[cb], 0, 0, 0);
+                accq[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.qh, bl, accq[cb], 0, 0, 0);
+            }
+        } else {
+            // Screened: the skipped blocks are branches, which the compiler
+            // does not schedule across, so the next block's A operands are
+            // formed one pair at a time between the column blocks' MFMA
+            // groups (the MFMAs in flight overlap the pair arithmetic).
+            const uint32_t mw = mask[(j0 >> 4) * ((Pp >> 4) / NCB) + grp];
+            uint32_t ph[4], pl[4], qh[4], ql[4];
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                if ((mw >> cb) & 1u) {
+                    const bf16x8 bh = hp[cb * 64], bl = lp[cb * 64];
+                    accp[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.ph, bh, accp[cb], 0, 0, 0);
+                    accq[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.qh, bh, accq[cb], 0, 0, 0);
+                    accp[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.pl, bh, accp[cb], 0, 0, 0);
+                    accq[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.ql, bh, accq[cb], 0, 0, 0);
+                    accp[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.ph, bl, accp[cb], 0, 0, 0);
+                    accq[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.qh, bl, accq[cb], 0, 0, 0);
+                }
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    if (jj * NCB / 4 != cb) continue;      // pair jj after column block jj NCB/4
+                    // empty asm statements pin the pair arithmetic to this
+                    // point (after this column block's MFMAs are issued)
+                    asm volatile("" : "+v"(n0[jj].x), "+v"(n0[jj].y), "+v"(n0[jj].z), "+v"(n0[jj].w),
+                                 "+v"(n1[jj].x), "+v"(n1[jj].z));
+                    float kpp, kpq, kqp, kqq;
+                    pair_K(a0, a1, n0[jj], n1[jj], kpp, kpq, kqp, kqq);
+                    split2(kpp, kpq, ph[jj], pl[jj]);
+                    split2(kqp, kqq, qh[jj], ql[jj]);
+                    asm volatile("" ::"v"(ph[jj]), "v"(pl[jj]), "v"(qh[jj]), "v"(ql[jj]));
+                }
+            }
+            nxt.ph = __builtin_bit_cast(bf16x8, (uint4){ph[0], ph[1], ph[2], ph[3]});
+            nxt.pl = __builtin_bit_cast(bf16x8, (uint4){pl[0], pl[1], pl[2], pl[3]});
+            nxt.qh = __builtin_bit_cast(bf16x8, (uint4){qh[0], qh[1], qh[2], qh[3]});
+            nxt.ql = __builtin_bit_cast(bf16x8, (uint4){ql[0], ql[1], ql[2], ql[3]});
+            load_pts(j0 + 32);
         }
         cur = nxt;
         if (more) store_x(buf ^ 1);
@@ -400,59 +451,72 @@ __device__ __forceinline__ void tile_bf16x3(int64_t npad, int64_t jlen, int32_t 
 }
 
 // One workgroup per (i tile, column group, j split): blockIdx = (tile, group, split).
-template <int NCB>
+// SCR: skip the (16-point, 16-column) blocks that the screening mask marks
+// inactive (the MFMA work only; the kernel tile is still formed).
+template <int NCB, bool SCR>
 __global__ __launch_bounds__(256, 2) void k_contract_f64(int64_t npad, int64_t jlen, int32_t Pp,
                                                          const double4 *__restrict__ P0,
                                                          const double4 *__restrict__ P1,
                                                          const double *__restrict__ X,
-                                                         double *__restrict__ Yout) {
+                                                         double *__restrict__ Yout,
+                                                         const uint32_t *__restrict__ mask) {
     __shared__ __attribute__((aligned(16))) char smem[smem_f64<NCB>()];
-    tile_f64<NCB>(npad, jlen, Pp, P0, P1, X, Yout, blockIdx.x, blockIdx.y, blockIdx.z, smem);
+    tile_f64<NCB, SCR>(npad, jlen, Pp, P0, P1, X, Yout, blockIdx.x, blockIdx.y, blockIdx.z, smem,
+                       mask);
 }
 
-template <int NCB>
+template <int NCB, bool SCR>
 __global__ __launch_bounds__(256, 2) void k_contract_f32(int64_t npad, int64_t jlen, int32_t Pp,
                                                          const float4 *__restrict__ P0,
                                                          const float4 *__restrict__ P1,
                                                          const float *__restrict__ X,
-                                                         float *__restrict__ Yout) {
+                                                         float *__restrict__ Yout,
+                                                         const uint32_t *__restrict__ mask) {
     __shared__ __attribute__((aligned(16))) char smem[smem_f32<NCB>()];
-    tile_f32<NCB>(npad, jlen, Pp, P0, P1, X, Yout, blockIdx.x, blockIdx.y, blockIdx.z, smem);
+    tile_f32<NCB, SCR>(npad, jlen, Pp, P0, P1, X, Yout, blockIdx.x, blockIdx.y, blockIdx.z, smem,
+                       mask);
 }
 
-template <int NCB>
+template <int NCB, bool SCR>
 __global__ __launch_bounds__(256, 2) void k_contract_bf16x3(int64_t npad, int64_t jlen, int32_t Pp,
                                                             const float4 *__restrict__ P0,
                                                             const float4 *__restrict__ P1,
                                                             const bf16x8 *__restrict__ Xhi,
                                                             const bf16x8 *__restrict__ Xlo,
-                                                            float *__restrict__ Yout) {
+                                                            float *__restrict__ Yout,
+                                                            const uint32_t *__restrict__ mask) {
     __shared__ __attribute__((aligned(16))) char smem[smem_bf16x3<NCB>()];
-    tile_bf16x3<NCB>(npad, jlen, Pp, P0, P1, Xhi, Xlo, Yout, blockIdx.x, blockIdx.y, blockIdx.z,
-                     smem);
+    tile_bf16x3<NCB, SCR>(npad, jlen, Pp, P0, P1, Xhi, Xlo, Yout, blockIdx.x, blockIdx.y,
+                          blockIdx.z, smem, mask);
 }
 
-template <int NCB>
-hipError_t run(vv10_plan *p, const Workspace &ws) {
+template <int NCB, bool SCR>
+hipError_t run_mode(vv10_plan *p, const Workspace &ws) {
     dim3 grid((unsigned)(p->npad / 64), (unsigned)ws.ngroups, (unsigned)ws.jsplit);
+    const uint32_t *mask = SCR ? ws.mask : nullptr;
     if (p->prec == VV10_FP64) {
         if constexpr (NCB <= 8)
-            k_contract_f64<NCB><<<grid, 256, 0, p->stream>>>(
+            k_contract_f64<NCB, SCR><<<grid, 256, 0, p->stream>>>(
                 p->npad, ws.jlen, ws.Pp, p->P0, p->P1, static_cast<const double *>(ws.X),
-                static_cast<double *>(ws.Ypart));
+                static_cast<double *>(ws.Ypart), mask);
         else
             return hipErrorInvalidValue;
     } else if (p->prec == VV10_MIXED_FP32) {
-        k_contract_f32<NCB><<<grid, 256, 0, p->stream>>>(
+        k_contract_f32<NCB, SCR><<<grid, 256, 0, p->stream>>>(
             p->npad, ws.jlen, ws.Pp, p->P0f, p->P1f, static_cast<const float *>(ws.X),
-            static_cast<float *>(ws.Ypart));
+            static_cast<float *>(ws.Ypart), mask);
     } else {
         const bf16x8 *xh = static_cast<const bf16x8 *>(ws.X);
         const bf16x8 *xl = xh + (size_t)p->npad * ws.Pp * 2 / 8;
-        k_contract_bf16x3<NCB><<<grid, 256, 0, p->stream>>>(
-            p->npad, ws.jlen, ws.Pp, p->P0f, p->P1f, xh, xl, static_cast<float *>(ws.Ypart));
+        k_contract_bf16x3<NCB, SCR><<<grid, 256, 0, p->stream>>>(
+            p->npad, ws.jlen, ws.Pp, p->P0f, p->P1f, xh, xl, static_cast<float *>(ws.Ypart), mask);
     }
     return hipGetLastError();
+}
+
+template <int NCB>
+hipError_t run(vv10_plan *p, const Workspace &ws, bool screen) {
+    return screen ? run_mode<NCB, true>(p, ws) : run_mode<NCB, false>(p, ws);
 }
 
 template <int NCB>
@@ -461,13 +525,13 @@ int occupancy(vv10_precision prec) {
     hipError_t e;
     if (prec == VV10_FP64) {
         if constexpr (NCB <= 8)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_contract_f64<NCB>, 256, 0);
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_contract_f64<NCB, false>, 256, 0);
         else
             return 0;
     } else if (prec == VV10_MIXED_FP32) {
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_contract_f32<NCB>, 256, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_contract_f32<NCB, false>, 256, 0);
     } else {
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_contract_bf16x3<NCB>, 256, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_contract_bf16x3<NCB, false>, 256, 0);
     }
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -574,9 +638,9 @@ int contract_blocks_per_cu(vv10_precision prec, int ncb) {
     return dispatch_ncb(ncb, [&](auto c) { return occupancy<decltype(c)::value>(prec); });
 }
 
-hipError_t launch_contract(vv10_plan *p, const Workspace &ws) {
+hipError_t launch_contract(vv10_plan *p, const Workspace &ws, bool screen) {
     if (ws.ncb < 1 || ws.ncb > max_ncb(p->prec)) return hipErrorInvalidValue;
-    return dispatch_ncb(ws.ncb, [&](auto c) { return run<decltype(c)::value>(p, ws); });
+    return dispatch_ncb(ws.ncb, [&](auto c) { return run<decltype(c)::value>(p, ws, screen); });
 }
 
 }  // namespace vv10

@@ -139,15 +139,18 @@ __global__ __launch_bounds__(256) void k_prep(
 // The mixed modes store -3/2 p and -3/2 q: their contraction forms the pair
 // kernel divided by the -3/2 factor of Phi.
 // A 32 x 32 (point x perturbation) tile is staged through LDS so that the
-// [P][N] reads are coalesced.
+// [P][N] reads are coalesced.  With bmax (screening), also
+//   bmax[i/16][x] = max over the 16-point block of max(|p|, |q|).
 constexpr int TT = 32;
 template <int MODE>
 __global__ __launch_bounds__(256) void k_pert_prep(
     int64_t n, int64_t npad, int32_t P, int32_t Pp, const double *__restrict__ rho_x,
     const double *__restrict__ grad_rho_x, const double *__restrict__ F,
-    void *__restrict__ Xv, double *__restrict__ L) {
+    void *__restrict__ Xv, double *__restrict__ L, float *__restrict__ bmax) {
     __shared__ double sr[TT][TT + 1];
     __shared__ double sg[TT][TT + 1];
+    __shared__ float sm[2][8][TT];
+    float mblk[2] = {0.f, 0.f};
     const int64_t i0 = (int64_t)blockIdx.x * TT;
     const int x0 = blockIdx.y * TT;
     const int tx = threadIdx.x % TT, ty = threadIdx.x / TT;   // 32 x 8
@@ -176,6 +179,7 @@ __global__ __launch_bounds__(256) void k_pert_prep(
         const double sc = MODE == VV10_FP64 ? 1.0 : -1.5;
         const double p = sc * wi * rx;
         const double qv = sc * wi * r * (F[F_OMR * npad + i] * rx + F[F_OMG * npad + i] * gxv);
+        mblk[k / 16] = fmaxf(mblk[k / 16], (float)fmax(fabs(p), fabs(qv)));
         if (MODE == VV10_FP64) {
             double *X = static_cast<double *>(Xv);
             X[(i * 2 + 0) * Pp + x] = p;
@@ -197,6 +201,63 @@ __global__ __launch_bounds__(256) void k_pert_prep(
         L[(i * 2 + 0) * Pp + x] = rx;
         L[(i * 2 + 1) * Pp + x] = gxv;
     }
+    if (bmax) {   // uniform over the workgroup
+        sm[0][ty][tx] = mblk[0];
+        sm[1][ty][tx] = mblk[1];
+        __syncthreads();
+        const int x = x0 + tx;
+        if (ty < 2 && x < Pp) {
+            float m = 0.f;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) m = fmaxf(m, sm[ty][t][tx]);
+            bmax[(i0 / 16 + ty) * Pp + x] = m;
+        }
+    }
+}
+
+// Screening mask of the contraction (blocks of 16 points x 16 columns):
+// colmax[x] = max over blocks of bmax[.][x]; a block is active when one of
+// its columns has bmax > tau colmax.  mask[b][grp] holds one bit per column
+// block of the contraction's column group (one scalar load per j block in
+// the kernel).  count receives the number of active blocks (zeroed by
+// k_screen_zero first).
+__global__ void k_screen_zero(int32_t *count) { *count = 0; }
+
+__global__ __launch_bounds__(256) void k_colmax(int64_t nblk, int32_t Pp, const float *__restrict__ bmax,
+                                                float *__restrict__ colmax) {
+    __shared__ float s[256];
+    const int x = blockIdx.x;
+    float m = 0.f;
+    for (int64_t b = threadIdx.x; b < nblk; b += 256) m = fmaxf(m, bmax[b * Pp + x]);
+    s[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) s[threadIdx.x] = fmaxf(s[threadIdx.x], s[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) colmax[x] = s[0];
+}
+
+__global__ __launch_bounds__(256) void k_mask(int64_t nblk, int32_t Pp, int32_t ncb, float tau,
+                                              const float *__restrict__ bmax,
+                                              const float *__restrict__ colmax,
+                                              uint32_t *__restrict__ mask, int32_t *__restrict__ count) {
+    const int ngroups = Pp / (16 * ncb);
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= nblk * ngroups) return;
+    const int64_t b = k / ngroups;
+    const int grp = (int)(k - b * ngroups);
+    uint32_t bits = 0;
+    for (int cb = 0; cb < ncb; ++cb) {
+        bool active = false;
+        for (int c = 0; c < 16; ++c) {
+            const int x = (grp * ncb + cb) * 16 + c;
+            active |= bmax[b * Pp + x] > tau * colmax[x];
+        }
+        if (active) bits |= 1u << cb;
+    }
+    mask[k] = bits;
+    if (bits) atomicAdd(count, __popc(bits));
 }
 
 }  // namespace
@@ -216,17 +277,26 @@ hipError_t launch_prepare(vv10_plan *p, const double *coords, const double *w,
 }
 
 hipError_t launch_pert_prep(vv10_plan *p, const Workspace &ws, const double *rho_x,
-                            const double *grad_rho_x) {
+                            const double *grad_rho_x, bool screen) {
     dim3 grid((unsigned)((p->npad + TT - 1) / TT), (unsigned)((ws.Pp + TT - 1) / TT));
+    float *bmax = screen ? ws.bmax : nullptr;
     if (p->prec == VV10_FP64)
         k_pert_prep<VV10_FP64><<<grid, 256, 0, p->stream>>>(p->n, p->npad, ws.P, ws.Pp, rho_x,
-                                                            grad_rho_x, p->F, ws.X, ws.L);
+                                                            grad_rho_x, p->F, ws.X, ws.L, bmax);
     else if (p->prec == VV10_MIXED_FP32)
         k_pert_prep<VV10_MIXED_FP32><<<grid, 256, 0, p->stream>>>(p->n, p->npad, ws.P, ws.Pp, rho_x,
-                                                                  grad_rho_x, p->F, ws.X, ws.L);
+                                                                  grad_rho_x, p->F, ws.X, ws.L, bmax);
     else
         k_pert_prep<VV10_MIXED_BF16X3><<<grid, 256, 0, p->stream>>>(p->n, p->npad, ws.P, ws.Pp, rho_x,
-                                                                    grad_rho_x, p->F, ws.X, ws.L);
+                                                                    grad_rho_x, p->F, ws.X, ws.L, bmax);
+    if (!screen) return hipGetLastError();
+    const int64_t nblk = p->npad / 16;
+    k_colmax<<<(unsigned)ws.Pp, 256, 0, p->stream>>>(nblk, ws.Pp, ws.bmax, ws.colmax);
+    k_screen_zero<<<1, 1, 0, p->stream>>>(ws.screen_count);
+    const int64_t tot = nblk * ws.ngroups;
+    k_mask<<<(unsigned)((tot + 255) / 256), 256, 0, p->stream>>>(nblk, ws.Pp, ws.ncb,
+                                                                 (float)p->screen_tau, ws.bmax,
+                                                                 ws.colmax, ws.mask, ws.screen_count);
     return hipGetLastError();
 }
 

@@ -137,6 +137,10 @@ void give_event(int device, hipEvent_t ev) {
 }
 
 void free_workspace(Workspace &ws) {
+    dfree(ws.bmax);
+    dfree(ws.colmax);
+    dfree(ws.mask);
+    dfree(ws.screen_count);
     dfree(ws.X);
     dfree(ws.L);
     if (ws.Ypart != ws.Y) dfree(ws.Ypart);
@@ -292,6 +296,31 @@ static vv10_status ensure_gradient_work(vv10_plan *p) {
         return hip_status(e);
     }
     p->gw = gw;
+    return VV10_OK;
+}
+
+// Allocate the screening buffers of a workspace (once).
+static vv10_status ensure_screen(vv10_plan *p, Workspace &ws) {
+    if (ws.mask) return VV10_OK;
+    const size_t nblk = (size_t)p->npad / 16;
+    hipError_t e = dalloc(&ws.bmax, nblk * ws.Pp);
+    if (e == hipSuccess) e = dalloc(&ws.colmax, (size_t)ws.Pp);
+    if (e == hipSuccess) e = dalloc(&ws.mask, nblk * ws.ngroups);
+    if (e == hipSuccess) e = dalloc(&ws.screen_count, 1);
+    if (e != hipSuccess) {
+        dfree(ws.bmax);
+        dfree(ws.colmax);
+        dfree(ws.mask);
+        dfree(ws.screen_count);
+        ws.bmax = nullptr;
+        ws.colmax = nullptr;
+        ws.mask = nullptr;
+        ws.screen_count = nullptr;
+        (void)hipGetLastError();
+        return hip_status(e);
+    }
+    ws.bytes += nblk * ws.Pp * sizeof(float) + ws.Pp * sizeof(float) +
+                nblk * ws.ngroups * sizeof(uint32_t) + 4;
     return VV10_OK;
 }
 
@@ -517,6 +546,11 @@ vv10_status vv10_nuclear_terms(vv10_plan *p, int32_t n_pert, const double *rho_x
         st = ensure_weight_work(p);
         if (st != VV10_OK) return st;
     }
+    const bool screen = p->screen_tau > 0.0;
+    if (screen) {
+        st = ensure_screen(p, p->ws);
+        if (st != VV10_OK) return st;
+    }
     // the grid-term pass also produces the pair integrals E, U, W, A, B, C
     hipError_t e = stage(p, VV10_STAGE_GRID, [&] {
         return vv10::launch_grid_terms(p, weighted ? p->ww.Ze : nullptr);
@@ -527,8 +561,12 @@ vv10_status vv10_nuclear_terms(vv10_plan *p, int32_t n_pert, const double *rho_x
         e = hipMemcpyAsync(out->w_coef, p->F + (size_t)vv10::F_F0 * p->npad,
                            (size_t)p->n * sizeof(double), hipMemcpyDeviceToDevice, p->stream);
     if (e == hipSuccess)
-        e = stage(p, VV10_STAGE_PERT_PREP, [&] { return vv10::launch_pert_prep(p, p->ws, rho_x, grad_rho_x); });
-    if (e == hipSuccess) e = stage(p, VV10_STAGE_CONTRACT, [&] { return vv10::launch_contract(p, p->ws); });
+        e = stage(p, VV10_STAGE_PERT_PREP, [&] { return vv10::launch_pert_prep(p, p->ws, rho_x, grad_rho_x, screen); });
+    if (e == hipSuccess) e = stage(p, VV10_STAGE_CONTRACT, [&] { return vv10::launch_contract(p, p->ws, screen); });
+    if (e == hipSuccess) {
+        p->ws.screened = screen;
+        p->rws.screened = false;
+    }
     if (e == hipSuccess && weighted)
         e = stage(p, VV10_STAGE_WEIGHTS, [&] {
             hipError_t r = vv10::launch_weight_prep(p, w_x);
@@ -587,16 +625,25 @@ vv10_status vv10_trial_response(vv10_plan *p, int32_t n_t, const double *rho_t,
     if (n_t < 0 || n_t > VV10_MAX_TRIAL) return VV10_E_ARG;
     if (n_t == 0) return VV10_OK;
     if (!rho_t || !grad_rho_t || !f_rho_t || !f_gamma_t) return VV10_E_ARG;
-    const vv10_status st = ensure_response_workspace(p, n_t);
+    vv10_status st = ensure_response_workspace(p, n_t);
     if (st != VV10_OK) return st;
+    const bool screen = p->screen_tau > 0.0;
+    if (screen) {
+        st = ensure_screen(p, p->rws);
+        if (st != VV10_OK) return st;
+    }
     hipError_t e = hipSuccess;
     if (!p->ir_ready) {
         e = stage(p, VV10_STAGE_PAIR, [&] { return vv10::launch_pair_integrals(p, true, p->Ir); });
         if (e == hipSuccess) p->ir_ready = true;
     }
     if (e == hipSuccess)
-        e = stage(p, VV10_STAGE_PERT_PREP, [&] { return vv10::launch_pert_prep(p, p->rws, rho_t, grad_rho_t); });
-    if (e == hipSuccess) e = stage(p, VV10_STAGE_CONTRACT, [&] { return vv10::launch_contract(p, p->rws); });
+        e = stage(p, VV10_STAGE_PERT_PREP, [&] { return vv10::launch_pert_prep(p, p->rws, rho_t, grad_rho_t, screen); });
+    if (e == hipSuccess) e = stage(p, VV10_STAGE_CONTRACT, [&] { return vv10::launch_contract(p, p->rws, screen); });
+    if (e == hipSuccess) {
+        p->rws.screened = screen;
+        p->ws.screened = false;
+    }
     if (e == hipSuccess)
         e = stage(p, VV10_STAGE_ASSEMBLE, [&] { return vv10::launch_trial_response(p, f_rho_t, f_gamma_t); });
     if (e != hipSuccess) {
@@ -627,6 +674,31 @@ vv10_status vv10_set_tiles(vv10_plan *p, const vv10_tiles *t) {
 vv10_status vv10_set_stream(vv10_plan *p, hipStream_t stream) {
     if (!p) return VV10_E_STATE;
     p->stream = stream;
+    return VV10_OK;
+}
+
+vv10_status vv10_set_screening(vv10_plan *p, double tau) {
+    if (!p) return VV10_E_STATE;
+    if (!(tau >= 0.0) || !std::isfinite(tau)) return VV10_E_ARG;
+    p->screen_tau = tau;
+    return VV10_OK;
+}
+
+vv10_status vv10_screening_stats(vv10_plan *p, int64_t *active, int64_t *total) {
+    if (!p) return VV10_E_STATE;
+    if (!active || !total) return VV10_E_ARG;
+    const Workspace *ws = p->ws.screened ? &p->ws : (p->rws.screened ? &p->rws : nullptr);
+    if (!ws) return VV10_E_STATE;
+    int32_t count = 0;
+    hipError_t e = hipMemcpyAsync(&count, ws->screen_count, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                  p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return VV10_E_HIP;
+    }
+    *active = count;
+    *total = (p->npad / 16) * (ws->Pp / 16);
     return VV10_OK;
 }
 

@@ -53,6 +53,12 @@ struct Workspace {
     double *Hpart = nullptr;     // [gsplit][Pp + 1][Pp] GEMM slices; row Pp: gradient
     double *Hsum = nullptr;      // [Pp + 1][Pp] the slices summed
     double *DS = nullptr;        // [n_atom][n_atom][9] Dpart summed over each atom's tiles
+    // screening of the contraction (allocated when the plan screens)
+    float *bmax = nullptr;       // [npad/16][Pp] block maxima of max(|p|, |q|)
+    float *colmax = nullptr;     // [Pp] column maxima
+    uint32_t *mask = nullptr;    // [npad/16][ngroups] bit cb: (16-point, 16-column) block active
+    int32_t *screen_count = nullptr;  // number of active blocks of the last screened contraction
+    bool screened = false;       // the last contraction used the mask
     size_t bytes = 0;
 };
 
@@ -115,6 +121,9 @@ struct vv10_plan {
     // tile overrides (vv10_set_tiles); 0 = automatic
     int32_t tiles_jsplit = 0, tiles_bgroups = 0;
 
+    // screening threshold of the contraction (vv10_set_screening); 0 = off
+    double screen_tau = 0.0;
+
     // per-stage timing (vv10_set_timing)
     bool timing = false;
     hipEvent_t ev[2 * VV10_NUM_STAGES] = {};
@@ -171,9 +180,11 @@ hipError_t launch_prepare(vv10_plan *p, const double *coords, const double *w,
                           const double *grad_rho);
 hipError_t launch_pair_integrals(vv10_plan *p, bool hessian_mode, double *I_out);
 hipError_t launch_potential(vv10_plan *p, double *energy, double *f_rho, double *f_gamma);
+// screen: also the block maxima and the contraction mask (ws.bmax etc. allocated).
 hipError_t launch_pert_prep(vv10_plan *p, const Workspace &ws, const double *rho_x,
-                            const double *grad_rho_x);
-hipError_t launch_contract(vv10_plan *p, const Workspace &ws);
+                            const double *grad_rho_x, bool screen = false);
+// screen: skip the (16-point, 16-column) blocks that ws.mask marks inactive.
+hipError_t launch_contract(vv10_plan *p, const Workspace &ws, bool screen = false);
 hipError_t launch_grid_terms(vv10_plan *p, double *Ze);
 hipError_t launch_grid_grad(vv10_plan *p);
 hipError_t launch_gradient(vv10_plan *p, const double *rho_x, const double *grad_rho_x,

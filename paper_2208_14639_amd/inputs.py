@@ -16,7 +16,8 @@ Recipe (atomic units, bohr):
     any of its atoms comes within 1.0 Angstrom of an atom of another molecule;
   * grid: n_pa points per atom at R_A + r u with ln r uniform on
     [ln 0.05, ln 10] and u uniform on the unit sphere; points are stored
-    grouped by owning atom (atom_of is nondecreasing);
+    grouped by owning atom (atom_of is nondecreasing), within an atom in
+    sampling order or (radial_order) by increasing radius;
   * weights, two kinds:
     - "atomic" (default): w = 1/(N q(r)) with q(r) = 1/(4 pi r^3 ln(10/0.05))
       the three-dimensional density of one atom's sampler and N the total
@@ -153,12 +154,18 @@ def water_cluster(n_water: int, rng: np.random.Generator) -> Molecule:
     return Molecule(Z=Z, zeta=zeta, R=R)
 
 
-def atom_grid(n_atom: int, n_pa: int, rng: np.random.Generator):
-    """Per-atom sampler: returns (atom_of, offsets, radii)."""
+def atom_grid(n_atom: int, n_pa: int, rng: np.random.Generator, radial_order: bool = False):
+    """Per-atom sampler: returns (atom_of, offsets, radii).  With radial_order
+    each atom's points are stored by increasing radius (the shell order of
+    atom-centred product grids); the sample itself is the same."""
     lr = rng.uniform(math.log(R_MIN), math.log(R_MAX), size=(n_atom, n_pa))
     r = np.exp(lr)
     u = rng.standard_normal((n_atom, n_pa, 3))
     u /= np.linalg.norm(u, axis=2, keepdims=True)
+    if radial_order:
+        k = np.argsort(r, axis=1, kind="stable")
+        r = np.take_along_axis(r, k, axis=1)
+        u = np.take_along_axis(u, k[..., None], axis=1)
     offsets = (r[..., None] * u).reshape(-1, 3)
     atom_of = np.repeat(np.arange(n_atom, dtype=np.int32), n_pa)
     return atom_of, offsets, r.reshape(-1)
@@ -420,17 +427,20 @@ def build_problem(mol: Molecule, atom_of, offsets, radii, with_derivatives=True,
 
 
 def make_problem(n_water: int, n_pa: int, seed: int, with_derivatives=True,
-                 weights: str = "atomic", weight_hessian: bool = False) -> Problem:
+                 weights: str = "atomic", weight_hessian: bool = False,
+                 radial_order: bool = False) -> Problem:
     rng = np.random.default_rng(seed)
     mol = water_cluster(n_water, rng)
-    atom_of, offsets, radii = atom_grid(mol.n_atom, n_pa, rng)
+    atom_of, offsets, radii = atom_grid(mol.n_atom, n_pa, rng, radial_order)
     return build_problem(mol, atom_of, offsets, radii, with_derivatives, seed, weights,
                          weight_hessian)
 
 
-def make_workload(name: str, with_derivatives=True, weights: str = "atomic") -> Problem:
+def make_workload(name: str, with_derivatives=True, weights: str = "atomic",
+                  radial_order: bool = False) -> Problem:
     cfg = WORKLOADS[name]
-    return make_problem(cfg["n_water"], cfg["n_pa"], cfg["seed"], with_derivatives, weights)
+    return make_problem(cfg["n_water"], cfg["n_pa"], cfg["seed"], with_derivatives, weights,
+                        radial_order=radial_order)
 
 
 def displaced(p: Problem, atom: int, axis: int, h: float, with_derivatives=False) -> Problem:

@@ -88,6 +88,10 @@ def load() -> ctypes.CDLL:
     lib.vv10_version.argtypes = []
     lib.vv10_set_tiles.restype = st
     lib.vv10_set_tiles.argtypes = [P, ctypes.POINTER(vv10_tiles)]
+    lib.vv10_set_screening.restype = st
+    lib.vv10_set_screening.argtypes = [P, ctypes.c_double]
+    lib.vv10_screening_stats.restype = st
+    lib.vv10_screening_stats.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.vv10_cached_bytes.restype = ctypes.c_size_t
     lib.vv10_cached_bytes.argtypes = []
     lib.vv10_release_cached.restype = None
@@ -227,6 +231,21 @@ def vv10_set_stream(plan: int, stream) -> None:
         raise VV10Error(st, "vv10_set_stream")
 
 
+def vv10_set_screening(plan: int, tau: float) -> None:
+    st = load().vv10_set_screening(plan, float(tau))
+    if st != VV10_OK:
+        raise VV10Error(st, "vv10_set_screening")
+
+
+def vv10_screening_stats(plan: int):
+    """(active, total) (16-point, 16-column) blocks of the last screened contraction."""
+    a, t = ctypes.c_int64(0), ctypes.c_int64(0)
+    st = load().vv10_screening_stats(plan, ctypes.byref(a), ctypes.byref(t))
+    if st != VV10_OK:
+        raise VV10Error(st, "vv10_screening_stats")
+    return a.value, t.value
+
+
 def vv10_get_tiles(plan: int):
     t = vv10_tiles()
     st = load().vv10_get_tiles(plan, ctypes.byref(t))
@@ -305,7 +324,8 @@ class Plan:
     n_grid, n_atom, b, C (e.g. inputs.Problem); arrays are copied to the
     device as FP64/int32 tensors."""
 
-    def __init__(self, problem, prec="fp64", device="cuda", stream=None, tiles=None):
+    def __init__(self, problem, prec="fp64", device="cuda", stream=None, tiles=None,
+                 screening=0.0):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -328,6 +348,8 @@ class Plan:
         if tiles is not None:
             vv10_set_tiles(self.handle, *tiles)
         self.tiles = tiles
+        if screening:
+            vv10_set_screening(self.handle, screening)
 
     def _dev(self, a):
         return self.torch.as_tensor(a, dtype=self.torch.float64).to(self.device).contiguous()
