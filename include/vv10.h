@@ -105,6 +105,10 @@ vv10_status vv10_prepare(const vv10_params *params, int64_t n_grid, int32_t n_at
  *   f_gamma_i = rho_i domega/dgamma W_i
  * (so dE/drho_i = w_i f_rho_i and dE/dgamma_i = w_i f_gamma_i).
  *  energy   [1] device scalar.  f_rho, f_gamma [N]; either may be NULL.
+ * The pair integrals depend only on the plan's grid and density, so a plan
+ * forms each of them once and keeps it: this call's pair pass computes E, U,
+ * W unless an earlier call on the plan formed them (vv10_nuclear_terms adds
+ * A, B, C in its grid pass; vv10_gradient forms E, U, W in its own).
  * Errors: VV10_E_ARG (energy NULL), VV10_E_STATE, VV10_E_HIP.
  */
 vv10_status vv10_energy_potential(vv10_plan *plan, double *energy, double *f_rho,

@@ -81,9 +81,9 @@ __device__ __forceinline__ void add_pair_integrals(const PairGeo<T> &q, T *c) {
     c[5] += pmR2 * q.R2;
 }
 
-// One LDS chunk of points j of atom B != A: pair integrals into pc, grid
-// sums into c (see k_grid); the D sums only when DSUM.
-template <bool DSUM, typename T, typename T4>
+// One LDS chunk of points j of atom B != A: pair integrals into pc (when
+// INTS), grid sums into c (see k_grid); the D sums only when DSUM.
+template <bool DSUM, bool INTS, typename T, typename T4>
 __device__ __forceinline__ void grid_chunk(const T4 a0, const T4 a1, const T4 *sA, const T4 *sB,
                                            int cnt, T *pc, T *c) {
     const T oi = a0.w;
@@ -91,7 +91,7 @@ __device__ __forceinline__ void grid_chunk(const T4 a0, const T4 a1, const T4 *s
     for (int jj = 0; jj < cnt; ++jj) {
         const T4 b0 = sA[jj];
         const PairGeo<T> q = pair_geo<T>(a0, a1, b0, sB[jj]);
-        add_pair_integrals(q, pc);
+        if (INTS) add_pair_integrals(q, pc);
         const T dx = b0.x - a0.x, dy = b0.y - a0.y, dz = b0.z - a0.z;
         const T Ti = oi * q.ig, Tj = b0.w * q.igp, Ts = (oi + b0.w) * q.is;
         const T T_ = Ti + Tj + Ts;
@@ -117,9 +117,11 @@ __device__ __forceinline__ void grid_chunk(const T4 a0, const T4 a1, const T4 *s
     }
 }
 
-// Fused with the pair integrals of the Hessian call: the group of atoms B of
-// a workgroup also covers the outer point's own atom for E, U, W, A, B, C,
-// whose per-group partial sums go to Ipart[group][6][npad].
+// Fused with the pair integrals of the Hessian call (INTS): the group of
+// atoms B of a workgroup also covers the outer point's own atom for
+// E, U, W, A, B, C, whose per-group partial sums go to Ipart[group][6][npad].
+// Without INTS (the plan already holds the six integrals) the own atom is
+// skipped and only the grid sums are formed.
 //
 // Per pair (B != A), with Ti = omega_i/g, Tj = omega_j/g', Ts = (omega_i + omega_j)/s,
 // T = Ti + Tj + Ts, TQ = T h + Ti/g + Ts/s, S = T^2 + Ti^2 + Tj^2 + Ts^2, the
@@ -130,7 +132,7 @@ __device__ __forceinline__ void grid_chunk(const T4 a0, const T4 a1, const T4 *s
 // D = 6 sum p S d d^T - 3 (sum p T) I.  The D sums are symmetric in the two
 // atoms (the summand a_i a_j Phi (2 S d d^T - T I) is symmetric in i, j), so
 // they are formed for B > A only and the assembly reads them for both orders.
-template <typename T, typename T4>
+template <typename T, typename T4, bool INTS>
 __global__ __launch_bounds__(64) void k_grid(
     int32_t n_atom, int32_t Pp, int32_t bgroups, int64_t npad, const int64_t *__restrict__ seg,
     const int32_t *__restrict__ tile_i0, const int32_t *__restrict__ tile_n,
@@ -147,6 +149,7 @@ __global__ __launch_bounds__(64) void k_grid(
     const double ai = live ? (double)a1.y : 0.0, ci = (double)a1.z;
     double pint[6] = {};
     for (int B = grp; B < n_atom; B += bgroups) {
+        if (!INTS && B == A) continue;
         const int64_t jb = seg[B], je = seg[B + 1];
         const bool dsum = B > A;
         double acc[16] = {};
@@ -167,13 +170,14 @@ __global__ __launch_bounds__(64) void k_grid(
                 }
             } else {
                 T c[16] = {};
-                if (dsum) grid_chunk<true, T, T4>(a0, a1, sA, sB, cnt, pc, c);
-                else grid_chunk<false, T, T4>(a0, a1, sA, sB, cnt, pc, c);
+                if (dsum) grid_chunk<true, INTS, T, T4>(a0, a1, sA, sB, cnt, pc, c);
+                else grid_chunk<false, INTS, T, T4>(a0, a1, sA, sB, cnt, pc, c);
 #pragma unroll
                 for (int k = 0; k < 16; ++k) acc[k] += (double)c[k];
             }
+            if (INTS)
 #pragma unroll
-            for (int k = 0; k < 6; ++k) pint[k] += (double)pc[k];
+                for (int k = 0; k < 6; ++k) pint[k] += (double)pc[k];
         }
         if (B == A) continue;
         // E^{Bgr} = 3 acc[0..2], U^{Bgr} = -3 acc[3..5], W^{Bgr} = -3 acc[6..8]
@@ -209,18 +213,19 @@ __global__ __launch_bounds__(64) void k_grid(
             if (lane == 0) dp[k] = tot;
         }
     }
-    if (live) {
+    if (INTS && live) {
         const double sc[6] = {-1.5, 1.5, 1.5, -3.0, -3.0, -3.0};
 #pragma unroll
         for (int k = 0; k < 6; ++k) Ipart[((int64_t)grp * NI + k) * npad + i] = sc[k] * pint[k];
     }
 }
 
-// I[k][i] = sum over atom groups of Ipart[grp][k][i] (group order), k < nrows, i < n.
-__global__ __launch_bounds__(256) void k_sum_groups(int64_t n, int64_t npad, int G, int nrows,
+// I[k][i] = sum over atom groups of Ipart[grp][k][i] (group order),
+// k0 <= k < nrows, i < n.
+__global__ __launch_bounds__(256) void k_sum_groups(int64_t n, int64_t npad, int G, int nrows, int k0,
                                                     const double *__restrict__ Ipart,
                                                     double *__restrict__ I) {
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x + (int64_t)k0 * n;
     if (e >= (int64_t)nrows * n) return;
     const int k = (int)(e / n);
     const int64_t i = e - (int64_t)k * n;
@@ -235,7 +240,8 @@ __global__ __launch_bounds__(256) void k_sum_groups(int64_t n, int64_t npad, int
 // from which the grid part of the gradient follows,
 // E_gr = -sum_{B != A} sum_{i in A} a_i E^{Bgr}_i (translational invariance).
 // The layout and the scaled sums are those of k_grid: E^{Bgr}_i = 3 sum_j p T d.
-template <typename T, typename T4>
+// Without INTS (the plan already holds E, U, W) only the grid sums are formed.
+template <typename T, typename T4, bool INTS>
 __global__ __launch_bounds__(64) void k_grid_grad(
     int32_t n_atom, int32_t bgroups, int64_t npad, const int64_t *__restrict__ seg,
     const int32_t *__restrict__ tile_i0, const int32_t *__restrict__ tile_n,
@@ -254,6 +260,11 @@ __global__ __launch_bounds__(64) void k_grid_grad(
     for (int B = grp; B < n_atom; B += bgroups) {
         const int64_t jb = seg[B], je = seg[B + 1];
         double acc[3] = {};
+        if (!INTS && B == A) {
+            if (lane == 0)
+                for (int k = 0; k < 3; ++k) Gpart[((int64_t)t * n_atom + B) * 3 + k] = 0.0;
+            continue;
+        }
         for (int64_t j0 = jb; j0 < je; j0 += TG) {
             __syncthreads();
             const int64_t j = j0 + lane;
@@ -276,10 +287,12 @@ __global__ __launch_bounds__(64) void k_grid_grad(
                 for (int jj = 0; jj < cnt; ++jj) {
                     const T4 b0 = sA[jj];
                     const PairGeo<T> q = pair_geo<T>(a0, a1, b0, sB[jj]);
-                    const T ph = q.p * q.h;
-                    pc[0] += q.p;
-                    pc[1] += ph;
-                    pc[2] += ph * q.R2;
+                    if (INTS) {
+                        const T ph = q.p * q.h;
+                        pc[0] += q.p;
+                        pc[1] += ph;
+                        pc[2] += ph * q.R2;
+                    }
                     const T e = q.p * (oi * q.ig + b0.w * q.igp + (oi + b0.w) * q.is);
                     c[0] += e * (b0.x - a0.x);
                     c[1] += e * (b0.y - a0.y);
@@ -288,8 +301,9 @@ __global__ __launch_bounds__(64) void k_grid_grad(
 #pragma unroll
                 for (int k = 0; k < 3; ++k) acc[k] += (double)c[k];
             }
+            if (INTS)
 #pragma unroll
-            for (int k = 0; k < 3; ++k) pint[k] += (double)pc[k];
+                for (int k = 0; k < 3; ++k) pint[k] += (double)pc[k];
         }
         double *gp = Gpart + ((int64_t)t * n_atom + B) * 3;
 #pragma unroll
@@ -298,7 +312,7 @@ __global__ __launch_bounds__(64) void k_grid_grad(
             if (lane == 0) gp[k] = tot;
         }
     }
-    if (live) {
+    if (INTS && live) {
         const double sc[3] = {-1.5, 1.5, 1.5};
 #pragma unroll
         for (int k = 0; k < 3; ++k) Ipart[((int64_t)grp * 3 + k) * npad + i] = sc[k] * pint[k];
@@ -307,37 +321,55 @@ __global__ __launch_bounds__(64) void k_grid_grad(
 
 }  // namespace
 
-hipError_t launch_grid_terms(vv10_plan *p, double *Ze) {
+template <bool INTS>
+void grid_terms_mode(vv10_plan *p, double *Ze) {
     const Workspace &ws = p->ws;
     dim3 grid((unsigned)p->ntiles, (unsigned)ws.bgroups);
     if (p->prec == VV10_FP64)
-        k_grid<double, double4><<<grid, TG, 0, p->stream>>>(
+        k_grid<double, double4, INTS><<<grid, TG, 0, p->stream>>>(
             p->n_atom, ws.Pp, ws.bgroups, p->npad, p->d_seg, p->d_tile_i0, p->d_tile_n,
             p->d_tile_atom, p->P0, p->P1, ws.Z, Ze, ws.Dpart, ws.Igrp);
     else
-        k_grid<float, float4><<<grid, TG, 0, p->stream>>>(
+        k_grid<float, float4, INTS><<<grid, TG, 0, p->stream>>>(
             p->n_atom, ws.Pp, ws.bgroups, p->npad, p->d_seg, p->d_tile_i0, p->d_tile_n,
             p->d_tile_atom, p->P0f, p->P1f, ws.Z, Ze, ws.Dpart, ws.Igrp);
-    const int64_t tot = (int64_t)NI * p->n;
-    k_sum_groups<<<(unsigned)((tot + 255) / 256), 256, 0, p->stream>>>(p->n, p->npad, ws.bgroups, NI,
-                                                                       ws.Igrp, p->I);
-    return hipGetLastError();
 }
 
-hipError_t launch_grid_grad(vv10_plan *p) {
+template <bool INTS>
+void grid_grad_mode(vv10_plan *p) {
     const GradWork &gw = p->gw;
     dim3 grid((unsigned)p->ntiles, (unsigned)gw.bgroups);
     if (p->prec == VV10_FP64)
-        k_grid_grad<double, double4><<<grid, TG, 0, p->stream>>>(
+        k_grid_grad<double, double4, INTS><<<grid, TG, 0, p->stream>>>(
             p->n_atom, gw.bgroups, p->npad, p->d_seg, p->d_tile_i0, p->d_tile_n, p->d_tile_atom,
             p->P0, p->P1, gw.Gpart, gw.Igrp);
     else
-        k_grid_grad<float, float4><<<grid, TG, 0, p->stream>>>(
+        k_grid_grad<float, float4, INTS><<<grid, TG, 0, p->stream>>>(
             p->n_atom, gw.bgroups, p->npad, p->d_seg, p->d_tile_i0, p->d_tile_n, p->d_tile_atom,
             p->P0f, p->P1f, gw.Gpart, gw.Igrp);
+}
+
+hipError_t launch_grid_terms(vv10_plan *p, double *Ze, int ints_from) {
+    if (ints_from >= NI) {
+        grid_terms_mode<false>(p, Ze);
+        return hipGetLastError();
+    }
+    grid_terms_mode<true>(p, Ze);
+    const int64_t tot = (int64_t)(NI - ints_from) * p->n;
+    k_sum_groups<<<(unsigned)((tot + 255) / 256), 256, 0, p->stream>>>(
+        p->n, p->npad, p->ws.bgroups, NI, ints_from, p->ws.Igrp, p->I);
+    return hipGetLastError();
+}
+
+hipError_t launch_grid_grad(vv10_plan *p, bool ints) {
+    if (!ints) {
+        grid_grad_mode<false>(p);
+        return hipGetLastError();
+    }
+    grid_grad_mode<true>(p);
     const int64_t tot = (int64_t)3 * p->n;
-    k_sum_groups<<<(unsigned)((tot + 255) / 256), 256, 0, p->stream>>>(p->n, p->npad, gw.bgroups, 3,
-                                                                       gw.Igrp, p->I);
+    k_sum_groups<<<(unsigned)((tot + 255) / 256), 256, 0, p->stream>>>(p->n, p->npad, p->gw.bgroups,
+                                                                       3, 0, p->gw.Igrp, p->I);
     return hipGetLastError();
 }
 

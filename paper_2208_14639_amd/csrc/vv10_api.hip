@@ -518,7 +518,14 @@ vv10_status vv10_energy_potential(vv10_plan *p, double *energy, double *f_rho, d
     if (!p) return VV10_E_STATE;
     if (p->failed) return VV10_E_STATE;
     if (!energy) return VV10_E_ARG;
-    hipError_t e = stage(p, VV10_STAGE_PAIR, [&] { return vv10::launch_pair_integrals(p, false, p->I); });
+    // the pair pass forms E, U, W unless the plan holds them already (a later
+    // nuclear-terms call adds A, B, C in its grid pass, which shares the pair
+    // arithmetic)
+    hipError_t e = hipSuccess;
+    if (p->ints_level < 3) {
+        e = stage(p, VV10_STAGE_PAIR, [&] { return vv10::launch_pair_integrals(p, false, p->I); });
+        if (e == hipSuccess) p->ints_level = 3;
+    }
     if (e == hipSuccess)
         e = stage(p, VV10_STAGE_POTENTIAL, [&] { return vv10::launch_potential(p, energy, f_rho, f_gamma); });
     if (e != hipSuccess) {
@@ -552,9 +559,12 @@ vv10_status vv10_nuclear_terms(vv10_plan *p, int32_t n_pert, const double *rho_x
         if (st != VV10_OK) return st;
     }
     // the grid-term pass also produces the pair integrals E, U, W, A, B, C
+    // unless the plan holds them already
+    const int ints_from = p->ints_level;    // 0: all six, 3: A, B, C only, 6: none
     hipError_t e = stage(p, VV10_STAGE_GRID, [&] {
-        return vv10::launch_grid_terms(p, weighted ? p->ww.Ze : nullptr);
+        return vv10::launch_grid_terms(p, weighted ? p->ww.Ze : nullptr, ints_from);
     });
+    if (e == hipSuccess) p->ints_level = 6;
     if (e == hipSuccess)
         e = stage(p, VV10_STAGE_POTENTIAL, [&] { return vv10::launch_potential(p, nullptr, nullptr, nullptr); });
     if (e == hipSuccess && out->w_coef)
@@ -605,7 +615,9 @@ vv10_status vv10_gradient(vv10_plan *p, int32_t n_pert, const double *rho_x,
             return VV10_E_OOM;
         }
     }
-    hipError_t e = stage(p, VV10_STAGE_GRID, [&] { return vv10::launch_grid_grad(p); });
+    const bool ints = p->ints_level < 3;
+    hipError_t e = stage(p, VV10_STAGE_GRID, [&] { return vv10::launch_grid_grad(p, ints); });
+    if (e == hipSuccess && ints) p->ints_level = 3;
     if (e == hipSuccess)
         e = stage(p, VV10_STAGE_POTENTIAL, [&] { return vv10::launch_potential(p, nullptr, nullptr, nullptr); });
     if (e == hipSuccess)

@@ -95,6 +95,11 @@ struct vv10_plan {
     int device = 0;
     int num_cu = 256;
     bool failed = false;
+    // pair integrals held in I: 0 none, 3 (E, U, W), 6 (E..C).  Each is
+    // formed once, by the first call that needs it, and never overwritten
+    // (the inputs never change), so later calls do not depend on which
+    // call formed them.
+    int ints_level = 0;
 
     std::vector<int64_t> seg;       // host: atom segments, seg[A]..seg[A+1]
     std::vector<int32_t> tile_i0, tile_n, tile_atom, tile_first;  // grid-term tiles
@@ -185,8 +190,11 @@ hipError_t launch_pert_prep(vv10_plan *p, const Workspace &ws, const double *rho
                             const double *grad_rho_x, bool screen = false);
 // screen: skip the (16-point, 16-column) blocks that ws.mask marks inactive.
 hipError_t launch_contract(vv10_plan *p, const Workspace &ws, bool screen = false);
-hipError_t launch_grid_terms(vv10_plan *p, double *Ze);
-hipError_t launch_grid_grad(vv10_plan *p);
+// ints_from: the pair integrals I[k] for ints_from <= k < 6 are formed in the
+// same pass and written to p->I (0: all six; 6: none, the plan holds them).
+hipError_t launch_grid_terms(vv10_plan *p, double *Ze, int ints_from = 0);
+// ints: also E, U, W into p->I (else the plan holds them).
+hipError_t launch_grid_grad(vv10_plan *p, bool ints = true);
 hipError_t launch_gradient(vv10_plan *p, const double *rho_x, const double *grad_rho_x,
                            const double *w_x, double *grad);
 // Weight-derivative terms: owner slots, packing, contraction.
