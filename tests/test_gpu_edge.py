@@ -102,3 +102,74 @@ def test_water_20mer_full_size(torch):
                                       p.rho_x, gx)
         assert np.max(np.abs(rr[:, i0:i0 + 4] - Yr)) <= 5e-5 * sr
         assert np.max(np.abs(rg[:, i0:i0 + 4] - Yg)) <= 5e-5 * sg
+
+
+def _weighted(torch, p, prec):
+    from paper_2208_14639_amd import vv10
+    with vv10.Plan(p, prec=prec) as pl:
+        out = pl.nuclear_terms(p.rho_x, p.grad_rho_x, hess=True, grad=True, fock=True, w_x=p.w_x,
+                               w_coef=True)
+        torch.cuda.synchronize()
+        return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def _oracle_weighted(p):
+    g, gx = oracle.problem_inputs(p)
+    args = (p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b, p.C, p.rho_x, gx)
+    H, _ = oracle.hessian_terms(*args, w_x=p.w_x)
+    G = oracle.gradient(*args, w_x=p.w_x)
+    vr, vg = oracle.fock_nuclear_terms(*args, w_x=p.w_x)
+    return dict(hess=H, grad=G, fock_rho=vr, fock_gamma=vg,
+                w_coef=oracle.weight_coefficients(p.coords, p.weights, p.rho, g, p.b, p.C))
+
+
+def test_becke_atom_without_points(torch):
+    """Becke weights on a dimer whose second oxygen has no grid points: its
+    cell function still enters every other point's weight, so its
+    perturbations carry weight derivatives everywhere."""
+    rng = np.random.default_rng(41)
+    mol = inputs.water_cluster(2, rng)
+    ao, off, r = inputs.atom_grid(mol.n_atom, 45, rng)
+    keep = ao != 3
+    p = inputs.build_problem(mol, ao[keep], off[keep], r[keep], weights="becke")
+    assert np.max(np.abs(p.w_x[9:12])) > 0
+    ref = _oracle_weighted(p)
+    got = _weighted(torch, p, "fp64")
+    errs = {k: normwise(got[k], ref[k]) for k in ref}
+    _say("    becke, atom without points", errs)
+    assert max(errs.values()) < TOL64
+
+
+@pytest.mark.parametrize("n_pa", [1, 3])
+def test_becke_few_points(torch, n_pa):
+    p = inputs.make_problem(1, n_pa, 70 + n_pa, weights="becke")
+    ref = _oracle_weighted(p)
+    got = _weighted(torch, p, "fp64")
+    errs = {k: normwise(got[k], ref[k]) for k in ref}
+    assert max(errs.values()) < TOL64, errs
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_screening_several_column_groups(torch, prec):
+    """15 waters (P = 135: nine 16-column blocks, two column groups in FP64,
+    one in split-BF16), 40 points per atom in shell order: screened response
+    rows stay within the unscreened ones' bound of the oracle."""
+    from paper_2208_14639_amd import vv10
+    p = inputs.make_problem(15, 40, 91, radial_order=True)
+    g, gx = oracle.problem_inputs(p)
+    Yr0, Yg0 = oracle.response_rows(0, p.n_grid, p.coords, p.weights, p.rho, g, p.b, p.C,
+                                    p.rho_x, gx)
+    res = {}
+    for tau in (0.0, 1e-8):
+        with vv10.Plan(p, prec=prec, screening=tau) as pl:
+            out = pl.nuclear_terms(p.rho_x, p.grad_rho_x, hess=True, resp=True)
+            tiles = vv10.vv10_get_tiles(pl.handle)
+            stats = vv10.vv10_screening_stats(pl.handle) if tau else None
+            torch.cuda.synchronize()
+            res[tau] = {k: v.cpu().numpy() for k, v in out.items()}
+        _say("   ", prec, "tau", tau, "tiles", tiles, "stats", stats)
+    bound = TOL64 if prec == "fp64" else 5e-5
+    assert normwise(res[0.0]["resp_rho"], Yr0) < bound
+    assert normwise(res[1e-8]["resp_rho"], res[0.0]["resp_rho"]) < 3e-6
+    assert normwise(res[1e-8]["resp_gamma"], res[0.0]["resp_gamma"]) < 3e-6
+    assert normwise(res[1e-8]["hess"], res[0.0]["hess"]) < 3e-6
