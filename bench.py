@@ -64,20 +64,30 @@ def measured_traffic(kernel_key, workload, prec):
 
 def row_sample(fn, n, target_s=10.0):
     """Rows 0..k of a row-wise oracle step fn(k), k sized so that the timed
-    call takes about target_s: its fixed cost (a full pair-integral pass) and
-    per-row cost come from calls on 16 and 48 rows.  Returns (k, seconds, result)."""
+    call takes about target_s.  Each call has a fixed cost (a full
+    pair-integral pass) besides its per-row cost, so k grows by 4x until a
+    call takes a quarter of the target, and the last two calls give the
+    linear model used to size the timed call.  Returns (k, seconds, result)."""
+    k, prev = min(n, 256), None
+    while True:
+        t0 = time.perf_counter()
+        res = fn(k)
+        t = time.perf_counter() - t0
+        if k >= n or t >= target_s / 4:
+            break
+        prev = (k, t)
+        k = min(n, 4 * k)
+    if prev is not None and k > prev[0] and t > prev[1]:
+        per = (t - prev[1]) / (k - prev[0])
+        fixed = max(t - per * k, 0.0)
+    else:
+        per, fixed = t / k, 0.0
+    k2 = int(max(16, min(n, (target_s - fixed) / per)))
+    if k2 <= k:
+        return k, t, res
     t0 = time.perf_counter()
-    fn(16)
-    ta = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    fn(48)
-    tb = time.perf_counter() - t0
-    per = max((tb - ta) / 32, 1e-7)
-    fixed = max(ta - 16 * per, 0.0)
-    k = int(max(16, min(n, (target_s - fixed) / per)))
-    t0 = time.perf_counter()
-    res = fn(k)
-    return k, time.perf_counter() - t0, res
+    res = fn(k2)
+    return k2, time.perf_counter() - t0, res
 
 
 def cpu_baseline(p, budget_s=30.0):
