@@ -130,6 +130,9 @@ typedef struct {
     double *w_coef;      /* [N] rho_i (beta + E_i): the coefficient of w^A_i in E^A_w and of
                             w^{AB}_i in the first sum of E^{AB}_{w,w}, which the caller forms
                             from its weights' second derivatives */
+    double *energy;      /* [1] the VV10 energy (Section II.A), from the same pair pass */
+    double *f_rho;       /* [N] potential f^rho_i, as vv10_energy_potential */
+    double *f_gamma;     /* [N] potential f^gamma_i */
 } vv10_nuclear_outputs;
 
 /*
@@ -143,6 +146,9 @@ typedef struct {
  * basis-function or weight derivatives) belong to the caller.
  * fock_rho/fock_gamma equal the derivative of the potential f^rho, f^gamma
  * when nucleus A moves with its grid points (and, with w_x, its weights).
+ * energy, f_rho and f_gamma come from the pair integrals that the grid-term
+ * pass forms anyway, so one call gives energy, potential and Hessian with a
+ * single pass over the pairs (vv10_energy_potential first would add its own).
  * Outputs set to NULL are not formed (no output: no work).
  *  n_pert, rho_x, grad_rho_x as for vv10_hessian_terms.
  *  w_x   [n_pert][N] DEVICE, or NULL for weights that do not depend on the

@@ -84,7 +84,8 @@ hipError_t enqueue_batch(vv10_batch *b, const double *rho_x, const double *grad_
     for (size_t m = 0; m < nm && e == hipSuccess; ++m) {
         vv10_plan *p = b->plans[m];
         p->stream = b->side[m % K];
-        const vv10_nuclear_outputs out = {hess + b->h_off[m], nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+        const vv10_nuclear_outputs out = {hess + b->h_off[m], nullptr, nullptr, nullptr, nullptr,
+                                          nullptr, nullptr, nullptr, nullptr, nullptr};
         e = vv10::launch_assemble(p, out, false);
     }
     for (int k = 0; k < K && e == hipSuccess; ++k) {

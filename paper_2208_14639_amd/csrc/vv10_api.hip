@@ -543,7 +543,7 @@ vv10_status vv10_nuclear_terms(vv10_plan *p, int32_t n_pert, const double *rho_x
     if (p->failed) return VV10_E_STATE;
     if (n_pert != 3 * p->n_atom || !rho_x || !grad_rho_x || !out) return VV10_E_ARG;
     if (!out->hess && !out->grad && !out->resp_rho && !out->resp_gamma && !out->fock_rho &&
-        !out->fock_gamma && !out->w_coef)
+        !out->fock_gamma && !out->w_coef && !out->energy && !out->f_rho && !out->f_gamma)
         return VV10_OK;
     vv10_status st = vv10::ensure_workspace(p);
     if (st != VV10_OK) return st;
@@ -566,7 +566,9 @@ vv10_status vv10_nuclear_terms(vv10_plan *p, int32_t n_pert, const double *rho_x
     });
     if (e == hipSuccess) p->ints_level = 6;
     if (e == hipSuccess)
-        e = stage(p, VV10_STAGE_POTENTIAL, [&] { return vv10::launch_potential(p, nullptr, nullptr, nullptr); });
+        e = stage(p, VV10_STAGE_POTENTIAL, [&] {
+            return vv10::launch_potential(p, out->energy, out->f_rho, out->f_gamma);
+        });
     if (e == hipSuccess && out->w_coef)
         e = hipMemcpyAsync(out->w_coef, p->F + (size_t)vv10::F_F0 * p->npad,
                            (size_t)p->n * sizeof(double), hipMemcpyDeviceToDevice, p->stream);
@@ -598,7 +600,8 @@ vv10_status vv10_hessian_terms(vv10_plan *p, int32_t n_pert, const double *rho_x
                                double *resp_rho, double *resp_gamma) {
     if (!p) return VV10_E_STATE;
     if (!hess) return VV10_E_ARG;
-    const vv10_nuclear_outputs out = {hess, grad, resp_rho, resp_gamma, nullptr, nullptr, nullptr};
+    const vv10_nuclear_outputs out = {hess, grad, resp_rho, resp_gamma, nullptr, nullptr,
+                                      nullptr, nullptr, nullptr, nullptr};
     return vv10_nuclear_terms(p, n_pert, rho_x, grad_rho_x, nullptr, &out);
 }
 

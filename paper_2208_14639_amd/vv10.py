@@ -42,7 +42,8 @@ class vv10_tiles(ctypes.Structure):
 
 class vv10_nuclear_outputs(ctypes.Structure):
     _fields_ = [(k, ctypes.c_void_p) for k in
-                ("hess", "grad", "resp_rho", "resp_gamma", "fock_rho", "fock_gamma", "w_coef")]
+                ("hess", "grad", "resp_rho", "resp_gamma", "fock_rho", "fock_gamma", "w_coef",
+                 "energy", "f_rho", "f_gamma")]
 
 
 class VV10Error(RuntimeError):
@@ -184,9 +185,9 @@ def vv10_hessian_terms(plan: int, n_pert: int, rho_x, grad_rho_x, hess, grad=Non
 
 def vv10_nuclear_terms(plan: int, n_pert: int, rho_x, grad_rho_x, hess=None, grad=None,
                        resp_rho=None, resp_gamma=None, fock_rho=None, fock_gamma=None,
-                       w_x=None, w_coef=None) -> None:
+                       w_x=None, w_coef=None, energy=None, f_rho=None, f_gamma=None) -> None:
     out = vv10_nuclear_outputs(*(_ptr(t) for t in (hess, grad, resp_rho, resp_gamma, fock_rho,
-                                                    fock_gamma, w_coef)))
+                                                    fock_gamma, w_coef, energy, f_rho, f_gamma)))
     st = load().vv10_nuclear_terms(plan, n_pert, _ptr(rho_x), _ptr(grad_rho_x), _ptr(w_x),
                                    ctypes.byref(out))
     if st != VV10_OK:
@@ -386,7 +387,7 @@ class Plan:
         return a if isinstance(a, t.Tensor) and a.is_cuda else self._dev(a)
 
     def nuclear_terms(self, rho_x, grad_rho_x, hess=True, grad=False, resp=False, fock=False,
-                      w_x=None, w_coef=False):
+                      w_x=None, w_coef=False, energy=False, potential=False):
         """Any subset of the nuclear-perturbation outputs of one pass; w_x
         ([3 n_atom, N], or None) are the weights' nuclear derivatives."""
         t = self.torch
@@ -396,7 +397,8 @@ class Plan:
         out = {"hess": mk(hess, (P, P)), "grad": mk(grad, P),
                "resp_rho": mk(resp, (P, self.n)), "resp_gamma": mk(resp, (P, self.n)),
                "fock_rho": mk(fock, (P, self.n)), "fock_gamma": mk(fock, (P, self.n)),
-               "w_coef": mk(w_coef, self.n)}
+               "w_coef": mk(w_coef, self.n), "energy": mk(energy, 1),
+               "f_rho": mk(potential, self.n), "f_gamma": mk(potential, self.n)}
         vv10_nuclear_terms(self.handle, P, rx, gx, w_x=wx, **out)
         return {k: v for k, v in out.items() if v is not None}
 

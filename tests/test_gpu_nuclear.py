@@ -91,3 +91,35 @@ def test_nuclear_terms_errors(torch):
         with pytest.raises(vv10.VV10Error) as ei:
             vv10.vv10_hessian_terms(pl.handle, 3 * p.n_atom, rx, gx, None)
         assert ei.value.status == vv10.VV10_E_ARG
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("case", CASES)
+def test_energy_potential_from_nuclear_terms(torch, case, prec):
+    """One vv10_nuclear_terms call returns the energy and potential from the
+    integrals its grid pass forms: against the oracle to the stated bounds,
+    and against vv10_energy_potential on a fresh plan (same sums, different
+    partial boundaries)."""
+    from paper_2208_14639_amd import vv10
+    from gpu_util import oracle_energy, oracle_hessian, relerr
+    p = problem(*case)
+    with vv10.Plan(p, prec=prec) as pl:
+        out = pl.nuclear_terms(p.rho_x, p.grad_rho_x, hess=True, grad=True, energy=True,
+                               potential=True)
+        torch.cuda.synchronize()
+        got = {k: v.cpu().numpy() for k, v in out.items()}
+    with vv10.Plan(p, prec=prec) as pl:
+        e2, fr2, fg2 = (x.cpu().numpy() for x in pl.energy_potential())
+    e0, fr0, fg0 = oracle_energy(*case)
+    H0, G0, _ = oracle_hessian(*case)
+    errs = dict(energy=relerr(got["energy"][0], e0), f_rho=normwise(got["f_rho"], fr0),
+                f_gamma=normwise(got["f_gamma"], fg0), hess=normwise(got["hess"], H0),
+                grad=normwise(got["grad"], G0), vs_energy_call=relerr(got["energy"][0], e2[0]))
+    _say("   ", prec, case, errs)
+    if prec == "fp64":
+        assert max(v for k, v in errs.items() if k != "vs_energy_call") < TOL64
+        assert errs["vs_energy_call"] < 1e-13
+    else:
+        assert errs["energy"] <= 1e-6 and errs["f_rho"] <= 1e-5 and errs["f_gamma"] <= 1e-5
+        assert errs["vs_energy_call"] < 1e-6
+        assert np.max(np.abs(got["hess"] - H0)) <= 1e-5
