@@ -4,7 +4,8 @@ import numpy as np
 import pytest
 
 from paper_2208_14639_amd import inputs
-from paper_2208_14639_amd.serve import FakeExecutor, Request, Server, percentile
+from fake_executor import FakeExecutor
+from paper_2208_14639_amd.serve import Request, Server, percentile
 
 
 def mols(n, seed=3):
