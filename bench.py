@@ -394,7 +394,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="water_hexamer",
                     choices=["water_dimer", "water_hexamer", "water_20mer", "batch64", "served",
-                             "trial_response", "gradient", "becke_hexamer"],
+                             "trial_response", "gradient", "becke_hexamer", "becke_20mer"],
                     help="batch64: 64 random clusters of 1-30 waters, 1500 points/atom, "
                          "one graph launch per step")
     ap.add_argument("--prec", default="bf16x3", choices=["fp64", "fp32", "bf16x3"],
@@ -439,9 +439,10 @@ def main():
         return bench_gradient(args, torch, np, inputs, vv10)
 
     from paper_2208_14639_amd import autotune
-    weighted = args.workload == "becke_hexamer"
+    weighted = args.workload.startswith("becke_")
     if weighted:
-        p = inputs.make_workload("water_hexamer", weights="becke", radial_order=args.shells)
+        base = {"becke_hexamer": "water_hexamer", "becke_20mer": "water_20mer"}[args.workload]
+        p = inputs.make_workload(base, weights="becke", radial_order=args.shells)
     else:
         p = inputs.make_workload(args.workload, radial_order=args.shells)
     if args.screen > 0:
@@ -523,7 +524,7 @@ def main():
     mfma_key = {"fp64": "mfma_f64", "fp32": "mfma_f32", "bf16x3": "mfma_bf16"}[args.prec]
     achieved = FLOPS_PER_PAIR_PERT * pair_pert / t_con / 1e12
     # the weighted workload runs the same main contraction launch on the same grid
-    traffic = measured_traffic("contract", "water_hexamer" if weighted else args.workload, args.prec)
+    traffic = measured_traffic("contract", base if weighted else args.workload, args.prec)
     roofline = dict(bound="mfma", kernel=f"k_contract_{args.prec}", achieved=achieved,
                     peak=PEAKS_TFLOPS[mfma_key], unit="TFLOP/s",
                     frac=achieved / PEAKS_TFLOPS[mfma_key], traffic=traffic)

@@ -241,7 +241,7 @@ def _distance_jet(d: np.ndarray, sel: np.ndarray, order: int) -> _Jet:
 
 def _becke_step(mu: np.ndarray):
     """s(mu) = (1 - f(f(f(mu))))/2 with f(x) = 3x/2 - x^3/2, and s', s''."""
-    f = lambda x: 1.5 * x - 0.5 * x ** 3
+    f = lambda x: x * (1.5 - 0.5 * x * x)
     fp = lambda x: 1.5 - 1.5 * x * x
     fpp = lambda x: -3.0 * x
     x1 = f(mu)
@@ -252,38 +252,53 @@ def _becke_step(mu: np.ndarray):
     return 0.5 * (1.0 - x3), -0.5 * d1, -0.5 * d2
 
 
-def _becke_cells_order1(mol: Molecule, atom_of: np.ndarray, pts: np.ndarray):
-    """Cell functions P_C (values [M][N]) with first derivatives ([M][N, M, 3]),
-    exploiting that mu_CD depends only on R_{O(i)}, R_C and R_D."""
+def _becke_order1(mol: Molecule, atom_of: np.ndarray, pts: np.ndarray):
+    """Becke partition P_O(i)(r_i) / sum_C P_C(r_i) of every point and its first
+    nuclear derivatives, [N] and [M, 3, N].  Each cell function's derivative
+    comes from its logarithmic derivative d ln P_C = sum_D (s'/s)(mu_CD) d mu_CD,
+    where mu_CD depends only on R_{O(i)}, R_C and R_D (three atoms per pair).
+    A factor s that rounds to zero has s' = 0 as well (s is flat at mu = 1)
+    and makes P_C and its derivative zero."""
     M = mol.n_atom
     N = atom_of.shape[0]
-    ar = np.arange(N)
-    d = [pts - mol.R[C] for C in range(M)]
-    u = [np.sqrt(np.einsum("ka,ka->k", x, x)) for x in d]
-    e = [d[C] / u[C][:, None] for C in range(M)]
-    vals, grads = [], []
+    seg = np.searchsorted(atom_of, np.arange(M + 1))
+    d = [(pts - mol.R[C]).T.copy() for C in range(M)]                # [3, N]
+    u = [np.sqrt(np.einsum("an,an->n", x, x)) for x in d]
+    e = [d[C] / u[C] for C in range(M)]
+    Zv = np.zeros(N)
+    Zg = np.zeros((M, 3, N))
+    ownv = np.zeros(N)
+    owng = np.zeros((M, 3, N))
     for C in range(M):
         v = np.ones(N)
-        g = np.zeros((N, M, 3))
+        L = np.zeros((M, 3, N))
+        Lown = np.zeros((3, N))          # the owner atom's slot, added per segment below
         for D in range(M):
             if D == C:
                 continue
             dd = mol.R[C] - mol.R[D]
             dist = math.sqrt(float(dd @ dd))
-            nCD = dd / dist
+            nCD = (dd / dist)[:, None]
             mu = (u[C] - u[D]) / dist
             s, sp, _ = _becke_step(mu)
-            c = (v * sp / dist)[:, None]
-            g *= s[:, None, None]
+            c = np.divide(sp, s, out=np.zeros(N), where=s > 0.0) / dist
             # d mu / dR_A = (sel_C[A] e_C - sel_D[A] e_D)/|R_CD| - mu (delta_AC - delta_AD) n_CD/|R_CD|
             # with sel_X[A] = delta_{A,O(i)} - delta_{A,X}
-            g[ar, atom_of, :] += c * (e[C] - e[D])
-            g[:, C, :] -= c * (e[C] + mu[:, None] * nCD)
-            g[:, D, :] += c * (e[D] + mu[:, None] * nCD)
+            Lown += c * (e[C] - e[D])
+            t = c * mu * nCD
+            L[C] -= c * e[C] + t
+            L[D] += c * e[D] + t
             v = v * s
-        vals.append(v)
-        grads.append(g)
-    return vals, grads
+        for A in range(M):
+            L[A, :, seg[A]:seg[A + 1]] += Lown[:, seg[A]:seg[A + 1]]
+        g = v * L
+        Zv += v
+        Zg += g
+        ownv[seg[C]:seg[C + 1]] = v[seg[C]:seg[C + 1]]
+        owng[:, :, seg[C]:seg[C + 1]] = g[:, :, seg[C]:seg[C + 1]]
+    part = ownv / Zv
+    dpart = (owng - part * Zg) / Zv
+    return part, dpart
 
 
 def becke_weights(mol: Molecule, atom_of: np.ndarray, offsets: np.ndarray,
@@ -298,18 +313,8 @@ def becke_weights(mol: Molecule, atom_of: np.ndarray, offsets: np.ndarray,
     counts = np.bincount(atom_of, minlength=M)
     w_rad = 4.0 * math.pi * radii ** 3 * math.log(R_MAX / R_MIN) / counts[atom_of]
     if order == 1 and not jets:
-        vals, grads = _becke_cells_order1(mol, atom_of, pts)
-        cell = [_Jet(vals[C], grads[C].reshape(N, 3 * M)) for C in range(M)]
-        Z = cell[0]
-        for C in range(1, M):
-            Z = Z + cell[C]
-        own = _Jet(np.empty(N), np.empty((N, 3 * M)))
-        for C in range(M):
-            idx = np.nonzero(atom_of == C)[0]
-            own.v[idx] = vals[C][idx]
-            own.g[idx] = cell[C].g[idx]
-        wj = own * Z.recip()
-        return w_rad * wj.v, np.ascontiguousarray((w_rad[:, None] * wj.g).T), None
+        part, dpart = _becke_order1(mol, atom_of, pts)
+        return w_rad * part, np.ascontiguousarray((w_rad * dpart).reshape(3 * M, N)), None
     owner = np.zeros((N, M))
     owner[np.arange(N), atom_of] = 1.0
     u = []
