@@ -189,3 +189,23 @@ def test_hexamer_becke_full_size(torch):
         wg = rho * og * Ww
         assert np.max(np.abs(dr[:, i0:i1] - wr)) <= FOCK_NORM["bf16x3"] * sr
         assert np.max(np.abs(dg[:, i0:i1] - wg)) <= FOCK_NORM["bf16x3"] * sg
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_weighted_several_column_groups(torch, prec):
+    """15 waters (P = 135) with Becke weights: the weight contraction runs in
+    five column groups of two blocks (FP64) or three groups of three
+    (split-BF16); outputs against the oracle."""
+    case = (15, 30, 95)
+    p = becke(*case)
+    H0, G0, vr0, vg0, coef0 = oracle_weighted(*case)
+    r = _run(torch, p, prec, p.w_x)
+    errs = dict(hess=normwise(r["hess"], H0), hess_abs=float(np.max(np.abs(r["hess"] - H0))),
+                grad=normwise(r["grad"], G0), fock_rho=normwise(r["fock_rho"], vr0),
+                fock_gamma=normwise(r["fock_gamma"], vg0))
+    _say("   ", prec, "P = 135", errs)
+    if prec == "fp64":
+        assert max(v for k, v in errs.items() if k != "hess_abs") < TOL64
+    else:
+        assert errs["hess_abs"] <= H_ABS and errs["grad"] <= V_NORM
+        assert errs["fock_rho"] <= FOCK_NORM[prec] and errs["fock_gamma"] <= FOCK_NORM[prec]
