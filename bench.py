@@ -51,9 +51,10 @@ def source_sha(rels):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_key, workload, prec):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when the kernel source changed since the counters were taken."""
+def counter_record(kernel_key, workload, prec):
+    """The committed rocprofv3 counter summary of a kernel (HBM bytes per
+    launch, VALU-issue and MFMA busy fractions), or None when the kernel
+    source changed since the counters were taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f).get(f"{kernel_key}:{workload}:{prec}")
@@ -61,7 +62,12 @@ def measured_traffic(kernel_key, workload, prec):
         return None
     if not rec or rec.get("source_sha") != source_sha(rec["sources"]):
         return None
-    return rec["bytes_per_launch"]
+    return rec
+
+
+def measured_traffic(kernel_key, workload, prec):
+    rec = counter_record(kernel_key, workload, prec)
+    return None if rec is None else rec["bytes_per_launch"]
 
 
 def row_sample(fn, n, target_s=10.0):
@@ -528,6 +534,11 @@ def main():
     roofline = dict(bound="mfma", kernel=f"k_contract_{args.prec}", achieved=achieved,
                     peak=PEAKS_TFLOPS[mfma_key], unit="TFLOP/s",
                     frac=achieved / PEAKS_TFLOPS[mfma_key], traffic=traffic)
+    rec = counter_record("contract", base if weighted else args.workload, args.prec)
+    if rec is not None and "valu_issue_busy" in rec:
+        # what limits the kernel, from the committed counter summary of the same launch
+        roofline["issue"] = {"valu_issue_busy": rec["valu_issue_busy"], "mfma_busy": rec["mfma_busy"],
+                             "source": rec["profile"]}
     # the pair integrals come from the grid pass unless --separate-energy
     pair_ms = stage_ms["pair"] if stage_ms["pair"] > 0 else stage_ms["grid"]
 
