@@ -632,6 +632,201 @@ __global__ __launch_bounds__(256, 2) void k_contract_persistent(const BatchMol *
 
 __global__ void k_zero_counter(int32_t *c) { *c = 0; }
 
+// ---------------------------------------------------------------------------
+// Fused split-BF16 contraction for weights that move with the nuclei (one
+// column group of at most four blocks): the pair geometry of each (i, j) is
+// formed once for the main 2 x 2 kernel and for the three weight rows
+// Y_pv, Y_qv, Y_vv of the weight contraction (weights.hip).  A stage is a
+// 32-point j block: the main contraction takes it as two 16-point
+// sub-blocks, the weight contraction as one K of 32 whose order follows the
+// same lanes' pairs, k = 8 g + e for the point 4 g + e (e < 4) or
+// 16 + 4 g + e - 4 (e >= 4) of the block, which is the order in which the
+// weight packing stores v.
+// ---------------------------------------------------------------------------
+// The four main values and the three weight values (r - c_i A, -R^2 A, r)
+// of pair (i, j), all divided by -3/2; the main values are those of pair_K.
+__device__ __forceinline__ void pair_KW(const float4 a0, const float4 a1, const float4 b0,
+                                        const float4 b1, float *k) {
+    const float dx = a0.x - b0.x, dy = a0.y - b0.y, dz = a0.z - b0.z;
+    const float R2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+    const float gg = __builtin_fmaf(a0.w, R2, a1.x);
+    const float gp = __builtin_fmaf(b0.w, R2, b1.x);
+    const float s = gg + gp, t = gg * gp;
+    const float r = rcp32(t * s);
+    const float sr = s * r;
+    const float is = t * r;
+    const float A = r * __builtin_fmaf(gp, sr, is);
+    const float Ap = r * __builtin_fmaf(gg, sr, is);
+    const float Q = (r + r) * __builtin_fmaf(is, is, sr);
+    const float ci = a1.z, cj = b1.z;
+    const float t1 = __builtin_fmaf(ci, Q, -Ap);
+    const float t2 = __builtin_fmaf(cj, Q, -A);
+    const float base = __builtin_fmaf(-ci, A, r);
+    k[0] = __builtin_fmaf(cj, t1, base);    // kpp
+    k[1] = R2 * t1;                         // kpq
+    k[2] = R2 * t2;                         // kqp
+    k[3] = (R2 * R2) * Q;                   // kqq
+    k[4] = base;                            // kpv
+    k[5] = -R2 * A;                         // kqv
+    k[6] = r;                               // kvv
+}
+
+template <int NCB>
+constexpr int smem_bf16x3_w() {
+    return 2 * 6 * NCB * 16 * 4 * (int)sizeof(bf16x8) + 2 * 64 * (int)sizeof(float4);
+}
+
+template <int NCB>
+__global__ __launch_bounds__(256, 2) void k_contract_bf16x3_w(
+    int64_t npad, int64_t jlen, int32_t Pp, const float4 *__restrict__ P0,
+    const float4 *__restrict__ P1, const bf16x8 *__restrict__ Xhi, const bf16x8 *__restrict__ Xlo,
+    const bf16x8 *__restrict__ Vhi, const bf16x8 *__restrict__ Vlo, float *__restrict__ Yout,
+    float *__restrict__ Ywout) {
+    constexpr int NC = NCB * 16;
+    constexpr int UNITS = NC * 4;           // 8-bf16 units of one array and block
+    constexpr int NARR = 6;                 // main hi (2 sub-blocks), main lo (2), weight hi, lo
+    constexpr int TOT = NARR * UNITS;
+    constexpr int PER = (TOT + 255) / 256;
+    __shared__ __attribute__((aligned(16))) char smem[smem_bf16x3_w<NCB>()];
+    bf16x8 *sX = reinterpret_cast<bf16x8 *>(smem);                 // [2][NARR][UNITS]
+    float4 *sP = reinterpret_cast<float4 *>(sX + 2 * TOT);         // [2][P0, P1][32]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m = lane & 15, g = lane >> 4;
+    const int64_t ibase = (int64_t)blockIdx.x * 64 + wave * 16;
+    const int64_t jbeg = (int64_t)blockIdx.z * jlen;
+    const int64_t jend = min(npad, jbeg + jlen);
+    const float4 a0 = P0[ibase + m], a1 = P1[ibase + m];
+    v4f accp[NCB], accq[NCB], awp[NCB], awq[NCB], awv[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+        accp[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
+        accq[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
+        awp[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
+        awq[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
+        awv[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
+    }
+    bf16x8 rx[PER];
+    float4 rp = {0.f, 0.f, 0.f, 0.f};
+    // unit e = a UNITS + u of a block: a = 0, 1 main hi of sub-block 0, 1;
+    // 2, 3 main lo; 4, 5 weight hi, lo
+    auto load = [&](int64_t j0) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = tid + 256 * k;
+            if (e < TOT) {
+                const int a = e / UNITS, u = e - a * UNITS;
+                const bf16x8 *src = a < 4 ? (a < 2 ? Xhi : Xlo) + ((j0 / 16 + (a & 1)) * Pp) * 4
+                                          : (a == 4 ? Vhi : Vlo) + ((j0 / 32) * Pp) * 4;
+                rx[k] = src[u];
+            }
+        }
+        if (tid < 64) rp = (tid < 32 ? P0 : P1)[j0 + (tid & 31)];
+    };
+    auto store = [&](int b) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = tid + 256 * k;
+            if (e < TOT) sX[b * TOT + e] = rx[k];
+        }
+        if (tid < 64) sP[b * 64 + tid] = rp;
+    };
+    load(jbeg);
+    store(0);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t j0 = jbeg; j0 < jend; j0 += 32) {
+        const bool more = j0 + 32 < jend;
+        if (more) load(j0 + 32);
+        const float4 *q0 = sP + buf * 64, *q1 = q0 + 32;
+        uint32_t mh[2][4], ml[2][4], nh[2][4], nl[2][4];
+        uint32_t vph[4], vpl[4], vqh[4], vql[4], vvh[4], vvl[4];
+#pragma unroll
+        for (int e = 0; e < 8; e += 2) {
+            const int sb = e >> 2, jj = e & 3;
+            const int jl = 16 * sb + 4 * g + jj;
+            float k0[7], k1[7];
+            pair_KW(a0, a1, q0[jl], q1[jl], k0);
+            pair_KW(a0, a1, q0[jl + 1], q1[jl + 1], k1);
+            split2(k0[0], k0[1], mh[sb][jj], ml[sb][jj]);
+            split2(k0[2], k0[3], nh[sb][jj], nl[sb][jj]);
+            split2(k1[0], k1[1], mh[sb][jj + 1], ml[sb][jj + 1]);
+            split2(k1[2], k1[3], nh[sb][jj + 1], nl[sb][jj + 1]);
+            split2(k0[4], k1[4], vph[e >> 1], vpl[e >> 1]);
+            split2(k0[5], k1[5], vqh[e >> 1], vql[e >> 1]);
+            split2(k0[6], k1[6], vvh[e >> 1], vvl[e >> 1]);
+        }
+        Aops A[2];
+#pragma unroll
+        for (int sb = 0; sb < 2; ++sb) {
+            A[sb].ph = __builtin_bit_cast(bf16x8, (uint4){mh[sb][0], mh[sb][1], mh[sb][2], mh[sb][3]});
+            A[sb].pl = __builtin_bit_cast(bf16x8, (uint4){ml[sb][0], ml[sb][1], ml[sb][2], ml[sb][3]});
+            A[sb].qh = __builtin_bit_cast(bf16x8, (uint4){nh[sb][0], nh[sb][1], nh[sb][2], nh[sb][3]});
+            A[sb].ql = __builtin_bit_cast(bf16x8, (uint4){nl[sb][0], nl[sb][1], nl[sb][2], nl[sb][3]});
+        }
+        const bf16x8 wph = __builtin_bit_cast(bf16x8, (uint4){vph[0], vph[1], vph[2], vph[3]});
+        const bf16x8 wpl = __builtin_bit_cast(bf16x8, (uint4){vpl[0], vpl[1], vpl[2], vpl[3]});
+        const bf16x8 wqh = __builtin_bit_cast(bf16x8, (uint4){vqh[0], vqh[1], vqh[2], vqh[3]});
+        const bf16x8 wql = __builtin_bit_cast(bf16x8, (uint4){vql[0], vql[1], vql[2], vql[3]});
+        const bf16x8 wvh = __builtin_bit_cast(bf16x8, (uint4){vvh[0], vvh[1], vvh[2], vvh[3]});
+        const bf16x8 wvl = __builtin_bit_cast(bf16x8, (uint4){vvl[0], vvl[1], vvl[2], vvl[3]});
+        const bf16x8 *xb = sX + buf * TOT + m * 4 + g;
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+#pragma unroll
+            for (int sb = 0; sb < 2; ++sb) {
+                const bf16x8 bh = xb[sb * UNITS + cb * 64], bl = xb[(2 + sb) * UNITS + cb * 64];
+                accp[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[sb].ph, bh, accp[cb], 0, 0, 0);
+                accq[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[sb].qh, bh, accq[cb], 0, 0, 0);
+                accp[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[sb].pl, bh, accp[cb], 0, 0, 0);
+                accq[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[sb].ql, bh, accq[cb], 0, 0, 0);
+                accp[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[sb].ph, bl, accp[cb], 0, 0, 0);
+                accq[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[sb].qh, bl, accq[cb], 0, 0, 0);
+            }
+            const bf16x8 vh = xb[4 * UNITS + cb * 64], vl = xb[5 * UNITS + cb * 64];
+            awp[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wph, vh, awp[cb], 0, 0, 0);
+            awq[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wqh, vh, awq[cb], 0, 0, 0);
+            awv[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wvh, vh, awv[cb], 0, 0, 0);
+            awp[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wpl, vh, awp[cb], 0, 0, 0);
+            awq[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wql, vh, awq[cb], 0, 0, 0);
+            awv[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wvl, vh, awv[cb], 0, 0, 0);
+            awp[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wph, vl, awp[cb], 0, 0, 0);
+            awq[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wqh, vl, awq[cb], 0, 0, 0);
+            awv[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wvh, vl, awv[cb], 0, 0, 0);
+        }
+        if (more) store(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+    // D layout: item r of lane l holds row 4 (l/16) + r, column l%16
+    float *Yb = Yout + (int64_t)blockIdx.z * npad * 2 * Pp;
+    float *Yw = Ywout + (int64_t)blockIdx.z * npad * 3 * Pp;
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t row = ibase + 4 * g + r;
+            const int64_t col = cb * 16 + m;
+            Yb[(row * 2 + 0) * Pp + col] = accp[cb][r];
+            Yb[(row * 2 + 1) * Pp + col] = accq[cb][r];
+            Yw[(row * 3 + 0) * Pp + col] = awp[cb][r];
+            Yw[(row * 3 + 1) * Pp + col] = awq[cb][r];
+            Yw[(row * 3 + 2) * Pp + col] = awv[cb][r];
+        }
+}
+
+template <int NCB>
+hipError_t run_weighted(vv10_plan *p, const Workspace &ws, const WeightWork &ww) {
+    dim3 grid((unsigned)(p->npad / 64), 1u, (unsigned)ws.jsplit);
+    const bf16x8 *xh = static_cast<const bf16x8 *>(ws.X);
+    const bf16x8 *xl = xh + (size_t)p->npad * ws.Pp * 2 / 8;
+    const bf16x8 *vh = static_cast<const bf16x8 *>(ww.Xv);
+    const bf16x8 *vl = vh + (size_t)p->npad * ws.Pp / 8;
+    k_contract_bf16x3_w<NCB><<<grid, 256, 0, p->stream>>>(
+        p->npad, ws.jlen, ws.Pp, p->P0f, p->P1f, xh, xl, vh, vl, static_cast<float *>(ws.Ypart),
+        static_cast<float *>(ww.Ypart));
+    return hipGetLastError();
+}
+
 }  // namespace
 
 int contract_blocks_per_cu(vv10_precision prec, int ncb) {
@@ -641,6 +836,21 @@ int contract_blocks_per_cu(vv10_precision prec, int ncb) {
 hipError_t launch_contract(vv10_plan *p, const Workspace &ws, bool screen) {
     if (ws.ncb < 1 || ws.ncb > max_ncb(p->prec)) return hipErrorInvalidValue;
     return dispatch_ncb(ws.ncb, [&](auto c) { return run<decltype(c)::value>(p, ws, screen); });
+}
+
+bool fused_weighted_contract(const vv10_plan *p, const Workspace &ws) {
+    return p->prec == VV10_MIXED_BF16X3 && ws.ngroups == 1 && ws.ncb <= 4;
+}
+
+hipError_t launch_contract_weighted(vv10_plan *p, const Workspace &ws, const WeightWork &ww) {
+    if (!fused_weighted_contract(p, ws)) return hipErrorInvalidValue;
+    switch (ws.ncb) {
+        case 1: return run_weighted<1>(p, ws, ww);
+        case 2: return run_weighted<2>(p, ws, ww);
+        case 3: return run_weighted<3>(p, ws, ww);
+        case 4: return run_weighted<4>(p, ws, ww);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace vv10

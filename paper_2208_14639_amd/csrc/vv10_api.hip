@@ -574,12 +574,22 @@ vv10_status vv10_nuclear_terms(vv10_plan *p, int32_t n_pert, const double *rho_x
                            (size_t)p->n * sizeof(double), hipMemcpyDeviceToDevice, p->stream);
     if (e == hipSuccess)
         e = stage(p, VV10_STAGE_PERT_PREP, [&] { return vv10::launch_pert_prep(p, p->ws, rho_x, grad_rho_x, screen); });
-    if (e == hipSuccess) e = stage(p, VV10_STAGE_CONTRACT, [&] { return vv10::launch_contract(p, p->ws, screen); });
+    // weighted split-BF16 with one column group of at most four blocks: one
+    // fused contraction for the main and the weight rows (timed as the
+    // contraction; the weight stage is then the packing alone)
+    const bool fused = weighted && !screen && vv10::fused_weighted_contract(p, p->ws);
+    if (e == hipSuccess && fused)
+        e = stage(p, VV10_STAGE_WEIGHTS, [&] { return vv10::launch_weight_prep(p, w_x); });
+    if (e == hipSuccess)
+        e = stage(p, VV10_STAGE_CONTRACT, [&] {
+            return fused ? vv10::launch_contract_weighted(p, p->ws, p->ww)
+                         : vv10::launch_contract(p, p->ws, screen);
+        });
     if (e == hipSuccess) {
         p->ws.screened = screen;
         p->rws.screened = false;
     }
-    if (e == hipSuccess && weighted)
+    if (e == hipSuccess && weighted && !fused)
         e = stage(p, VV10_STAGE_WEIGHTS, [&] {
             hipError_t r = vv10::launch_weight_prep(p, w_x);
             if (r == hipSuccess) r = vv10::launch_weight_contract(p);

@@ -202,6 +202,10 @@ void weight_shape(int32_t Pp, vv10_precision prec, WeightWork &ww);
 hipError_t launch_weight_own(vv10_plan *p, const double *w_x, double *Wown);
 hipError_t launch_weight_prep(vv10_plan *p, const double *w_x);
 hipError_t launch_weight_contract(vv10_plan *p);
+// The fused split-BF16 contraction (main and weight rows in one pass over the
+// pairs) applies when the columns form one group of at most four blocks.
+bool fused_weighted_contract(const vv10_plan *p, const Workspace &ws);
+hipError_t launch_contract_weighted(vv10_plan *p, const Workspace &ws, const WeightWork &ww);
 hipError_t launch_trial_response(vv10_plan *p, double *f_rho_t, double *f_gamma_t);
 // weighted: also the weight-derivative terms (p->ww filled by the weight stages)
 hipError_t launch_assemble(vv10_plan *p, const vv10_nuclear_outputs &out, bool weighted);

@@ -22,9 +22,13 @@
 // Arithmetic modes as in the main contraction:
 //  FP64, FP32: v_mfma_{f64,f32}_16x16x4, one pair per lane per 4 j, three
 //              MFMAs per 16 columns (one per output);
-//  BF16X3:     v_mfma_f32_16x16x32_bf16 with K over 32 consecutive j of the one
-//              channel (each lane forms 8 pairs per block), hi/lo split of both
-//              operands and three products per output.
+//  BF16X3:     v_mfma_f32_16x16x32_bf16 with K over a 32-point j block of the
+//              one channel (each lane forms 8 pairs per block: the points
+//              4 g .. 4 g + 3 of both 16-point halves, g = lane/16), hi/lo split
+//              of both operands and three products per output.  When the
+//              columns form one group of at most four blocks the main
+//              contraction forms these pairs anyway, and the fused kernel of
+//              contract.hip evaluates both from one pair geometry.
 #include "dev_common.h"
 #include "vv10_internal.h"
 
@@ -52,7 +56,10 @@ __global__ __launch_bounds__(256) void k_wown(int64_t n, int32_t n_atom,
 
 // Lw[i][x] = w^x_i (owner slot from Wown, zero for padding) and the packed
 // channel v = sc w^x_i rho_i (sc = 1 in FP64, -3/2 in the mixed modes):
-// FP64/FP32 [npad][Pp]; BF16X3 hi then lo, each [npad/32][Pp][32].
+// FP64/FP32 [npad][Pp]; BF16X3 hi then lo, each [npad/32][Pp][32] with the
+// point o of a 32-point block at K position 8 ((o mod 16)/4) + o mod 4 + 4 (o/16),
+// so that the 8 K values of lane group g are the points 4 g .. 4 g + 3 of
+// both 16-point halves (the pairs the main contraction's lanes form).
 constexpr int TT = 32;
 template <int MODE>
 __global__ __launch_bounds__(256) void k_wprep(int64_t n, int64_t npad, int32_t P, int32_t Pp,
@@ -87,7 +94,8 @@ __global__ __launch_bounds__(256) void k_wprep(int64_t n, int64_t npad, int32_t 
         } else {
             __bf16 *Xh = static_cast<__bf16 *>(Xv);
             __bf16 *Xl = Xh + npad * Pp;
-            const int64_t o = ((i / 32) * Pp + x) * 32 + i % 32;
+            const int oo = (int)(i % 32);
+            const int64_t o = ((i / 32) * Pp + x) * 32 + 8 * ((oo & 15) >> 2) + (oo & 3) + 4 * (oo >> 4);
             const __bf16 h = (__bf16)(float)v;
             Xh[o] = h;
             Xl[o] = (__bf16)(float)(v - (double)(float)h);
@@ -326,16 +334,18 @@ __global__ __launch_bounds__(256, 2) void k_wcontract_bf16x3(int64_t npad, int64
             }
         }
     };
-    // this lane's 8 j of a block: j = blk + 8 g + e
+    // this lane's 8 j of a block (K position 8 g + e): j = blk + 4 g + e for
+    // e < 4 and blk + 16 + 4 g + e - 4 for e >= 4
     float4 n0[8];
     float nk[8];
     const float *P1s = reinterpret_cast<const float *>(P1);
     auto load_pts = [&](int64_t blk) {
-        const int64_t jq = min(blk, npad - 32) + 8 * g;   // clamped: never read past npad
+        const int64_t jq = min(blk, npad - 32) + 4 * g;   // clamped: never read past npad
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            n0[e] = P0[jq + e];
-            nk[e] = P1s[4 * (jq + e)];
+            const int64_t j = jq + (e < 4 ? e : 12 + e);
+            n0[e] = P0[j];
+            nk[e] = P1s[4 * j];
         }
     };
     load_pts(jbeg);

@@ -132,3 +132,22 @@ def test_screening_hexamer_shells_full_size(torch):
     assert np.array_equal(b["hess"], b["hess"].T)
     assert err <= SCREEN_NORM
     assert act < 0.8 * tot
+
+
+def test_screening_with_weight_derivatives(torch):
+    """Screening with Becke weights: the screened main contraction runs beside
+    the separate weight contraction (the fused kernel does not screen); the
+    weighted outputs stay within SCREEN_NORM of the unscreened ones."""
+    from paper_2208_14639_amd import vv10
+    p = inputs.make_problem(4, 120, 33, weights="becke", radial_order=True)
+    res = {}
+    for tau in (0.0, TAU):
+        with vv10.Plan(p, prec="bf16x3", screening=tau) as pl:
+            out = pl.nuclear_terms(p.rho_x, p.grad_rho_x, hess=True, grad=True, fock=True,
+                                   w_x=p.w_x)
+            torch.cuda.synchronize()
+            res[tau] = {k: v.cpu().numpy() for k, v in out.items()}
+    for k in ("hess", "grad", "fock_rho", "fock_gamma"):
+        err = normwise(res[TAU][k], res[0.0][k])
+        _say("    weighted, screened vs unscreened", k, err)
+        assert err <= SCREEN_NORM, (k, err)
