@@ -123,3 +123,27 @@ def test_energy_potential_from_nuclear_terms(torch, case, prec):
         assert errs["energy"] <= 1e-6 and errs["f_rho"] <= 1e-5 and errs["f_gamma"] <= 1e-5
         assert errs["vs_energy_call"] < 1e-6
         assert np.max(np.abs(got["hess"] - H0)) <= 1e-5
+
+
+def test_fused_step_hexamer_as_timed(torch):
+    """The benchmark's step on the hexamer workload (N = 27000, P = 54):
+    split-BF16, tuned tiles, one vv10_nuclear_terms call with energy,
+    potential, Hessian and gradient, against the whole oracle."""
+    from paper_2208_14639_amd import vv10
+    from gpu_util import oracle_energy, oracle_hessian, relerr
+    case = (6, 1500, 1002)
+    p = problem(*case)
+    with vv10.Plan(p, prec="bf16x3", tiles="auto") as pl:
+        out = pl.nuclear_terms(p.rho_x, p.grad_rho_x, hess=True, grad=True, energy=True,
+                               potential=True)
+        torch.cuda.synchronize()
+        got = {k: v.cpu().numpy() for k, v in out.items()}
+    e0, fr0, fg0 = oracle_energy(*case)
+    H0, G0, _ = oracle_hessian(*case)
+    errs = dict(energy=relerr(got["energy"][0], e0), f_rho=normwise(got["f_rho"], fr0),
+                f_gamma=normwise(got["f_gamma"], fg0), grad=normwise(got["grad"], G0),
+                hess_abs=float(np.max(np.abs(got["hess"] - H0))))
+    _say("    hexamer fused step", errs)
+    assert errs["energy"] <= 1e-6 and errs["hess_abs"] <= 1e-5
+    assert max(errs["f_rho"], errs["f_gamma"], errs["grad"]) <= 1e-5
+    assert np.array_equal(got["hess"], got["hess"].T)
