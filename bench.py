@@ -36,6 +36,12 @@ HBM_GBS = 8000.0
 FLOPS_PER_PAIR_PERT = 8          # contraction: 4 FMAs per pair and perturbation
 FLOPS_PER_PAIR_PERT_W = 6        # weight contraction: 3 FMAs per pair and perturbation
 FLOPS_PER_PAIR_INTEGRALS = 38    # E, U, W (26) + A, B, C (12)
+FLOPS_PER_PAIR_EUW = 26          # k_pair, energy call: E, U, W
+# fused grid pass (k_grid with the pair integrals), per pair by atom class:
+# the outer point's own atom (pair geometry 22 + six integral sums 14), an
+# atom B below it (+ grid sums E/U/W^{Bgr} 34), an atom above it (+ D sums 24)
+FLOPS_GRID_OWN, FLOPS_GRID_BELOW, FLOPS_GRID_ABOVE = 36, 70, 94
+FP32_NO_PACKED_TFLOPS = 78.6     # one FP32 FMA per lane and cycle (packed FP32 off)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -68,6 +74,30 @@ def counter_record(kernel_key, workload, prec):
 def measured_traffic(kernel_key, workload, prec):
     rec = counter_record(kernel_key, workload, prec)
     return None if rec is None else rec["bytes_per_launch"]
+
+
+def pair_pass_roofline(p, kernel, ms, prec):
+    """Algorithmic FP32 (FP64) VALU rate of the pair pass against the vector
+    peak; the FP32 peak counts packed FP32 (two FMAs per lane and cycle),
+    which all device code here is built without, so the rate is also given
+    against one FMA per lane and cycle."""
+    import numpy as np
+    cnt = np.bincount(p.atom_of, minlength=p.n_atom).astype(np.float64)
+    n = float(p.n_grid)
+    if kernel == "k_pair":
+        flops = FLOPS_PER_PAIR_EUW * n * n
+    else:
+        own = float(np.sum(cnt * cnt))
+        cross = (n * n - own) / 2.0               # pairs with B above (= below) the outer atom
+        flops = FLOPS_GRID_OWN * own + (FLOPS_GRID_BELOW + FLOPS_GRID_ABOVE) * cross
+    achieved = flops / (ms * 1e-3) / 1e12
+    peak = PEAKS_TFLOPS["valu_f64" if prec == "fp64" else "valu_f32"]
+    out = dict(bound="alu", kernel=kernel, achieved=achieved, peak=peak, unit="TFLOP/s",
+               frac=achieved / peak, flops_per_pair=flops / (n * n))
+    if prec != "fp64":
+        out["peak_no_packed"] = FP32_NO_PACKED_TFLOPS
+        out["frac_no_packed"] = achieved / FP32_NO_PACKED_TFLOPS
+    return out
 
 
 def row_sample(fn, n, target_s=10.0):
@@ -561,7 +591,9 @@ def main():
         "roofline": roofline,
         "stage_ms": stage_ms,
         "pair_pass": {"kernel": "k_pair" if stage_ms["pair"] > 0 else "k_grid (fused)",
-                      "pairs_per_s": float(n) * n / (pair_ms * 1e-3)},
+                      "pairs_per_s": float(n) * n / (pair_ms * 1e-3),
+                      "roofline": pair_pass_roofline(p, "k_pair" if stage_ms["pair"] > 0 else "k_grid",
+                                                     pair_ms, args.prec)},
         "step_calls": "vv10_energy_potential + vv10_hessian_terms" if args.separate_energy
                       else "vv10_nuclear_terms (energy, potential, Hessian, gradient)",
         "footprint_bytes": vv10.vv10_footprint_bytes(n, na, prec),
