@@ -189,17 +189,40 @@ __global__ __launch_bounds__(256) void k_pert_prep(
             X[(i * 2 + 0) * Pp + x] = (float)p;
             X[(i * 2 + 1) * Pp + x] = (float)qv;
         } else {
-            __bf16 *Xh = static_cast<__bf16 *>(Xv);
-            __bf16 *Xl = Xh + npad * 2 * Pp;
-            const int64_t o = ((i / 16) * Pp + x) * 32 + 2 * (i % 16);
-            const __bf16 ph = (__bf16)(float)p, qh = (__bf16)(float)qv;
-            Xh[o] = ph;
-            Xh[o + 1] = qh;
-            Xl[o] = (__bf16)(float)(p - (double)(float)ph);
-            Xl[o + 1] = (__bf16)(float)(qv - (double)(float)qh);
+            sr[tx][ty + k] = p;     // this thread's element only: split below
+            sg[tx][ty + k] = qv;
         }
         L[(i * 2 + 0) * Pp + x] = rx;
         L[(i * 2 + 1) * Pp + x] = gxv;
+    }
+    if constexpr (MODE == VV10_MIXED_BF16X3) {
+        // thread -> (16-point block hb, column xo, quarter qq): the four points
+        // i0 + 16 hb + 4 qq + e; their (p, q) hi and lo words are 16 B each,
+        // and four adjacent threads write one column's 64 B run of a block.
+        __syncthreads();
+        const int qq = threadIdx.x & 3, xo = (threadIdx.x >> 2) & (TT - 1), hb = threadIdx.x >> 7;
+        const int x = x0 + xo;
+        const int io = 16 * hb + 4 * qq;
+        if (x < Pp && i0 + io < npad) {
+            uint32_t hw[4], lw[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const double pv = sr[xo][io + e], qv = sg[xo][io + e];
+                const __bf16 ph = (__bf16)(float)pv, qh = (__bf16)(float)qv;
+                const __bf16 pl = (__bf16)(float)(pv - (double)(float)ph);
+                const __bf16 ql = (__bf16)(float)(qv - (double)(float)qh);
+                hw[e] = (uint32_t)__builtin_bit_cast(uint16_t, ph) |
+                        ((uint32_t)__builtin_bit_cast(uint16_t, qh) << 16);
+                lw[e] = (uint32_t)__builtin_bit_cast(uint16_t, pl) |
+                        ((uint32_t)__builtin_bit_cast(uint16_t, ql) << 16);
+            }
+            // element offset ((i / 16) Pp + x) 32 + 2 (i mod 16) of the first point, in 16 B units
+            const int64_t o = ((((i0 + io) / 16) * Pp + x) * 32 + 2 * ((i0 + io) % 16)) / 8;
+            uint4 *Xh = static_cast<uint4 *>(Xv);
+            uint4 *Xl = Xh + npad * 2 * Pp / 8;
+            Xh[o] = (uint4){hw[0], hw[1], hw[2], hw[3]};
+            Xl[o] = (uint4){lw[0], lw[1], lw[2], lw[3]};
+        }
     }
     if (bmax) {   // uniform over the workgroup
         sm[0][ty][tx] = mblk[0];
