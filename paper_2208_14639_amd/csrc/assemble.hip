@@ -322,14 +322,18 @@ __global__ __launch_bounds__(256, 2) void k_gemm(int64_t n, int64_t npad, int64_
 // Hsum[e] = sum_s Hpart[s][e], e < (Pp + 1) Pp, over the S slices of Hpart
 // and then the S2 slices of H2: 64 entries per workgroup, the four waves sum
 // consecutive quarters of the slices, added in wave order.
-__global__ __launch_bounds__(256) void k_hsum(int64_t len, int S, const double *__restrict__ Hpart,
-                                              int S2, const double *__restrict__ H2,
-                                              double *__restrict__ Hsum) {
-    __shared__ double part[4][64];
+// 16 waves per 64 elements, each over a sixteenth of the slices, so that
+// the few workgroups of a small Hessian keep enough loads in flight.
+constexpr int kHsumWaves = 16;
+__global__ __launch_bounds__(64 * kHsumWaves) void k_hsum(int64_t len, int S,
+                                                          const double *__restrict__ Hpart, int S2,
+                                                          const double *__restrict__ H2,
+                                                          double *__restrict__ Hsum) {
+    __shared__ double part[kHsumWaves][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t e = (int64_t)blockIdx.x * 64 + lane;
     const int St = S + S2;
-    const int q = (St + 3) / 4;
+    const int q = (St + kHsumWaves - 1) / kHsumWaves;
     const int sb = min(St, wave * q), se = min(St, sb + q);
     double a = 0.0;
     if (e < len)
@@ -338,7 +342,12 @@ __global__ __launch_bounds__(256) void k_hsum(int64_t len, int S, const double *
             a += s < S ? Hpart[(int64_t)s * len + e] : H2[(int64_t)(s - S) * len + e];
     part[wave][lane] = a;
     __syncthreads();
-    if (wave == 0 && e < len) Hsum[e] = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+    if (wave == 0 && e < len) {
+        double t = part[0][lane];
+#pragma unroll
+        for (int w = 1; w < kHsumWaves; ++w) t += part[w][lane];
+        Hsum[e] = t;
+    }
 }
 
 // DS[A][B][c] = sum over the tiles t of atom A of Dpart[t][B][c] (tile order).
@@ -373,9 +382,14 @@ __device__ __forceinline__ double dsym(int32_t n_atom, const double *__restrict_
 __device__ __forceinline__ double egrgr(int32_t n_atom, const double *__restrict__ DS, int A, int B,
                                         int c) {
     if (A != B) return dsym(n_atom, DS, A, B, c);
+    // every load issued (the C = A entry is read and discarded), so that
+    // they are in flight together
     double v = 0.0;
-    for (int C = 0; C < n_atom; ++C)
-        if (C != A) v -= dsym(n_atom, DS, A, C, c);
+#pragma unroll 8
+    for (int C = 0; C < n_atom; ++C) {
+        const double d = dsym(n_atom, DS, A, C, c);
+        v -= C != A ? d : 0.0;
+    }
     return v;
 }
 
@@ -397,8 +411,11 @@ __global__ __launch_bounds__(256) void k_finish(int32_t n_atom, int32_t P, int32
         const int x = (int)(k - PP);
         const int A = x / 3, a = x % 3;
         double gr = 0.0;
-        for (int B = 0; B < n_atom; ++B)
-            if (B != A) gr -= DS[((int64_t)A * n_atom + B) * 9 + 6 + a];
+#pragma unroll 8
+        for (int B = 0; B < n_atom; ++B) {
+            const double d = DS[((int64_t)A * n_atom + B) * 9 + 6 + a];
+            gr -= B != A ? d : 0.0;
+        }
         grad[x] = Hsum[(int64_t)Pp * Pp + x] + gr;
     }
 }
@@ -526,7 +543,7 @@ hipError_t launch_assemble(vv10_plan *p, const vv10_nuclear_outputs &out, bool w
     }
     {
         const int64_t len = (int64_t)(ws.Pp + 1) * ws.Pp;
-        k_hsum<<<(unsigned)((len + 63) / 64), 256, 0, p->stream>>>(
+        k_hsum<<<(unsigned)((len + 63) / 64), 64 * kHsumWaves, 0, p->stream>>>(
             len, ws.gsplit, ws.Hpart, weighted ? ws.gsplit : 0, ww.Hpart, ws.Hsum);
     }
     const int64_t nds = (int64_t)p->n_atom * p->n_atom * 9;

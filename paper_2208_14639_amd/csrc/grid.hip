@@ -230,6 +230,7 @@ __global__ __launch_bounds__(256) void k_sum_groups(int64_t n, int64_t npad, int
     const int k = (int)(e / n);
     const int64_t i = e - (int64_t)k * n;
     double a = 0.0;
+#pragma unroll 8
     for (int gidx = 0; gidx < G; ++gidx) a += Ipart[((int64_t)gidx * nrows + k) * npad + i];
     I[k * npad + i] = a;
 }

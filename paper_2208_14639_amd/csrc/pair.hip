@@ -105,6 +105,7 @@ __global__ __launch_bounds__(256) void k_sum_integrals(int64_t npad, int nout, i
     const int k = (int)(e / npad);
     const int64_t i = e - (int64_t)k * npad;
     double a = 0.0;
+#pragma unroll 8
     for (int s = 0; s < S; ++s) a += Ipart[((int64_t)s * NI + k) * npad + i];
     I[k * npad + i] = a;
 }

@@ -41,6 +41,7 @@ __global__ __launch_bounds__(256) void k_coord_partials(int64_t n, const double 
 __global__ void k_coord_centroid(int nblk, int64_t n, double *part) {
     if (threadIdx.x < 3) {
         double t = 0.0;
+#pragma unroll 16   // loads in flight together; the sum stays in block order
         for (int b = 0; b < nblk; ++b) t += part[3 * b + threadIdx.x];
         part[3 * nblk + threadIdx.x] = t / (double)n;
     }
