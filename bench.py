@@ -32,7 +32,7 @@ sys.path.insert(0, ROOT)
 PEAKS_TFLOPS = {"mfma_f64": 78.6, "mfma_f32": 157.3, "mfma_bf16": 2500.0, "valu_f32": 157.3,
                 "valu_f64": 78.6}
 HBM_GBS = 8000.0
-# algorithmic work per unit
+# algorithmic work per unit, counted from the formulas (FMA = 2 flops)
 FLOPS_PER_PAIR_PERT = 8          # contraction: 4 FMAs per pair and perturbation
 FLOPS_PER_PAIR_PERT_W = 6        # weight contraction: 3 FMAs per pair and perturbation
 FLOPS_PER_PAIR_INTEGRALS = 38    # E, U, W (26) + A, B, C (12)
@@ -452,7 +452,7 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this engine runs on one GPU; multi-GPU runs are not supported "
-              "(see DESIGN.md for how the path would shard).", file=sys.stderr)
+              "(--gpus 1 measures one GPU's throughput).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
