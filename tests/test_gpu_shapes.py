@@ -1,0 +1,131 @@
+"""Parity across the launch shapes of the Hessian call (Section II.B: E_{G,G},
+E_{G,gr}, E_{gr,gr}) through the C ABI, against the FP64 oracle: every
+16-column block count of one column group (1 to 8 waters, P = 9 to 72),
+two column groups in every precision (22 waters, P = 198), and explicit
+tile overrides (j splits of the contraction, atom groups of the grid pass).
+"""
+import functools
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import normwise, relerr
+from paper_2208_14639_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+E_REL, H_ABS, V_NORM = 1e-6, 1e-5, 1e-5
+# The shape sweeps use 30 points per atom to stay small.  On so sparse a grid
+# each E_i is dominated by a few pair terms, so the FP32 pair arithmetic's
+# rounding (a few units of 2^-24 per term) does not average out, and the
+# energy's two parts cancel (beta sum against the pair sum, a factor of 7 on
+# five waters): the mixed energy error reaches 1.1e-6 there (3e-10 on the
+# 700-point dimer grid).  Its bound on these grids is 3e-6; the other bounds
+# are unchanged.  Likewise the Hessian: its elements are large on such grids
+# (up to 6.5 au on five waters, against 0.03 au on the hexamer's grid) and
+# the split-BF16 products' error (about 2^-17 each) averages over few terms:
+# up to 1.2e-5 of the largest element (2e-6 on the hexamer), 1.8e-5 au.  The
+# sparse sweeps therefore bound the mixed Hessian by 1e-5 au or 5e-5 of its
+# largest element, whichever is larger (an indexing mistake exceeds that by
+# orders of magnitude); the plain 1e-5 au bound applies on the denser grid of
+# the tile test.
+E_REL_SPARSE, H_REL_SPARSE = 3e-6, 5e-5
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+@functools.lru_cache(maxsize=16)
+def case(n_water, n_pa, seed):
+    p = inputs.make_problem(n_water, n_pa, seed)
+    g, gx = oracle.problem_inputs(p)
+    args = (p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b, p.C, p.rho_x, gx)
+    H, _ = oracle.hessian_terms(*args)
+    G = oracle.gradient(*args)
+    e, fr, fg = oracle.energy_potential(p.coords, p.weights, p.rho, g, p.b, p.C)
+    return p, dict(hess=H, grad=G, energy=e, f_rho=fr, f_gamma=fg)
+
+
+def _run(torch, p, prec, tiles=None):
+    from paper_2208_14639_amd import vv10
+    with vv10.Plan(p, prec=prec, tiles=tiles) as pl:
+        out = pl.nuclear_terms(p.rho_x, p.grad_rho_x, hess=True, grad=True, energy=True,
+                               potential=True)
+        used = vv10.vv10_get_tiles(pl.handle)
+        torch.cuda.synchronize()
+        res = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in out.items()}
+    return res, used
+
+
+def _check(res, ref, prec, tag, sparse=False):
+    H = res["hess"]
+    errs = dict(energy=relerr(float(np.asarray(res["energy"]).reshape(-1)[0]), ref["energy"]),
+                f_rho=normwise(res["f_rho"], ref["f_rho"]),
+                f_gamma=normwise(res["f_gamma"], ref["f_gamma"]),
+                grad=normwise(res["grad"], ref["grad"]),
+                hess=normwise(H, ref["hess"]),
+                hess_abs=float(np.max(np.abs(H - ref["hess"]))))
+    _say("   ", tag, prec, errs)
+    assert np.array_equal(H, H.T), tag
+    if prec == "fp64":
+        for k, v in errs.items():
+            if k != "hess_abs":
+                assert v < TOL64, (tag, k, v)
+    else:
+        assert errs["energy"] <= (E_REL_SPARSE if sparse else E_REL), tag
+        if sparse:
+            hmax = float(np.max(np.abs(ref["hess"])))
+            assert errs["hess_abs"] <= max(H_ABS, H_REL_SPARSE * hmax), (tag, hmax)
+        else:
+            assert errs["hess_abs"] <= H_ABS, tag
+        for k in ("f_rho", "f_gamma", "grad"):
+            assert errs[k] <= V_NORM, (tag, k, errs[k])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("n_water", [1, 2, 3, 4, 5, 8])
+def test_column_block_counts(torch, n_water, prec):
+    """One column group of 1 (P = 9) to 5 (P = 72) 16-column blocks, 30
+    points per atom (N = 90 per water, every tile ragged)."""
+    p, ref = case(n_water, 30, 300 + n_water)
+    res, used = _run(torch, p, prec)
+    _check(res, ref, prec, f"{n_water} waters, tiles {used}", sparse=True)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_two_column_groups(torch, prec):
+    """22 waters, 30 points per atom (N = 1980, P = 198, thirteen 16-column
+    blocks): two column groups of seven blocks in every precision (a block
+    count whose X staging leaves some threads idle)."""
+    p, ref = case(22, 30, 322)
+    res, used = _run(torch, p, prec)
+    _check(res, ref, prec, f"22 waters, tiles {used}", sparse=True)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_tile_overrides(torch, prec):
+    """3 waters, 300 points per atom (N = 2700, P = 27): j splits 1, 2, 5
+    and 10 and grid-pass atom groups 1, 2 and 9 all meet the bounds; the
+    mixed results of different shapes agree to well within them."""
+    p, ref = case(3, 300, 333)
+    first = None
+    for js in (1, 2, 5, 10):
+        for bg in (1, 2, 9):
+            res, used = _run(torch, p, prec, tiles=(js, bg))
+            assert used == (js, bg), used
+            _check(res, ref, prec, f"tiles ({js}, {bg})")
+            if first is None:
+                first = res["hess"]
+            else:
+                assert normwise(res["hess"], first) <= (1e-13 if prec == "fp64" else 1e-6)
