@@ -14,8 +14,10 @@ ordered pairs (self pairs included) and P = 3 N_atom.
 
 Prints one JSON line with the metric, a roofline entry for the dominant
 kernel (the perturbation contraction, timed with HIP events recorded by the
-library on the plan's stream) and a CPU baseline (the FP64 oracle on the
-host, rank 0 only).
+library on the plan's stream), the pair pass against the vector peak (the
+step's fused grid pass, and the energy call's own pair kernel timed apart
+from the steps) and a CPU baseline (the FP64 oracle on the host, rank 0
+only).
 """
 from __future__ import annotations
 
@@ -598,6 +600,23 @@ def main():
                       else "vv10_nuclear_terms (energy, potential, Hessian, gradient)",
         "footprint_bytes": vv10.vv10_footprint_bytes(n, na, prec),
     }
+    if not args.separate_energy:
+        # the energy call on its own (its own pair pass, k_pair), timed apart
+        # from the steps: a few untimed-step calls, the pass from HIP events
+        e_ms = []
+        e3, fr3, fg3 = torch.empty_like(energy), torch.empty_like(f_rho), torch.empty_like(f_gamma)
+        for k in range(max(3, min(args.steps, 10))):
+            h = vv10.vv10_prepare(p.b, p.C, n, na, coords, w, atom_of, rho, grad, prec, stream)
+            try:
+                vv10.vv10_set_timing(h, True)
+                vv10.vv10_energy_potential(h, e3, fr3, fg3)
+                e_ms.append(vv10.vv10_stage_times(h)["pair"])
+            finally:
+                vv10.vv10_destroy(h)
+        e_ms = float(np.median(e_ms[1:]))
+        out["energy_call"] = {"kernel": "k_pair", "pair_pass_ms": e_ms,
+                              "pairs_per_s": float(n) * n / (e_ms * 1e-3),
+                              "roofline": pair_pass_roofline(p, "k_pair", e_ms, args.prec)}
     if weighted:
         t_w = stage_ms["weights"] * 1e-3
         aw = FLOPS_PER_PAIR_PERT_W * pair_pert / t_w / 1e12
