@@ -257,30 +257,48 @@ __global__ __launch_bounds__(256, 2) void k_gemm(int64_t n, int64_t npad, int64_
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
-    for (int64_t k0 = rb; k0 < re; k0 += 4) {
-        const int64_t k = k0 + kk;
-        const bool ok = k < re;
-        const int64_t kr = ok ? k : rb;
-        double av[4], bv[4];
+    // four k steps per iteration, their loads issued before their MFMAs, so
+    // that several steps' loads are in flight together (one workgroup per
+    // CU leaves little latency hiding to other waves); the MFMAs of each
+    // accumulator still run in k order
+    for (int64_t k00 = rb; k00 < re; k00 += 16) {
+        // loads without branches, from clamped in-range addresses (finite
+        // values); rows past the slice and columns past Pp are zeroed by a
+        // multiplication, so that no load waits for another
+        double av[4][4], bv[4][4], wa[4], wb[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) av[a] = (ok && a < nlb) ? L[kr * Pp + l0 + 16 * a + ll] : 0.0;
+        for (int st = 0; st < 4; ++st) {
+            const int64_t k = k00 + 4 * st + kk;
+            const bool ok = k < re;
+            const int64_t kr = ok ? k : rb;
+            const double on = ok ? 1.0 : 0.0;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) bv[b] = (ok && b < nmb) ? R[kr * Pp + m0 + 16 * b + ll] : 0.0;
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
+            for (int a = 0; a < 4; ++a)
+                av[st][a] = L[kr * Pp + min(l0 + 16 * a, Pp - 16) + ll] * (a < nlb ? on : 0.0);
 #pragma unroll
             for (int b = 0; b < 4; ++b)
-                acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
-        if (grad) {
-            double wf = 0.0;
+                bv[st][b] = R[kr * Pp + min(m0 + 16 * b, Pp - 16) + ll] * (b < nmb ? on : 0.0);
             if (NCH == 2) {
                 const int64_t pt = kr >> 1;
-                wf = ok ? F[F_W * npad + pt] * F[((kr & 1) ? F_FG : F_FR) * npad + pt] : 0.0;
+                wa[st] = F[F_W * npad + pt] * on;
+                wb[st] = F[((kr & 1) ? F_FG : F_FR) * npad + pt];
             } else {
-                wf = ok ? F[F_F0 * npad + kr] : 0.0;
+                wa[st] = F[F_F0 * npad + kr] * on;
+                wb[st] = 1.0;
             }
+        }
 #pragma unroll
-            for (int a = 0; a < 4; ++a) gacc[a] = __builtin_fma(av[a], wf, gacc[a]);
+        for (int st = 0; st < 4; ++st) {
+            const double wf = NCH == 2 ? wa[st] * wb[st] : wa[st];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[st][a], bv[st][b], acc[a][b],
+                                                                     0, 0, 0);
+            if (grad)
+#pragma unroll
+                for (int a = 0; a < 4; ++a) gacc[a] = __builtin_fma(av[st][a], wf, gacc[a]);
         }
     }
     // gradient: sum the four k lanes of each column
