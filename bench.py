@@ -512,7 +512,7 @@ def main():
     screen_stats = []
 
     def step(prec=prec, hess=hess, gradient=gradient, energy=energy, f_rho=f_rho, f_gamma=f_gamma,
-             tau=args.screen):
+             tau=args.screen, stages=None):
         h = vv10.vv10_prepare(p.b, p.C, n, na, coords, w, atom_of, rho, grad, prec, stream)
         try:
             tiles = tuned[vv10._prec_name(prec)]
@@ -520,7 +520,10 @@ def main():
                 vv10.vv10_set_tiles(h, *tiles)
             if tau > 0:
                 vv10.vv10_set_screening(h, tau)
-            vv10.vv10_set_timing(h, True)
+            if stages is None:
+                vv10.vv10_set_timing(h, True)
+            else:
+                vv10.vv10_set_timing_stages(h, stages)
             if args.separate_energy:
                 vv10.vv10_energy_potential(h, energy, f_rho, f_gamma)
                 if weighted:
@@ -554,7 +557,24 @@ def main():
         t1 = time.perf_counter()
         return (t1 - t0) / args.steps, {k: float(np.mean([s[k] for s in stages])) for k in stages[0]}
 
-    dt, stage_ms = timed(args.prec)
+    # the timed steps bracket only the stages the roofline reads with events
+    # (each timed stage adds two event records to the stream); the other
+    # stages' times come from a few steps after the timed region
+    roof_stages = ["contract", "weights"] if weighted else ["contract"]
+
+    def measure(tag, **kw):
+        dt, roof_ms = timed(tag, stages=roof_stages, **kw)
+        ns = min(args.steps, 5)
+        stage_ms = {}
+        for k in range(ns):
+            st = step(**kw)
+            stage_ms = {kk: stage_ms.get(kk, 0.0) + v / ns for kk, v in st.items()}
+        log(f"{tag}: stage breakdown done")
+        for kk in roof_stages:
+            stage_ms[kk] = roof_ms[kk]
+        return dt, stage_ms
+
+    dt, stage_ms = measure(args.prec)
     pair_pert = float(n) * n * P
     value = pair_pert / dt
 
@@ -642,7 +662,8 @@ def main():
         g2 = torch.empty_like(gradient)
         e2 = torch.empty_like(energy)
         fr2, fg2 = torch.empty_like(f_rho), torch.empty_like(f_gamma)
-        dt2, st2 = timed("unscreened", hess=h2, gradient=g2, energy=e2, f_rho=fr2, f_gamma=fg2, tau=0.0)
+        dt2, st2 = measure("unscreened", hess=h2, gradient=g2, energy=e2, f_rho=fr2, f_gamma=fg2,
+                           tau=0.0)
         Hu = h2.cpu().numpy()
         out["vs_unscreened"] = {"ms_per_step": dt2 * 1e3, "value": pair_pert / dt2,
                                 "speedup": dt2 / dt, "contract_ms": st2["contract"],
@@ -654,8 +675,8 @@ def main():
         g2 = torch.empty_like(gradient)
         e2 = torch.empty_like(energy)
         fr2, fg2 = torch.empty_like(f_rho), torch.empty_like(f_gamma)
-        dt2, st2 = timed(args.compare, prec=vv10.PRECISIONS[args.compare], hess=h2, gradient=g2,
-                         energy=e2, f_rho=fr2, f_gamma=fg2)
+        dt2, st2 = measure(args.compare, prec=vv10.PRECISIONS[args.compare], hess=h2, gradient=g2,
+                           energy=e2, f_rho=fr2, f_gamma=fg2)
         cmp = dict(precision=args.compare, ms_per_step=dt2 * 1e3, value=pair_pert / dt2,
                    stage_ms=st2, hess=h2.cpu().numpy(), energy=e2.item(),
                    f_rho=fr2.cpu().numpy(), f_gamma=fg2.cpu().numpy())

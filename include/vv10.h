@@ -268,9 +268,18 @@ vv10_status vv10_set_stream(vv10_plan *plan, hipStream_t stream);
  * Errors: VV10_E_STATE (NULL plan), VV10_E_HIP (event creation failed). */
 vv10_status vv10_set_timing(vv10_plan *plan, int32_t enable);
 
-/* Device time in milliseconds of each stage's most recent run, from the
- * events above; ms has VV10_NUM_STAGES entries (HOST memory), stages never
- * run report 0.  Waits for the recorded events to complete.
+/* Per-stage timing for the chosen stages only: bit k of mask (1 << k, k a
+ * vv10_stage) brackets stage k with the event pair above; 0 disables timing
+ * (vv10_set_timing(plan, 1) equals the mask of every stage).  Each timed
+ * stage adds two event records to the stream, so timing only the stages
+ * that are read disturbs the launch sequence least.
+ * Errors: VV10_E_STATE (NULL plan), VV10_E_ARG (bits beyond the stages),
+ * VV10_E_HIP (event creation failed). */
+vv10_status vv10_set_timing_stages(vv10_plan *plan, uint32_t mask);
+
+/* Device time in milliseconds of each stage's most recent timed run, from
+ * the events above; ms has VV10_NUM_STAGES entries (HOST memory), stages
+ * never timed report 0.  Waits for the recorded events to complete.
  * Errors: VV10_E_STATE (NULL plan or timing never enabled), VV10_E_ARG
  * (ms NULL), VV10_E_HIP. */
 vv10_status vv10_stage_times(vv10_plan *plan, double *ms);

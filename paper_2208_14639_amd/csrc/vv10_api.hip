@@ -359,14 +359,15 @@ static vv10_status ensure_weight_work(vv10_plan *p) {
 
 namespace {
 
-// Run one stage, bracketed by timing events when timing is enabled.
+// Run one stage, bracketed by timing events when timing is enabled for it.
 template <typename Fn>
 hipError_t stage(vv10_plan *p, int k, Fn &&fn) {
+    const bool timed = (p->timing >> k) & 1u;
     hipError_t e = hipSuccess;
-    if (p->timing) e = hipEventRecord(p->ev[2 * k], p->stream);
+    if (timed) e = hipEventRecord(p->ev[2 * k], p->stream);
     if (e == hipSuccess) e = fn();
-    if (e == hipSuccess && p->timing) e = hipEventRecord(p->ev[2 * k + 1], p->stream);
-    if (e == hipSuccess && p->timing) p->ran[k] = true;
+    if (e == hipSuccess && timed) e = hipEventRecord(p->ev[2 * k + 1], p->stream);
+    if (e == hipSuccess && timed) p->ran[k] = true;
     return e;
 }
 
@@ -737,9 +738,10 @@ vv10_status vv10_get_tiles(vv10_plan *p, vv10_tiles *t) {
     return VV10_OK;
 }
 
-vv10_status vv10_set_timing(vv10_plan *p, int32_t enable) {
+vv10_status vv10_set_timing_stages(vv10_plan *p, uint32_t mask) {
     if (!p) return VV10_E_STATE;
-    if (enable && !p->ev[0]) {
+    if (mask >> VV10_NUM_STAGES) return VV10_E_ARG;
+    if (mask && !p->ev[0]) {
         for (auto &ev : p->ev) {
             if (take_event(p->device, &ev) != hipSuccess) {
                 ev = nullptr;
@@ -748,8 +750,12 @@ vv10_status vv10_set_timing(vv10_plan *p, int32_t enable) {
             }
         }
     }
-    p->timing = enable != 0;
+    p->timing = mask;
     return VV10_OK;
+}
+
+vv10_status vv10_set_timing(vv10_plan *p, int32_t enable) {
+    return vv10_set_timing_stages(p, enable ? (1u << VV10_NUM_STAGES) - 1u : 0u);
 }
 
 vv10_status vv10_stage_times(vv10_plan *p, double *ms) {

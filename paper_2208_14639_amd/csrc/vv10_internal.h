@@ -129,8 +129,9 @@ struct vv10_plan {
     // screening threshold of the contraction (vv10_set_screening); 0 = off
     double screen_tau = 0.0;
 
-    // per-stage timing (vv10_set_timing)
-    bool timing = false;
+    // per-stage timing (vv10_set_timing, vv10_set_timing_stages): bit k
+    // set = stage k is bracketed by events
+    uint32_t timing = 0;
     hipEvent_t ev[2 * VV10_NUM_STAGES] = {};
     bool ran[VV10_NUM_STAGES] = {};
 

@@ -112,6 +112,8 @@ def load() -> ctypes.CDLL:
     lib.vv10_batch_destroy.argtypes = [P]
     lib.vv10_set_timing.restype = st
     lib.vv10_set_timing.argtypes = [P, i32]
+    lib.vv10_set_timing_stages.restype = st
+    lib.vv10_set_timing_stages.argtypes = [P, ctypes.c_uint32]
     lib.vv10_stage_times.restype = st
     lib.vv10_stage_times.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
     _lib = lib
@@ -302,6 +304,14 @@ def vv10_set_timing(plan: int, enable: bool = True) -> None:
     st = load().vv10_set_timing(plan, 1 if enable else 0)
     if st != VV10_OK:
         raise VV10Error(st, "vv10_set_timing")
+
+
+def vv10_set_timing_stages(plan: int, stages) -> None:
+    """Time only the named stages (names of STAGES) or a bit mask of them."""
+    mask = stages if isinstance(stages, int) else sum(1 << STAGES.index(s) for s in set(stages))
+    st = load().vv10_set_timing_stages(plan, mask)
+    if st != VV10_OK:
+        raise VV10Error(st, "vv10_set_timing_stages")
 
 
 def vv10_stage_times(plan: int) -> dict:

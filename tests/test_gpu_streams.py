@@ -1,7 +1,8 @@
 """Streams and stage timing through the C ABI: a plan rebound to another
 stream (vv10_set_stream), two plans running at once on two streams, and
-per-stage timing (vv10_set_timing, vv10_stage_times), all giving bitwise
-the results of a plan on the default stream."""
+per-stage timing (vv10_set_timing, vv10_set_timing_stages,
+vv10_stage_times), all giving bitwise the results of a plan on the default
+stream."""
 import numpy as np
 import pytest
 
@@ -112,3 +113,31 @@ def test_stage_times(torch, prob):
         torch.cuda.synchronize()
         st = vv10.vv10_stage_times(pl.handle)
         assert st["pair"] > 0.0 and st["contract"] == 0.0, st
+
+
+def test_timing_chosen_stages(torch, prob):
+    """vv10_set_timing_stages brackets only the chosen stages; results stay
+    bitwise the same; a mask beyond the stages is rejected."""
+    from paper_2208_14639_amd import vv10
+    p = prob
+    with vv10.Plan(p, prec="bf16x3") as pl:
+        ref = _host(torch, _terms(pl, p))
+    with vv10.Plan(p, prec="bf16x3") as pl:
+        with pytest.raises(vv10.VV10Error) as ei:
+            vv10.vv10_set_timing_stages(pl.handle, 1 << len(vv10.STAGES))
+        assert ei.value.status == vv10.VV10_E_ARG
+        vv10.vv10_set_timing_stages(pl.handle, ["contract"])
+        got = _host(torch, _terms(pl, p))
+        st = vv10.vv10_stage_times(pl.handle)
+        assert st["contract"] > 0.0, st
+        assert all(v == 0.0 for k, v in st.items() if k != "contract"), st
+        vv10.vv10_set_timing_stages(pl.handle, ["grid", "assemble"])
+        _host(torch, _terms(pl, p))
+        st2 = vv10.vv10_stage_times(pl.handle)
+        assert st2["grid"] > 0.0 and st2["assemble"] > 0.0, st2
+        assert st2["contract"] == st["contract"], (st, st2)   # most recent timed run
+        vv10.vv10_set_timing_stages(pl.handle, 0)
+        _host(torch, _terms(pl, p))
+        assert vv10.vv10_stage_times(pl.handle) == st2
+    for k in ref:
+        assert np.array_equal(got[k], ref[k]), k
