@@ -26,9 +26,12 @@
  *  - A plan is used from one host thread and one stream at a time; distinct
  *    plans may run concurrently on distinct streams.
  *  - All inner sums run over every grid point, the self pair j = i included.
- *  - Quadrature weights are taken as independent of nuclear positions (they
- *    move rigidly with their owner atom), so every weight-derivative term of
- *    the paper's gradient and nine-term Hessian split is zero and absent.
+ *  - Unless a call receives the weights' nuclear derivatives, quadrature
+ *    weights are taken as independent of nuclear positions (they move
+ *    rigidly with their owner atom), so the weight-derivative terms of the
+ *    paper's gradient and nine-term Hessian split vanish.  vv10_nuclear_terms
+ *    and vv10_gradient accept w^x (weights that depend on every nucleus, as
+ *    for an atom-partitioned grid) and then add those terms.
  */
 #ifndef VV10_H
 #define VV10_H
