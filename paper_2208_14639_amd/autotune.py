@@ -6,8 +6,10 @@ Two knobs decide how the O(N^2) work is cut into workgroups:
   * bgroups -- atom groups of the grid-term pass (more groups give more
                waves but more partial pair integrals).
 For a problem size the tuner times candidate values of each knob with the
-library's own per-stage HIP events (a fresh plan per candidate, one warm-up
-and `repeats` timed calls), keeps the fastest, and caches the choice in a
+library's own per-stage HIP events (jsplit on the contraction plus the
+assembly that sums its partials, bgroups on the grid pass; a fresh plan per
+call, one untimed call and `repeats` timed ones), keeps the fastest, and
+caches the choice in a
 JSON file keyed by device architecture, precision and size bucket:
     "<arch>:<prec>:P<16-column blocks>:N<points, rounded up to 8192>"
 Plans and batches take the cached tiles through vv10_set_tiles; sizes with
@@ -64,18 +66,23 @@ def candidates(auto: int, lo: int, hi: int):
     return sorted(v for v in vals if lo <= v <= hi)
 
 
-def _time_stage(problem, prec, tiles, stage, repeats, rx, gx):
+def _time_stages(problem, prec, tiles, stages, repeats, rx, gx):
+    """Fastest summed time of `stages` over `repeats` calls, each on a fresh
+    plan (so the grid pass forms the pair integrals, as on a new geometry),
+    after one untimed call; only the scored stages carry timing events."""
     import torch
     from . import vv10
-    with vv10.Plan(problem, prec=prec, tiles=tiles) as pl:
-        vv10.vv10_set_timing(pl.handle, True)
-        pl.hessian_terms(rx, gx)                   # warm-up (and workspace)
-        ms = []
-        for _ in range(repeats):
-            pl.hessian_terms(rx, gx)
-            ms.append(vv10.vv10_stage_times(pl.handle)[stage])
-        torch.cuda.synchronize()
-        return min(ms), vv10.vv10_get_tiles(pl.handle)
+    ms, used = [], None
+    for r in range(repeats + 1):
+        with vv10.Plan(problem, prec=prec, tiles=tiles) as pl:
+            vv10.vv10_set_timing_stages(pl.handle, stages)
+            pl.nuclear_terms(rx, gx, hess=True, grad=True, energy=True, potential=True)
+            st = vv10.vv10_stage_times(pl.handle)
+            used = vv10.vv10_get_tiles(pl.handle)
+            torch.cuda.synchronize()
+        if r > 0:
+            ms.append(sum(st[s] for s in stages))
+    return min(ms), used
 
 
 def tune(problem, prec: str = "bf16x3", repeats: int = 3, log=print) -> dict:
@@ -88,19 +95,20 @@ def tune(problem, prec: str = "bf16x3", repeats: int = 3, log=print) -> dict:
     with vv10.Plan(problem, prec=prec) as pl:
         auto_j, auto_b = vv10.vv10_get_tiles(pl.handle)
     npad = ((problem.n_grid + 255) // 256) * 256
+    # j splits: the contraction and the assembly, which sums the splits' partials
     best_j, best_jt = auto_j, None
     for j in candidates(auto_j, 1, max(1, npad // 256)):
-        t, (jj, _) = _time_stage(problem, prec, (j, auto_b), "contract", repeats, rx, gx)
-        log(f"  jsplit {j} (effective {jj}): contract {t:.3f} ms")
+        t, (jj, _) = _time_stages(problem, prec, (j, auto_b), ["contract", "assemble"], repeats, rx, gx)
+        log(f"  jsplit {j} (effective {jj}): contract + assembly {t:.3f} ms")
         if best_jt is None or t < best_jt * 0.99:
             best_j, best_jt = jj, t
     best_b, best_bt = auto_b, None
     for bgr in candidates(auto_b, 1, problem.n_atom):
-        t, (_, bb) = _time_stage(problem, prec, (best_j, bgr), "grid", repeats, rx, gx)
+        t, (_, bb) = _time_stages(problem, prec, (best_j, bgr), ["grid"], repeats, rx, gx)
         log(f"  bgroups {bgr} (effective {bb}): grid {t:.3f} ms")
         if best_bt is None or t < best_bt * 0.99:
             best_b, best_bt = bb, t
-    return {"jsplit": best_j, "bgroups": best_b, "contract_ms": best_jt, "grid_ms": best_bt,
+    return {"jsplit": best_j, "bgroups": best_b, "contract_assemble_ms": best_jt, "grid_ms": best_bt,
             "auto": [auto_j, auto_b], "n_grid": problem.n_grid, "n_atom": problem.n_atom}
 
 
@@ -110,7 +118,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--workload", default="water_hexamer", choices=sorted(inputs.WORKLOADS))
     ap.add_argument("--prec", default="bf16x3", choices=["fp64", "fp32", "bf16x3"])
-    ap.add_argument("--repeats", type=int, default=3)
+    ap.add_argument("--repeats", type=int, default=5)
     ap.add_argument("--cache", default=CACHE)
     args = ap.parse_args(argv)
     p = inputs.make_workload(args.workload)
