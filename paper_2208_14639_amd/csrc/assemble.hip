@@ -429,9 +429,12 @@ __global__ __launch_bounds__(256) void k_finish(int32_t n_atom, int32_t P, int32
         const int x = (int)(k - PP);
         const int A = x / 3, a = x % 3;
         double gr = 0.0;
+        // sum_{i in A} a_i E^{Bgr}_i, formed for B > A; for B < A it is
+        // minus the (B, A) sum (a_i e_ij symmetric, d_ij = -d_ji)
 #pragma unroll 8
         for (int B = 0; B < n_atom; ++B) {
-            const double d = DS[((int64_t)A * n_atom + B) * 9 + 6 + a];
+            const double d = B > A ? DS[((int64_t)A * n_atom + B) * 9 + 6 + a]
+                                   : -DS[((int64_t)B * n_atom + A) * 9 + 6 + a];
             gr -= B != A ? d : 0.0;
         }
         grad[x] = Hsum[(int64_t)Pp * Pp + x] + gr;

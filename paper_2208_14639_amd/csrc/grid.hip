@@ -13,12 +13,16 @@
 // (the two channels that multiply p and q in E_{G,gr}), optionally
 //   Ze[i][3B+a] = E^{Bgr}_{i,a}   (the channel of E_{w,gr}), and per tile t of
 // outer points (all in one atom A) the sums
-//   Dpart[t][B][0..5] = sum_{i in t} a_i D^B_i   (xx, yy, zz, xy, xz, yz; B > A only,
-//                                                  zero for B < A)
+//   Dpart[t][B][0..5] = sum_{i in t} a_i D^B_i   (xx, yy, zz, xy, xz, yz)
 //   Dpart[t][B][6..8] = sum_{i in t} a_i E^{Bgr}_i
-// from which the assembly builds E_{gr,gr} and the grid part of the
-// gradient.  The own-atom slot B = O(i) follows from translational
-// invariance and is filled by the assembly.
+// for B > A only (zero for B < A), from which the assembly builds E_{gr,gr}
+// and the grid part of the gradient: summed over the tiles of A, both are
+// (anti)symmetric in the atom pair (a_i a_j Phi (2 S d d^T - T I) is
+// symmetric in i, j; a_i e_ij is symmetric and d_ij = -d_ji), so the
+// (B, A) sums give the B < A ones.  For B < A the pass therefore forms
+// E^{Bgr} + c_i U^{Bgr} as one vector (and E^{Bgr} only for Ze).  The
+// own-atom slot B = O(i) follows from translational invariance and is
+// filled by the assembly.
 //
 // The same pass also accumulates the pair integrals E, U, W, A, B, C of the
 // Hessian call (over every j, the outer point's own atom included), so the
@@ -82,11 +86,16 @@ __device__ __forceinline__ void add_pair_integrals(const PairGeo<T> &q, T *c) {
 }
 
 // One LDS chunk of points j of atom B != A: pair integrals into pc (when
-// INTS), grid sums into c (see k_grid); the D sums only when DSUM.
-template <bool DSUM, bool INTS, typename T, typename T4>
+// INTS), grid sums into c (see k_grid); the D sums only when DSUM.  The
+// first six sums (SUMS): kEU, c[0..2] = sum e d and c[3..5] = sum u d
+// (B > A, where the tile sums need E^{Bgr} on its own); kZ, c[0..2] =
+// sum (e - c_i u) d, the combination the Z channel needs (B < A); kZE, kZ
+// and c[3..5] = sum e d (B < A with Ze).
+enum { kEU = 0, kZ = 1, kZE = 2 };
+template <bool DSUM, bool INTS, int SUMS, typename T, typename T4>
 __device__ __forceinline__ void grid_chunk(const T4 a0, const T4 a1, const T4 *sA, const T4 *sB,
                                            int cnt, T *pc, T *c) {
-    const T oi = a0.w;
+    const T oi = a0.w, ci = a1.z;
 #pragma unroll 4
     for (int jj = 0; jj < cnt; ++jj) {
         const T4 b0 = sA[jj];
@@ -97,10 +106,18 @@ __device__ __forceinline__ void grid_chunk(const T4 a0, const T4 a1, const T4 *s
         const T T_ = Ti + Tj + Ts;
         const T TQ = T_ * q.h + Ti * q.ig + Ts * q.is;
         const T e = q.p * T_;
-        const T u = q.p * TQ;
         const T v = q.p * (q.R2 * TQ - q.h);
-        c[0] += e * dx; c[1] += e * dy; c[2] += e * dz;
-        c[3] += u * dx; c[4] += u * dy; c[5] += u * dz;
+        if (SUMS == kEU) {
+            const T u = q.p * TQ;
+            c[0] += e * dx; c[1] += e * dy; c[2] += e * dz;
+            c[3] += u * dx; c[4] += u * dy; c[5] += u * dz;
+        } else {
+            const T z = q.p * (T_ - ci * TQ);
+            c[0] += z * dx; c[1] += z * dy; c[2] += z * dz;
+            if (SUMS == kZE) {
+                c[3] += e * dx; c[4] += e * dy; c[5] += e * dz;
+            }
+        }
         c[6] += v * dx; c[7] += v * dy; c[8] += v * dz;
         if (DSUM) {
             const T S = T_ * T_ + Ti * Ti + Tj * Tj + Ts * Ts;
@@ -129,11 +146,12 @@ __device__ __forceinline__ void grid_chunk(const T4 a0, const T4 a1, const T4 *s
 //   g[0..2] = sum p T d,  g[3..5] = sum p TQ d,  g[6..8] = sum p (R^2 TQ - h) d,
 //   g[9..14] = sum p S d d^T (xx, yy, zz, xy, xz, yz),  g[15] = sum p T
 // give e d, u d, v d and D through e = 3 p T, u = -3 p TQ, v = -3 p (R^2 TQ - h),
-// D = 6 sum p S d d^T - 3 (sum p T) I.  The D sums are symmetric in the two
-// atoms (the summand a_i a_j Phi (2 S d d^T - T I) is symmetric in i, j), so
-// they are formed for B > A only and the assembly reads them for both orders.
-template <typename T, typename T4, bool INTS>
-__global__ __launch_bounds__(64) void k_grid(
+// D = 6 sum p S d d^T - 3 (sum p T) I.  The D sums and the tile sums of
+// a_i E^{Bgr}_i are formed for B > A only (see above); for B < A
+// g[0..2] = sum p (T - c_i TQ) d gives E^{Bgr} + c_i U^{Bgr} = 3 g[0..2],
+// and g[3..5] = sum p T d only for Ze.
+template <typename T, typename T4, bool INTS, bool ZE>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) void k_grid(
     int32_t n_atom, int32_t Pp, int32_t bgroups, int64_t npad, const int64_t *__restrict__ seg,
     const int32_t *__restrict__ tile_i0, const int32_t *__restrict__ tile_n,
     const int32_t *__restrict__ tile_atom, const T4 *__restrict__ P0,
@@ -170,8 +188,8 @@ __global__ __launch_bounds__(64) void k_grid(
                 }
             } else {
                 T c[16] = {};
-                if (dsum) grid_chunk<true, INTS, T, T4>(a0, a1, sA, sB, cnt, pc, c);
-                else grid_chunk<false, INTS, T, T4>(a0, a1, sA, sB, cnt, pc, c);
+                if (dsum) grid_chunk<true, INTS, kEU, T, T4>(a0, a1, sA, sB, cnt, pc, c);
+                else grid_chunk<false, INTS, ZE ? kZE : kZ, T, T4>(a0, a1, sA, sB, cnt, pc, c);
 #pragma unroll
                 for (int k = 0; k < 16; ++k) acc[k] += (double)c[k];
             }
@@ -180,21 +198,23 @@ __global__ __launch_bounds__(64) void k_grid(
                 for (int k = 0; k < 6; ++k) pint[k] += (double)pc[k];
         }
         if (B == A) continue;
-        // E^{Bgr} = 3 acc[0..2], U^{Bgr} = -3 acc[3..5], W^{Bgr} = -3 acc[6..8]
+        // B > A: E^{Bgr} = 3 acc[0..2], U^{Bgr} = -3 acc[3..5]; B < A:
+        // E^{Bgr} + c_i U^{Bgr} = 3 acc[0..2] (and E^{Bgr} = 3 acc[3..5] with
+        // Ze); W^{Bgr} = -3 acc[6..8]
         if (live) {
             double *z0 = Z + (i * 2 + 0) * Pp + 3 * B;
             double *z1 = Z + (i * 2 + 1) * Pp + 3 * B;
-            z0[0] = 3.0 * (acc[0] - ci * acc[3]);
-            z0[1] = 3.0 * (acc[1] - ci * acc[4]);
-            z0[2] = 3.0 * (acc[2] - ci * acc[5]);
+            z0[0] = 3.0 * (dsum ? acc[0] - ci * acc[3] : acc[0]);
+            z0[1] = 3.0 * (dsum ? acc[1] - ci * acc[4] : acc[1]);
+            z0[2] = 3.0 * (dsum ? acc[2] - ci * acc[5] : acc[2]);
             z1[0] = -3.0 * acc[6];
             z1[1] = -3.0 * acc[7];
             z1[2] = -3.0 * acc[8];
-            if (Ze) {
+            if (ZE) {
                 double *ze = Ze + i * Pp + 3 * B;
-                ze[0] = 3.0 * acc[0];
-                ze[1] = 3.0 * acc[1];
-                ze[2] = 3.0 * acc[2];
+                ze[0] = 3.0 * (dsum ? acc[0] : acc[3]);
+                ze[1] = 3.0 * (dsum ? acc[1] : acc[4]);
+                ze[2] = 3.0 * (dsum ? acc[2] : acc[5]);
             }
         }
         const double di = -3.0 * acc[15];
@@ -205,7 +225,7 @@ __global__ __launch_bounds__(64) void k_grid(
         double *dp = Dpart + ((int64_t)t * n_atom + B) * 9;
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            if (k < 6 && !dsum) {
+            if (!dsum) {   // B < A: the assembly reads both parts from the (B, A) sums
                 if (lane == 0) dp[k] = 0.0;
                 continue;
             }
@@ -322,18 +342,24 @@ __global__ __launch_bounds__(64) void k_grid_grad(
 
 }  // namespace
 
-template <bool INTS>
-void grid_terms_mode(vv10_plan *p, double *Ze) {
+template <bool INTS, bool ZE>
+void grid_terms_launch(vv10_plan *p, double *Ze) {
     const Workspace &ws = p->ws;
     dim3 grid((unsigned)p->ntiles, (unsigned)ws.bgroups);
     if (p->prec == VV10_FP64)
-        k_grid<double, double4, INTS><<<grid, TG, 0, p->stream>>>(
+        k_grid<double, double4, INTS, ZE><<<grid, TG, 0, p->stream>>>(
             p->n_atom, ws.Pp, ws.bgroups, p->npad, p->d_seg, p->d_tile_i0, p->d_tile_n,
             p->d_tile_atom, p->P0, p->P1, ws.Z, Ze, ws.Dpart, ws.Igrp);
     else
-        k_grid<float, float4, INTS><<<grid, TG, 0, p->stream>>>(
+        k_grid<float, float4, INTS, ZE><<<grid, TG, 0, p->stream>>>(
             p->n_atom, ws.Pp, ws.bgroups, p->npad, p->d_seg, p->d_tile_i0, p->d_tile_n,
             p->d_tile_atom, p->P0f, p->P1f, ws.Z, Ze, ws.Dpart, ws.Igrp);
+}
+
+template <bool INTS>
+void grid_terms_mode(vv10_plan *p, double *Ze) {
+    if (Ze) grid_terms_launch<INTS, true>(p, Ze);
+    else grid_terms_launch<INTS, false>(p, Ze);
 }
 
 template <bool INTS>
