@@ -41,8 +41,9 @@ FLOPS_PER_PAIR_INTEGRALS = 38    # E, U, W (26) + A, B, C (12)
 FLOPS_PER_PAIR_EUW = 26          # k_pair, energy call: E, U, W
 # fused grid pass (k_grid with the pair integrals), per pair by atom class:
 # the outer point's own atom (pair geometry 22 + six integral sums 14), an
-# atom B below it (+ grid sums E/U/W^{Bgr} 34), an atom above it (+ D sums 24)
-FLOPS_GRID_OWN, FLOPS_GRID_BELOW, FLOPS_GRID_ABOVE = 36, 70, 94
+# atom B below it (+ the grid sums E^{Bgr} + c U^{Bgr} and W^{Bgr}, 29), an atom above
+# it (+ E^{Bgr}, U^{Bgr} and W^{Bgr} apart, 34, and the D sums, 24)
+FLOPS_GRID_OWN, FLOPS_GRID_BELOW, FLOPS_GRID_ABOVE = 36, 65, 94
 FP32_NO_PACKED_TFLOPS = 78.6     # one FP32 FMA per lane and cycle (packed FP32 off)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
