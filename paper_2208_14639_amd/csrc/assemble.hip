@@ -446,7 +446,9 @@ __global__ __launch_bounds__(256) void k_finish(int32_t n_atom, int32_t P, int32
 // Gradient (Section II.A, first form of the grid part): for x = 3 A + a,
 //   grad[x] = sum_i w_i (f^rho_i rho^x_i + f^gamma_i gamma^x_i)
 //           [+ sum_i w^x_i rho_i (beta + E_i)]
-//           - sum_{B != A} sum_{tiles t of A} Gpart[t][B][a],
+//           - sum_{B > A} sum_{tiles t of A} Gpart[t][B][a]
+//           + sum_{B < A} sum_{tiles t of B} Gpart[t][A][a]
+// (the tile sums are antisymmetric in the atom pair; the pass forms B > A),
 // gamma^x = 2 grad rho . grad rho^x; w^x (optional) with the owner slot from
 // Wown.  One workgroup per x; both sums are fixed-order tree reductions,
 // added at the end.
@@ -474,12 +476,15 @@ __global__ __launch_bounds__(256) void k_gradient(int64_t n, int64_t npad, int32
             eg += wx * F[F_F0 * npad + i];
         }
     }
+    // -sum_{B != A} sum_{t in A} Gpart[t][B]: the pass forms B > A; a B < A
+    // term is minus the (B, A) one, i.e. +Gpart[t][A] over the tiles t of B
     const int t0 = tile_first[A], nt = tile_first[A + 1] - t0;
     double gr = 0.0;
-    for (int k = tid; k < n_atom * nt; k += 256) {
-        const int B = k / nt, t = t0 + k % nt;
-        if (B != A) gr -= Gpart[((int64_t)t * n_atom + B) * 3 + a];
+    for (int k = tid; k < (n_atom - A - 1) * nt; k += 256) {
+        const int B = A + 1 + k / nt, t = t0 + k % nt;
+        gr -= Gpart[((int64_t)t * n_atom + B) * 3 + a];
     }
+    for (int t = tid; t < t0; t += 256) gr += Gpart[((int64_t)t * n_atom + A) * 3 + a];
     sg[tid] = eg;
     sr[tid] = gr;
     __syncthreads();

@@ -257,9 +257,10 @@ __global__ __launch_bounds__(256) void k_sum_groups(int64_t n, int64_t npad, int
 
 // Gradient pass (Section II.A): the pair integrals E, U, W of every outer
 // point (over all j) and, per tile t of outer points (atom A) and atom
-// B != A, Gpart[t][B][a] = sum_{i in t} a_i E^{Bgr}_{i,a} (zero for B = A),
+// B > A, Gpart[t][B][a] = sum_{i in t} a_i E^{Bgr}_{i,a} (zero for B <= A),
 // from which the grid part of the gradient follows,
-// E_gr = -sum_{B != A} sum_{i in A} a_i E^{Bgr}_i (translational invariance).
+// E_gr = -sum_{B != A} sum_{i in A} a_i E^{Bgr}_i (translational invariance),
+// the B < A terms being minus the (B, A) ones.
 // The layout and the scaled sums are those of k_grid: E^{Bgr}_i = 3 sum_j p T d.
 // Without INTS (the plan already holds E, U, W) only the grid sums are formed.
 template <typename T, typename T4, bool INTS>
@@ -281,7 +282,11 @@ __global__ __launch_bounds__(64) void k_grid_grad(
     for (int B = grp; B < n_atom; B += bgroups) {
         const int64_t jb = seg[B], je = seg[B + 1];
         double acc[3] = {};
-        if (!INTS && B == A) {
+        // the tile sums are antisymmetric in (A, B) (a_i e_ij symmetric,
+        // d_ij = -d_ji): formed for B > A only, the assembly takes the B < A
+        // ones from the (B, A) sums; B <= A still adds to the pair integrals
+        const bool gsum = B > A;
+        if (!INTS && !gsum) {
             if (lane == 0)
                 for (int k = 0; k < 3; ++k) Gpart[((int64_t)t * n_atom + B) * 3 + k] = 0.0;
             continue;
@@ -294,7 +299,7 @@ __global__ __launch_bounds__(64) void k_grid_grad(
             __syncthreads();
             const int cnt = (int)min((int64_t)TG, je - j0);
             T pc[3] = {}, c[3] = {};
-            if (B == A) {
+            if (!gsum) {
 #pragma unroll 4
                 for (int jj = 0; jj < cnt; ++jj) {
                     const PairGeo<T> q = pair_geo<T>(a0, a1, sA[jj], sB[jj]);
@@ -329,7 +334,7 @@ __global__ __launch_bounds__(64) void k_grid_grad(
         double *gp = Gpart + ((int64_t)t * n_atom + B) * 3;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const double tot = B == A ? 0.0 : wave_sum(ai * 3.0 * acc[k]);
+            const double tot = gsum ? wave_sum(ai * 3.0 * acc[k]) : 0.0;
             if (lane == 0) gp[k] = tot;
         }
     }
