@@ -1,23 +1,34 @@
 #!/usr/bin/env python3
 """Benchmark of the VV10 Hessian-term engine on one MI355X.
 
-One step is one pass of the whole hot path over one synthetic molecule
-already resident in HBM: vv10_prepare (per-point prep) -> vv10_nuclear_terms
-with the energy, potential, Hessian-term and gradient outputs (one pass over
-the pairs for the pair integrals E..C and the grid-position terms, the
-potential and energy, perturbation packing, MFMA contraction, assembly) ->
-vv10_destroy.  --separate-energy times vv10_energy_potential (its own pair
-pass) followed by vv10_hessian_terms instead.
+Default run: the water 20-mer (N = 120000 grid points, P = 180 nuclear
+perturbations).  One step is one pass of the whole hot path over the
+molecule, already resident in HBM: vv10_prepare (per-point prep) ->
+vv10_nuclear_terms with the energy, potential, Hessian-term and gradient
+outputs (one pass over the pairs for the pair integrals and the
+grid-position terms, potential and energy, perturbation packing, MFMA
+contraction, assembly) -> vv10_destroy.  The split-BF16 path is timed, then
+the FP64 and FP32 paths on the same inputs ("mixed vs FP64"), and the run
+reports:
+  * every mixed output against the FP64 GPU path element by element
+    (energy, potential, gradient, every Hessian element, response rows);
+  * every path against the FP64 oracle on rows sampled at three places
+    (potential and response rows of 4 points each);
+  * a served stream (continuous batching, Poisson arrivals, a fresh seeded
+    cluster per request) with p50/p99 latency, each result checked against
+    the FP64 GPU path alone and the smallest against the oracle;
+  * the oracle timed on the host cores on a bounded row sample.
+--separate-energy times vv10_energy_potential (its own pair pass) followed
+by vv10_hessian_terms instead.
 
 Metric: grid-pair x perturbation per second, N^2 P / t_step, with N^2 the
 ordered pairs (self pairs included) and P = 3 N_atom.
 
 Prints one JSON line with the metric, a roofline entry for the dominant
 kernel (the perturbation contraction, timed with HIP events recorded by the
-library on the plan's stream), the pair pass against the vector peak (the
-step's fused grid pass, and the energy call's own pair kernel timed apart
-from the steps) and a CPU baseline (the FP64 oracle on the host, rank 0
-only).
+library on the plan's stream), the pair pass against the vector peak, the
+comparison legs with their errors, the served latencies and a CPU baseline
+(rank 0 only).
 """
 from __future__ import annotations
 
@@ -46,6 +57,8 @@ FLOPS_PER_PAIR_EUW = 26          # k_pair, energy call: E, U, W
 FLOPS_GRID_OWN, FLOPS_GRID_BELOW, FLOPS_GRID_ABOVE = 36, 65, 94
 FP32_NO_PACKED_TFLOPS = 78.6     # one FP32 FMA per lane and cycle (packed FP32 off)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+METRIC = "VV10 Hessian grid-pair\u00b7perturbation/s, mixed vs FP64, at stated err; p99 latency"
+DTYPES = {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f32+f64"}
 
 
 def log(*a):
@@ -131,6 +144,26 @@ def row_sample(fn, n, target_s=10.0):
     return k2, time.perf_counter() - t0, res
 
 
+def host_info():
+    """Provenance of a host-side timing: CPU model, logical CPUs visible to
+    the process and the OpenMP thread setting."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        nproc = os.cpu_count()
+    return {"cpu_model": model, "nproc": nproc,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
 def cpu_baseline(p, budget_s=30.0):
     """FP64 oracle on the host.  Full workload when it fits the budget, else
     the dominant O(N^2 P) step (response rows, and with weight derivatives the
@@ -139,35 +172,94 @@ def cpu_baseline(p, budget_s=30.0):
     g, gx = oracle.problem_inputs(p)
     n, P = p.n_grid, p.n_pert
     est_rate = 3e9 * oracle.num_threads() / 8      # pair*pert/s, measured order of magnitude
+    base = dict(unit="pair*pert/s", cores=oracle.num_threads(), kind="oracle", **host_info())
     if p.w_x is not None:
         def rows(k):
             oracle.response_rows(0, k, p.coords, p.weights, p.rho, g, p.b, p.C, p.rho_x, gx)
             oracle.weight_integrals(p.coords, p.rho, g, p.b, p.C, p.w_x, 0, k)
         k, dt, _ = row_sample(rows, n)
-        return dict(value=k * n * P / dt, unit="pair*pert/s", cores=oracle.num_threads(),
-                    kind="oracle", seconds=dt,
+        return dict(value=k * n * P / dt, seconds=dt,
                     sample=f"response rows and weight integrals of rows 0..{k} of N={n}, P={P} "
-                           f"(dominant N^2 P steps incl. one full pair-integral pass)"), None
+                           f"(the dominant N^2 P steps)", **base), None
     if n * n * P / est_rate <= budget_s:
         t0 = time.perf_counter()
         H, _ = oracle.hessian_terms(p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b, p.C,
                                     p.rho_x, gx)
         e0, fr0, fg0 = oracle.energy_potential(p.coords, p.weights, p.rho, g, p.b, p.C)
         dt = time.perf_counter() - t0
-        return dict(value=n * n * P / dt, unit="pair*pert/s", cores=oracle.num_threads(),
-                    kind="oracle", seconds=dt,
-                    sample=f"whole workload: energy, potential and Hessian terms, N={n}, P={P}"), \
-            dict(H=H, E=e0, f_rho=fr0, f_gamma=fg0)
+        return dict(value=n * n * P / dt, seconds=dt,
+                    sample=f"whole workload: energy, potential and Hessian terms, N={n}, P={P}",
+                    **base), dict(H=H, E=e0, f_rho=fr0, f_gamma=fg0)
     k, dt, _ = row_sample(
         lambda k: oracle.response_rows(0, k, p.coords, p.weights, p.rho, g, p.b, p.C, p.rho_x, gx), n)
-    return dict(value=k * n * P / dt, unit="pair*pert/s", cores=oracle.num_threads(),
-                kind="oracle", seconds=dt,
-                sample=f"response rows 0..{k} of N={n}, P={P} (dominant N^2 P step incl. one "
-                       f"full pair-integral pass)"), None
+    return dict(value=k * n * P / dt, seconds=dt,
+                sample=f"response rows 0..{k} of N={n}, P={P} (the dominant N^2 P step: each "
+                       f"row sums over all N points for all P perturbations)", **base), None
+
+
+ROW_SAMPLE = 4          # rows per sampled place
+
+
+def sample_places(n):
+    """Three places of ROW_SAMPLE rows: the first points, the middle, the last."""
+    mid = n // 2 + 7
+    return [0, min(mid, n - ROW_SAMPLE), n - ROW_SAMPLE]
+
+
+def oracle_row_checks(p, results):
+    """Potential (f^rho, f^gamma) and response rows of the oracle on rows
+    sampled at three places, against each path's GPU outputs (normwise over
+    the sampled rows, scaled by the largest GPU value of the whole output).
+    results: {prec: dict(f_rho, f_gamma, resp_rho, resp_gamma)} as numpy."""
+    import numpy as np
+    import oracle
+    g, gx = oracle.problem_inputs(p)
+    places = sample_places(p.n_grid)
+    ref = []
+    for i0 in places:
+        fr, fg, _ = oracle.potential_rows(i0, i0 + ROW_SAMPLE, p.coords, p.weights, p.rho, g, p.b, p.C)
+        Yr, Yg = oracle.response_rows(i0, i0 + ROW_SAMPLE, p.coords, p.weights, p.rho, g, p.b, p.C,
+                                      p.rho_x, gx)
+        ref.append((i0, fr, fg, Yr, Yg))
+    out = {"rows": [[i0, i0 + ROW_SAMPLE] for i0 in places]}
+    for prec, r in results.items():
+        e = dict(f_rho=0.0, f_gamma=0.0, resp_rho=0.0, resp_gamma=0.0)
+        scale = {k: float(np.max(np.abs(r[k]))) for k in e}
+        for i0, fr, fg, Yr, Yg in ref:
+            sl = slice(i0, i0 + ROW_SAMPLE)
+            e["f_rho"] = max(e["f_rho"], float(np.max(np.abs(r["f_rho"][sl] - fr))) / scale["f_rho"])
+            e["f_gamma"] = max(e["f_gamma"], float(np.max(np.abs(r["f_gamma"][sl] - fg))) / scale["f_gamma"])
+            e["resp_rho"] = max(e["resp_rho"], float(np.max(np.abs(r["resp_rho"][:, sl] - Yr))) / scale["resp_rho"])
+            e["resp_gamma"] = max(e["resp_gamma"], float(np.max(np.abs(r["resp_gamma"][:, sl] - Yg))) / scale["resp_gamma"])
+        out[prec] = e
+    return out
+
+
+def errors_vs(a, b):
+    """Outputs a of one path against b of another (numpy dicts): energy
+    relative; potential, gradient and response rows normwise; every Hessian
+    element absolute (max and how many exceed the 1e-5 au bound)."""
+    import numpy as np
+    nw = lambda x, y: float(np.max(np.abs(x - y)) / np.max(np.abs(y)))
+    out = {"energy_rel": abs(a["energy"] - b["energy"]) / abs(b["energy"]),
+           "f_rho_normwise": nw(a["f_rho"], b["f_rho"]),
+           "f_gamma_normwise": nw(a["f_gamma"], b["f_gamma"]),
+           "grad_normwise": nw(a["grad"], b["grad"]),
+           "hess_max_abs": float(np.max(np.abs(a["hess"] - b["hess"]))),
+           "hess_elements_over_1e-5": int(np.sum(np.abs(a["hess"] - b["hess"]) > 1e-5)),
+           "hess_elements": int(a["hess"].size),
+           "hess_max_abs_value": float(np.max(np.abs(b["hess"])))}
+    if "resp_rho" in a and "resp_rho" in b:
+        out["resp_rho_normwise"] = nw(a["resp_rho"], b["resp_rho"])
+        out["resp_gamma_normwise"] = nw(a["resp_gamma"], b["resp_gamma"])
+    return out
 
 
 def bench_batch(args, torch, np, inputs, vv10):
-    """64 molecules of uneven size in one graph launch per step."""
+    """64 molecules of uneven size in one graph launch per step.  Every
+    molecule's energy and Hessian terms are checked against the same batch
+    run on the FP64 path; the oracle checks the three smallest molecules in
+    full and the largest molecule's energy and sampled potential rows."""
     sizes = inputs.random_cluster_sizes(64, seed=1004)
     probs = []
     for m, k in enumerate(sizes):
@@ -191,24 +283,43 @@ def bench_batch(args, torch, np, inputs, vv10):
         energies = b.energy.cpu().numpy()
         blocks = [h.cpu().numpy() for h in b.blocks()]
     out = {
-        "metric": "VV10 Hessian grid-pair\u00b7perturbation/s, mixed vs FP64, at stated err; p99 latency",
+        "metric": METRIC,
         "value": pair_pert / dt, "unit": "pair*pert/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f32+f64"}[args.prec],
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPES[args.prec],
         "data": "synthetic",
         "config": {"workload": "batch64", "n_mol": len(probs), "waters": sizes, "n_pa": 1500,
                    "precision": args.prec, "work_items": n_items, "persistent_workgroups": n_wg},
         "roofline": None, "cpu_baseline": None,
     }
+    # every molecule against the FP64 path (the same batch, one untimed launch)
+    if args.prec != "fp64":
+        with vv10.Batch(probs, prec="fp64", tiles="auto") as b:
+            t0 = time.perf_counter()
+            b.run()
+            torch.cuda.synchronize()
+            t64 = time.perf_counter() - t0
+            e64 = b.energy.cpu().numpy()
+            H64 = [h.cpu().numpy() for h in b.blocks()]
+        log("fp64 batch done")
+        per = [{"mol": m, "n_grid": probs[m].n_grid,
+                "energy_rel": float(abs(energies[m] - e64[m]) / abs(e64[m])),
+                "hess_max_abs": float(np.max(np.abs(blocks[m] - H64[m])))} for m in range(len(probs))]
+        out["vs_fp64"] = {"ms_per_launch": t64 * 1e3, "speedup_vs_one_fp64_launch": t64 / dt,
+                          "energy_rel_max": max(r["energy_rel"] for r in per),
+                          "hess_max_abs_max": max(r["hess_max_abs"] for r in per),
+                          "within_stated_bounds": all(r["energy_rel"] <= 1e-6 and r["hess_max_abs"] <= 1e-5
+                                                      for r in per),
+                          "per_molecule": per}
     # CPU baseline: the whole oracle on the three smallest molecules, whose
-    # results also check the batch's
+    # results also check the batch's; the largest molecule's energy and
+    # potential rows against the oracle
     if not args.no_cpu_baseline:
         import oracle
-        order = np.argsort([p.n_grid for p in probs])[:3]
+        order = np.argsort([p.n_grid for p in probs])
         errs = []
         work, secs = 0.0, 0.0
-        for m in order:
+        for m in order[:3]:
             p = probs[m]
             g, gx = oracle.problem_inputs(p)
             t0 = time.perf_counter()
@@ -220,8 +331,17 @@ def bench_batch(args, torch, np, inputs, vv10):
             errs.append({"mol": int(m), "n_grid": p.n_grid,
                          "energy_rel": abs(energies[m] - e0) / abs(e0),
                          "hess_max_abs": float(np.max(np.abs(blocks[m] - H0)))})
+        big = int(order[-1])
+        p = probs[big]
+        log(f"oracle energy of the largest molecule (N={p.n_grid}) running ...")
+        g = oracle.gamma(p.grad_rho)
+        e0, _, _ = oracle.energy_potential(p.coords, p.weights, p.rho, g, p.b, p.C)
+        rec = {"mol": big, "n_grid": p.n_grid, "energy_rel": abs(energies[big] - e0) / abs(e0)}
+        if args.prec != "fp64":
+            rec["fp64_energy_rel"] = abs(e64[big] - e0) / abs(e0)
+        errs.append(rec)
         out["cpu_baseline"] = dict(value=work / secs, unit="pair*pert/s", cores=oracle.num_threads(),
-                                   kind="oracle", seconds=secs,
+                                   kind="oracle", seconds=secs, **host_info(),
                                    sample="energy, potential and Hessian terms of the three "
                                           "smallest molecules of the batch")
         out["errors_vs_oracle"] = errs
@@ -365,63 +485,128 @@ def bench_trial_response(args, torch, np, inputs, vv10, n_t=54):
     print(json.dumps(out), flush=True)
 
 
-def bench_served(args, torch, np, inputs, vv10, pool_size=16, n_requests=96, n_warm=8):
-    """Poisson stream of requests (1-30 waters, 1000-2500 points/atom) through
-    the continuous-batching server; p50/p99 latency and throughput."""
-    from paper_2208_14639_amd.serve import GpuExecutor, Request, Server
+def served_stream(args, torch, np, inputs, vv10, n_requests=56, n_warm=8, n_probe=8, load=0.7,
+                  check=True):
+    """Poisson stream of Hessian-term requests through the continuous-batching
+    server, each a fresh seeded water cluster (1-30 waters, 1000-2500 points
+    per atom, seed 3000 + k), its density and nuclear derivatives built on
+    the device before the stream starts.  Arrival rate: `load` times the
+    single-slot capacity measured on the first n_probe requests.  Returns
+    the served record: p50/p99 latency (the first n_warm requests are
+    warm-up), throughput, a latency breakdown by request size (queue wait
+    and service time), and the result checks: every result against the same
+    request run alone (bitwise) and alone on the FP64 path (stated bounds),
+    and the two smallest requests against the oracle."""
+    from paper_2208_14639_amd.serve import GpuExecutor, Request, Server, percentile
     rng = np.random.default_rng(1005)
-    pool = []
-    for k in range(pool_size):
-        pool.append(inputs.make_problem(int(rng.integers(1, 31)), int(rng.integers(1000, 2501)),
-                                        3000 + k))
-        log(f"generated {k + 1}/{pool_size} molecules (N={pool[-1].n_grid})")
-    # single-slot service times (also the results alone)
-    alone, service = [], []
-    for k, p in enumerate(pool):
-        with vv10.Plan(p, prec=args.prec, tiles="auto") as pl:
-            pl.hessian_terms(p.rho_x, p.grad_rho_x)
+    dev = torch.device("cuda:0")
+    sizes = [(int(rng.integers(1, 31)), int(rng.integers(1000, 2501))) for _ in range(n_requests)]
+    reqs_in = []
+    for k, (nw, npa) in enumerate(sizes):
+        reqs_in.append(inputs.make_problem_on_device(nw, npa, 3000 + k, torch, dev))
+    torch.cuda.synchronize()
+    log(f"served: {n_requests} requests built on the device "
+        f"(N {min(q.n_grid for q in reqs_in)}..{max(q.n_grid for q in reqs_in)})")
+    tiles = "auto"
+
+    def alone(p, prec):
+        with vv10.Plan(p, prec=prec, tiles=tiles) as pl:
+            out = pl.nuclear_terms(p.rho_x, p.grad_rho_x, hess=True, energy=True)
             torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            e, _, _ = pl.energy_potential()
-            H = pl.hessian_terms(p.rho_x, p.grad_rho_x)["hess"]
-            torch.cuda.synchronize()
-            service.append(time.perf_counter() - t0)
-            alone.append((e.item(), H.cpu().numpy()))
-        log(f"alone {k + 1}/{pool_size}: {service[-1] * 1e3:.1f} ms")
-    rate = 0.7 / float(np.mean(service))             # 70% of the single-slot capacity
+            return out["energy"].item(), out["hess"].cpu().numpy()
+
+    # single-slot service time (prepare + one Hessian-terms call) on the first
+    # n_probe requests, after one untimed call each
+    service = []
+    for p in reqs_in[:n_probe]:
+        alone(p, args.prec)
+        t0 = time.perf_counter()
+        alone(p, args.prec)
+        service.append(time.perf_counter() - t0)
+    rate = load / float(np.mean(service))
     gaps = rng.exponential(1.0 / rate, size=n_requests)
     arrivals = np.cumsum(gaps) - gaps[0]
-    which = rng.integers(0, pool_size, size=n_requests)
     ex = GpuExecutor(prec=args.prec, n_slots=4)
     budget = 96 * 1024 ** 3
     srv = Server(ex, budget, n_slots=4)
-    futs = [srv.submit(Request(k, f"m{m}", pool[m]), at=float(t))
-            for k, (m, t) in enumerate(zip(which, arrivals))]
+    futs = [srv.submit(Request(k, f"r{k}", reqs_in[k]), at=float(t))
+            for k, t in enumerate(arrivals)]
     t0 = time.perf_counter()
     srv.run_until_idle(timeout_s=240)
     wall = time.perf_counter() - t0
-    max_diff, same = 0.0, True
-    for k, m in enumerate(which):
-        e, H = futs[k].result()
-        same &= bool(np.array_equal(H, alone[m][1])) and e == alone[m][0]
-        max_diff = max(max_diff, float(np.max(np.abs(H - alone[m][1]))))
+    log(f"served: stream drained in {wall:.1f} s")
     st = srv.stats(skip=n_warm)
+    done = sorted((r for r in srv.done if r.status == "done"), key=lambda r: r.rid)[n_warm:]
+    # latency by request size: queue wait (arrival -> admission) and service
+    buckets = [(0, 30000), (30000, 90000), (90000, 150000), (150000, 10 ** 9)]
+    by_size = []
+    for lo, hi in buckets:
+        rs = [r for r in done if lo <= r.problem.n_grid < hi]
+        if not rs:
+            continue
+        lat = [r.latency for r in rs]
+        by_size.append({"n_grid": [lo, hi if hi < 10 ** 9 else None], "requests": len(rs),
+                        "p50_s": percentile(lat, 50), "p99_s": percentile(lat, 99),
+                        "mean_wait_s": float(np.mean([r.admitted - r.arrival for r in rs])),
+                        "mean_service_s": float(np.mean([r.finished - r.admitted for r in rs]))})
+    slow = sorted(done, key=lambda r: r.latency)[-3:]
+    tail = [{"rid": r.rid, "n_grid": r.problem.n_grid, "n_pert": r.problem.n_pert,
+             "latency_s": r.latency, "wait_s": r.admitted - r.arrival,
+             "service_s": r.finished - r.admitted} for r in slow]
+    rec = {"requests": n_requests, "warmup": n_warm, "reuse_fraction": 0.0,
+           "request_sizes": "fresh cluster per request: U{1..30} waters, U{1000..2500} points/atom",
+           "arrival_rate_per_s": rate, "rate_fraction_of_single_slot": load,
+           "single_slot_mean_s": float(np.mean(service)), "slots": 4, "budget_bytes": budget,
+           "wall_s": wall, "latency_s": {"p50": st["p50_s"], "p99": st["p99_s"], "mean": st["mean_s"]},
+           "throughput_pair_pert_per_s": st["throughput_pair_pert_per_s"],
+           "completed": st["completed"], "failed": st["failed"], "rejected": st["rejected"],
+           "peak_bytes": st["peak_bytes"], "latency_by_size": by_size, "slowest": tail}
+    if check:
+        # every result against the same request alone (same precision,
+        # bitwise) and alone on the FP64 path (stated bounds)
+        same, e_max, h_max = True, 0.0, 0.0
+        for k, f in enumerate(futs):
+            e, H = f.result()
+            ea, Ha = alone(reqs_in[k], args.prec)
+            same &= bool(np.array_equal(H, Ha)) and e == ea
+            e64, H64 = alone(reqs_in[k], "fp64")
+            e_max = max(e_max, abs(e - e64) / abs(e64))
+            h_max = max(h_max, float(np.max(np.abs(H - H64))))
+        log("served: results checked against alone and FP64")
+        rec["results_identical_alone_and_in_mix"] = same
+        rec["vs_fp64_alone"] = {"energy_rel_max": e_max, "hess_max_abs_max": h_max,
+                                "within_bounds": bool(e_max <= 1e-6 and h_max <= 1e-5)}
+        import oracle
+        chk = []
+        for k in sorted(range(n_requests), key=lambda k: reqs_in[k].n_grid)[:2]:
+            q = reqs_in[k]
+            hp = inputs.Problem(mol=q.mol, atom_of=q.atom_of, offsets=q.offsets, coords=q.coords,
+                                weights=q.weights, rho=q.rho.cpu().numpy(),
+                                grad_rho=q.grad_rho.cpu().numpy(), radii=q.radii,
+                                rho_x=q.rho_x.cpu().numpy(), grad_rho_x=q.grad_rho_x.cpu().numpy())
+            g, gx = oracle.problem_inputs(hp)
+            H0, _ = oracle.hessian_terms(hp.atom_of, hp.n_atom, hp.coords, hp.weights, hp.rho, g,
+                                         hp.b, hp.C, hp.rho_x, gx)
+            e0, _, _ = oracle.energy_potential(hp.coords, hp.weights, hp.rho, g, hp.b, hp.C)
+            e, H = futs[k].result()
+            chk.append({"rid": k, "n_grid": hp.n_grid, "energy_rel": abs(e - e0) / abs(e0),
+                        "hess_max_abs": float(np.max(np.abs(H - H0)))})
+        rec["vs_oracle"] = chk
     srv.close()
+    return rec
+
+
+def bench_served(args, torch, np, inputs, vv10):
+    """The served stream alone as the JSON line's workload."""
+    rec = served_stream(args, torch, np, inputs, vv10)
     out = {
-        "metric": "VV10 Hessian grid-pair\u00b7perturbation/s, mixed vs FP64, at stated err; p99 latency",
-        "value": st["throughput_pair_pert_per_s"], "unit": "pair*pert/s", "n_gpus": 1,
-        "steps": n_requests, "warmup": n_warm, "ms_per_step": wall / n_requests * 1e3,
+        "metric": METRIC, "value": rec["throughput_pair_pert_per_s"], "unit": "pair*pert/s",
+        "n_gpus": 1, "steps": rec["requests"], "warmup": rec["warmup"],
+        "ms_per_step": rec["wall_s"] / rec["requests"] * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f32+f64"}[args.prec],
-        "data": "synthetic",
-        "config": {"workload": "served", "pool": pool_size, "requests": n_requests,
-                   "arrival_rate_per_s": rate, "rate_fraction_of_single_slot": 0.7,
-                   "slots": 4, "budget_bytes": budget, "precision": args.prec},
-        "latency_s": {"p50": st["p50_s"], "p99": st["p99_s"], "mean": st["mean_s"]},
-        "single_slot_mean_s": float(np.mean(service)),
-        "served": st,
-        "results_identical_alone_and_in_mix": same, "max_abs_diff_vs_alone": max_diff,
-        "roofline": None, "cpu_baseline": None,
+        "dtype": DTYPES[args.prec], "data": "synthetic",
+        "config": {"workload": "served", "precision": args.prec},
+        "latency_s": rec["latency_s"], "served": rec, "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
 
@@ -431,15 +616,20 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="water_hexamer",
+    ap.add_argument("--workload", default="water_20mer",
                     choices=["water_dimer", "water_hexamer", "water_20mer", "batch64", "served",
                              "trial_response", "gradient", "becke_hexamer", "becke_20mer"],
                     help="batch64: 64 random clusters of 1-30 waters, 1500 points/atom, "
                          "one graph launch per step")
     ap.add_argument("--prec", default="bf16x3", choices=["fp64", "fp32", "bf16x3"],
                     help="arithmetic of the headline path (default: split-BF16 mixed)")
-    ap.add_argument("--compare", default="fp64", choices=["fp64", "fp32", "bf16x3", "none"],
-                    help="also time this precision on the same workload (the 'vs FP64' ratio)")
+    ap.add_argument("--compare", default="fp64,fp32",
+                    help="comma-separated precisions also timed on the same workload, each "
+                         "compared element by element with the FP64 path ('none': no leg)")
+    ap.add_argument("--no-served", action="store_true",
+                    help="skip the served-stream leg of the single-molecule workloads")
+    ap.add_argument("--no-oracle-rows", action="store_true",
+                    help="skip the oracle checks on sampled rows")
     ap.add_argument("--shells", action="store_true",
                     help="store each atom's points in radial-shell order (same sample)")
     ap.add_argument("--screen", type=float, default=0.0,
@@ -484,8 +674,12 @@ def main():
         p = inputs.make_workload(base, weights="becke", radial_order=args.shells)
     else:
         p = inputs.make_workload(args.workload, radial_order=args.shells)
+    compare = [c for c in args.compare.split(",") if c and c != "none" and c != args.prec]
+    for c in compare:
+        if c not in vv10.PRECISIONS:
+            raise SystemExit(f"bench.py: unknown precision {c!r} in --compare")
     if args.screen > 0:
-        args.compare = args.prec          # the comparison leg: unscreened
+        compare = []                      # the comparison leg: the same precision unscreened
     n, na, P = p.n_grid, p.n_atom, p.n_pert
     tuned = {name: autotune.lookup(n, na, name) for name in ("fp64", "fp32", "bf16x3")}
     log(f"workload {args.workload}: N={n} atoms={na} P={P} prec={args.prec}")
@@ -609,8 +803,8 @@ def main():
         "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f32+f64"}[args.prec],
         "data": "synthetic",
         "config": {"workload": args.workload, "n_grid": n, "n_atom": na, "n_pert": P,
-                   "precision": args.prec, "b": p.b, "C": p.C, "seed": p.seed,
-                   "tiles": tuned[args.prec] or "automatic"},
+                   "precision": args.prec, "compared": compare, "b": p.b, "C": p.C,
+                   "seed": p.seed, "tiles": tuned[args.prec] or "automatic"},
         "roofline": roofline,
         "stage_ms": stage_ms,
         "pair_pass": {"kernel": "k_pair" if stage_ms["pair"] > 0 else "k_grid (fused)",
@@ -657,7 +851,28 @@ def main():
                             "note": "value counts every pair; the contraction computed "
                                     "computed_fraction of its (16-point, 16-column) blocks"}
         hs = hess.clone()
-    cmp = None
+
+    def outputs(hh, gg, ee, fr, fg):
+        return dict(hess=hh.cpu().numpy(), grad=gg.cpu().numpy(), energy=ee.item(),
+                    f_rho=fr.cpu().numpy(), f_gamma=fg.cpu().numpy())
+
+    def resp_rows(pr):
+        """Response rows of one untimed call (the inner sums of E_{G,G}), for
+        the element-by-element and oracle-row comparisons."""
+        h = vv10.vv10_prepare(p.b, p.C, n, na, coords, w, atom_of, rho, grad, vv10.PRECISIONS[pr], stream)
+        try:
+            tiles = tuned[pr]
+            if tiles is not None:
+                vv10.vv10_set_tiles(h, *tiles)
+            rr = torch.empty((P, n), dtype=torch.float64, device=dev)
+            rg = torch.empty_like(rr)
+            vv10.vv10_nuclear_terms(h, P, rho_x, grad_x, resp_rho=rr, resp_gamma=rg, w_x=w_x)
+            torch.cuda.synchronize()
+            return rr.cpu().numpy(), rg.cpu().numpy()
+        finally:
+            vv10.vv10_destroy(h)
+
+    results = {args.prec: outputs(hess, gradient, energy, f_rho, f_gamma)}
     if args.screen > 0:
         h2 = torch.empty_like(hess)
         g2 = torch.empty_like(gradient)
@@ -671,44 +886,70 @@ def main():
                                 "screened_contract_ms": stage_ms["contract"],
                                 "hess_change_normwise": float(np.max(np.abs(hs.cpu().numpy() - Hu))
                                                               / np.max(np.abs(Hu)))}
-    elif args.compare != "none" and args.compare != args.prec:
+    for c in compare:
         h2 = torch.empty_like(hess)
         g2 = torch.empty_like(gradient)
         e2 = torch.empty_like(energy)
         fr2, fg2 = torch.empty_like(f_rho), torch.empty_like(f_gamma)
-        dt2, st2 = measure(args.compare, prec=vv10.PRECISIONS[args.compare], hess=h2, gradient=g2,
-                           energy=e2, f_rho=fr2, f_gamma=fg2)
-        cmp = dict(precision=args.compare, ms_per_step=dt2 * 1e3, value=pair_pert / dt2,
-                   stage_ms=st2, hess=h2.cpu().numpy(), energy=e2.item(),
-                   f_rho=fr2.cpu().numpy(), f_gamma=fg2.cpu().numpy())
-        out[f"vs_{args.compare}"] = {"precision": args.compare, "ms_per_step": dt2 * 1e3,
-                                     "value": pair_pert / dt2, "speedup": dt2 / dt,
-                                     "contract_ms": st2["contract"], "stage_ms": st2}
+        dt2, st2 = measure(c, prec=vv10.PRECISIONS[c], hess=h2, gradient=g2, energy=e2,
+                           f_rho=fr2, f_gamma=fg2)
+        results[c] = outputs(h2, g2, e2, fr2, fg2)
+        out[f"vs_{c}"] = {"precision": c, "ms_per_step": dt2 * 1e3, "value": pair_pert / dt2,
+                          "speedup": dt2 / dt, "contract_ms": st2["contract"], "stage_ms": st2}
 
-    # results of the last step, checked against the oracle when it ran in full
-    H = hess.cpu().numpy()
+    # response rows of every path (one untimed call each)
+    if not weighted:
+        for pr in results:
+            results[pr]["resp_rho"], results[pr]["resp_gamma"] = resp_rows(pr)
+        log("response rows of every path done")
+
+    # every mixed output against the FP64 GPU path, element by element
+    if "fp64" in results:
+        ref64 = results["fp64"]
+        for pr, r in results.items():
+            if pr == "fp64":
+                continue
+            e = errors_vs(r, ref64)
+            e["within_stated_bounds"] = bool(
+                e["energy_rel"] <= 1e-6 and e["hess_max_abs"] <= 1e-5
+                and e["f_rho_normwise"] <= 1e-5 and e["f_gamma_normwise"] <= 1e-5
+                and e["grad_normwise"] <= 1e-5)
+            if pr == args.prec:
+                out["errors_vs_fp64"] = e
+            else:
+                out[f"vs_{pr}"]["errors_vs_fp64"] = e
+
+    # results of the last step: properties that hold at any size
+    H = results[args.prec]["hess"]
     out["checks"] = {"hess_symmetric": bool(np.array_equal(H, H.T)),
                      "hess_row_sum_rel": float(np.max(np.abs(H.reshape(P, na, 3).sum(axis=1)))
                                                / np.max(np.abs(H)))}
+    if not args.no_oracle_rows and not weighted:
+        log("oracle rows (three places) running ...")
+        out["errors_vs_oracle_rows"] = oracle_row_checks(p, results)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) running ...")
         cb, ref = cpu_baseline(p)
         out["cpu_baseline"] = cb
         if ref is not None:
-            def errs(e, fr, fg, HH):
+            def errs(r):
                 return {
-                    "energy_rel": abs(e - ref["E"]) / abs(ref["E"]),
-                    "f_rho_normwise": float(np.max(np.abs(fr - ref["f_rho"])) / np.max(np.abs(ref["f_rho"]))),
-                    "f_gamma_normwise": float(np.max(np.abs(fg - ref["f_gamma"])) / np.max(np.abs(ref["f_gamma"]))),
-                    "hess_normwise": float(np.max(np.abs(HH - ref["H"])) / np.max(np.abs(ref["H"]))),
-                    "hess_max_abs": float(np.max(np.abs(HH - ref["H"]))),
+                    "energy_rel": abs(r["energy"] - ref["E"]) / abs(ref["E"]),
+                    "f_rho_normwise": float(np.max(np.abs(r["f_rho"] - ref["f_rho"])) / np.max(np.abs(ref["f_rho"]))),
+                    "f_gamma_normwise": float(np.max(np.abs(r["f_gamma"] - ref["f_gamma"])) / np.max(np.abs(ref["f_gamma"]))),
+                    "hess_normwise": float(np.max(np.abs(r["hess"] - ref["H"])) / np.max(np.abs(ref["H"]))),
+                    "hess_max_abs": float(np.max(np.abs(r["hess"] - ref["H"]))),
                 }
-            out["errors_vs_oracle"] = errs(energy.item(), f_rho.cpu().numpy(), f_gamma.cpu().numpy(), H)
-            if cmp is not None:
-                out[f"vs_{args.compare}"]["errors_vs_oracle"] = errs(cmp["energy"], cmp["f_rho"],
-                                                                      cmp["f_gamma"], cmp["hess"])
+            out["errors_vs_oracle"] = errs(results[args.prec])
+            for c in compare:
+                out[f"vs_{c}"]["errors_vs_oracle"] = errs(results[c])
     else:
         out["cpu_baseline"] = None
+    if not args.no_served and args.screen == 0 and not weighted:
+        log("served stream running ...")
+        rec = served_stream(args, torch, np, inputs, vv10)
+        out["latency_s"] = rec["latency_s"]
+        out["served"] = rec
     print(json.dumps(out), flush=True)
 
 

@@ -51,6 +51,7 @@ def _load():
         _lib.oracle_energy_potential.argtypes = [i64, P, P, P, P, d, d, P, P, P, P]
         _lib.oracle_second_matrices.argtypes = [i64, P, P, P, P, d, d, P, P, P, P]
         _lib.oracle_response_rows.argtypes = [i64, i64, i64, P, P, P, P, d, d, i32, P, P, P, P]
+        _lib.oracle_potential_rows.argtypes = [i64, i64, i64, P, P, P, P, d, d, P, P, P]
         _lib.oracle_grid_vectors.argtypes = [i64, i32, P, P, P, P, P, d, d, P, P, P]
         _lib.oracle_grid_D.restype = ctypes.c_int
         _lib.oracle_grid_D.argtypes = [i64, i32, i64, i32, P, P, P, P, P, d, d, P]
@@ -124,6 +125,20 @@ def energy_potential(coords, w, rho, gam, b, C, with_integrals=False):
     if with_integrals:
         return float(e[0]), fr, fg, ints
     return float(e[0]), fr, fg
+
+
+def potential_rows(i0, i1, coords, w, rho, gam, b, C):
+    """f^rho_i, f^gamma_i and the six inner integrals [6, k] of the rows
+    i0 <= i < i1 only (Section II.A): O(k N) work, for sampled checks of
+    large grids."""
+    c, w, r, g = map(_f64, (coords, w, rho, gam))
+    n = w.shape[0]
+    ints = np.zeros((6, n))
+    fr = np.zeros(n)
+    fg = np.zeros(n)
+    _load().oracle_potential_rows(i0, i1, n, _ptr(c), _ptr(w), _ptr(r), _ptr(g), b, C,
+                                  _ptr(ints), _ptr(fr), _ptr(fg))
+    return fr[i0:i1], fg[i0:i1], ints[:, i0:i1]
 
 
 def second_matrices(coords, w, rho, gam, b, C):

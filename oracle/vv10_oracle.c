@@ -144,11 +144,12 @@ static pair_t pair_terms(const double *ri, const double *rj, const double *pti,
 /* (Section II.B), all six as plain sums over every j.                 */
 /* out is [6][n] in the order E, U, W, A, B, C.                        */
 /* ------------------------------------------------------------------ */
-static void pair_integrals_pt(int64_t n, const double *coords, const double *w,
-                              const double *rho, const double *pt, double *out)
+static void pair_integrals_rows(int64_t i0, int64_t i1, int64_t n, const double *coords,
+                                const double *w, const double *rho, const double *pt,
+                                double *out)
 {
 #pragma omp parallel for schedule(static)
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t i = i0; i < i1; ++i) {
         double E = 0, U = 0, W = 0, A = 0, B = 0, Cc = 0;
         for (int64_t j = 0; j < n; ++j) {
             pair_t p = pair_terms(coords + 3 * i, coords + 3 * j, pt + PT_N * i, pt + PT_N * j);
@@ -165,6 +166,12 @@ static void pair_integrals_pt(int64_t n, const double *coords, const double *w,
         out[0 * n + i] = E; out[1 * n + i] = U; out[2 * n + i] = W;
         out[3 * n + i] = A; out[4 * n + i] = B; out[5 * n + i] = Cc;
     }
+}
+
+static void pair_integrals_pt(int64_t n, const double *coords, const double *w,
+                              const double *rho, const double *pt, double *out)
+{
+    pair_integrals_rows(0, n, n, coords, w, rho, pt, out);
 }
 
 void oracle_pair_integrals(int64_t n, const double *coords, const double *w,
@@ -202,6 +209,25 @@ void oracle_energy_potential(int64_t n, const double *coords, const double *w,
     }
     *energy = e;
     if (!ints) free(I);
+    free(pt);
+}
+
+/* The potential of rows i in [i0, i1) only (each row needs its own     */
+/* inner integrals, a sum over every j): f^rho_i, f^gamma_i and the      */
+/* integrals [6][n], those rows set.                                     */
+void oracle_potential_rows(int64_t i0, int64_t i1, int64_t n, const double *coords,
+                           const double *w, const double *rho, const double *gamma, double b,
+                           double C, double *ints, double *f_rho, double *f_gamma)
+{
+    double *pt = all_points(n, rho, gamma, b, C);
+    pair_integrals_rows(i0, i1, n, coords, w, rho, pt, ints);
+    double beta = oracle_beta(b);
+    for (int64_t i = i0; i < i1; ++i) {
+        double Ei = ints[i], Ui = ints[n + i], Wi = ints[2 * n + i];
+        const double *q = pt + PT_N * i;
+        f_rho[i] = beta + Ei + rho[i] * (q[PT_KAPPA_R] * Ui + q[PT_OMEGA_R] * Wi);
+        f_gamma[i] = rho[i] * q[PT_OMEGA_G] * Wi;
+    }
     free(pt);
 }
 
@@ -313,7 +339,8 @@ void oracle_response_rows(int64_t i0, int64_t i1, int64_t n, const double *coord
 {
     double *pt = all_points(n, rho, gamma, b, C);
     double *I = (double *)malloc(sizeof(double) * 6 * (size_t)n);
-    pair_integrals_pt(n, coords, w, rho, pt, I);
+    /* the local bracket of row i needs row i's integrals only */
+    pair_integrals_rows(i0, i1, n, coords, w, rho, pt, I);
     response_rows(i0, i1, n, coords, w, rho, pt, I, n_pert, rho_x, gamma_x, Yr, Yg);
     free(I);
     free(pt);

@@ -2,6 +2,8 @@
 //
 // 1. k_resp, one wave per point i, lanes over the perturbations x:
 //      Y = sum of the contraction's j-split partials (split order, FP64)
+//          plus the self pair j = i, which the contraction leaves out:
+//          Y_p += K_pp(i, i) p_i in FP64
 //      Yr = Y_p + rho omega_r Y_q + loc_rho,   Yg = rho omega_g Y_q + loc_gamma
 //    (the paper's inner sums sum_j w_j (f^{rho rho}_ij rho^x_j + f^{rho gamma}_ij gamma^x_j)
 //    and sum_j w_j (f^{gamma rho}_ij rho^x_j + f^{gamma gamma}_ij gamma^x_j); the local parts are
@@ -102,8 +104,8 @@ struct WeightIn {
 template <typename T, bool WT>
 __global__ __launch_bounds__(256) void k_resp(
     int64_t n, int64_t npad, int32_t P, int32_t Pp, int32_t S, const int32_t *__restrict__ atom_of,
-    const double *__restrict__ F, const double *__restrict__ I, const double *__restrict__ L,
-    const T *Ypart, double *Y, const double *__restrict__ Z, WeightIn<T> wt,
+    const double4 *__restrict__ P1, const double *__restrict__ F, const double *__restrict__ I,
+    const double *__restrict__ L, const T *Ypart, double *Y, const double *__restrict__ Z, WeightIn<T> wt,
     double *__restrict__ resp_rho, double *__restrict__ resp_gamma, double *__restrict__ fock_rho,
     double *__restrict__ fock_gamma) {
     const int lane = threadIdx.x & 63;
@@ -111,6 +113,12 @@ __global__ __launch_bounds__(256) void k_resp(
     if (i >= n) return;
     const PointFields f = point_fields(F, I, npad, i);
     const int A = atom_of[i];
+    // the self pair, left out of the contraction: K_pp p_i (and for the
+    // weight rows (Phi + c Phi_g) v_i, Phi v_i), in FP64
+    const double4 pd = P1[i];
+    const double kself = self_kpp(pd.x, pd.z);
+    const SelfPair sq = self_pair(pd.x);
+    const double kself_pv = sq.phi + pd.z * sq.phig, kself_vv = sq.phi;
     const double *z0 = Z + (i * 2 + 0) * Pp, *z1 = Z + (i * 2 + 1) * Pp;
     const double *ze = WT ? wt.Ze + i * Pp : nullptr;
 
@@ -146,6 +154,7 @@ __global__ __launch_bounds__(256) void k_resp(
             yp += (double)Ypart[s * len + o];
             yq += (double)Ypart[s * len + o + Pp];
         }
+        yp += kself * (f.w * L[o]);
         double Yr, Yg;
         point_response(f, L[o], L[o + Pp], yp, yq, Yr, Yg);
         const int a = x % 3;
@@ -165,6 +174,9 @@ __global__ __launch_bounds__(256) void k_resp(
                 yqv += (double)wt.Ypart[s * lw + ow + Pp];
                 yvv += (double)wt.Ypart[s * lw + ow + 2 * Pp];
             }
+            const double vself = wt.Lw[i * Pp + x] * f.r;   // v_i = w^x_i rho_i
+            ypv += kself_pv * vself;
+            yvv += kself_vv * vself;
             const double o2 = a == 0 ? own2[0] : (a == 1 ? own2[1] : own2[2]);
             const double zev = self ? o2 : ze[x];
             const double wx = wt.Lw[i * Pp + x];
@@ -192,9 +204,9 @@ __global__ __launch_bounds__(256) void k_resp(
 constexpr int TRI = 32, TRX = 64;
 template <typename T>
 __global__ __launch_bounds__(256) void k_trial_resp(
-    int64_t n, int64_t npad, int32_t P, int32_t Pp, int32_t S, const double *__restrict__ F,
-    const double *__restrict__ I, const double *__restrict__ L, const T *__restrict__ Ypart,
-    double *__restrict__ f_rho_t, double *__restrict__ f_gamma_t) {
+    int64_t n, int64_t npad, int32_t P, int32_t Pp, int32_t S, const double4 *__restrict__ P1,
+    const double *__restrict__ F, const double *__restrict__ I, const double *__restrict__ L,
+    const T *__restrict__ Ypart, double *__restrict__ f_rho_t, double *__restrict__ f_gamma_t) {
     __shared__ double sR[TRI][TRX + 1], sG[TRI][TRX + 1];
     const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
     const int64_t i0 = (int64_t)blockIdx.x * TRI;
@@ -210,6 +222,9 @@ __global__ __launch_bounds__(256) void k_trial_resp(
                 yp += (double)Ypart[s * len + o];
                 yq += (double)Ypart[s * len + o + Pp];
             }
+            // the self pair, left out of the contraction (FP64)
+            const double4 pd = P1[i];
+            yp += self_kpp(pd.x, pd.z) * (F[F_W * npad + i] * L[o]);
             point_response(point_fields(F, I, npad, i), L[o], L[o + Pp], yp, yq, Yr, Yg);
         }
         sR[rr][tx] = Yr;
@@ -515,11 +530,11 @@ hipError_t launch_trial_response(vv10_plan *p, double *f_rho_t, double *f_gamma_
     dim3 grid((unsigned)((p->n + TRI - 1) / TRI), (unsigned)((ws.P + TRX - 1) / TRX));
     if (p->prec == VV10_FP64)
         k_trial_resp<double><<<grid, 256, 0, p->stream>>>(
-            p->n, p->npad, ws.P, ws.Pp, ws.jsplit, p->F, p->Ir, ws.L,
+            p->n, p->npad, ws.P, ws.Pp, ws.jsplit, p->P1, p->F, p->Ir, ws.L,
             static_cast<const double *>(ws.Ypart), f_rho_t, f_gamma_t);
     else
         k_trial_resp<float><<<grid, 256, 0, p->stream>>>(
-            p->n, p->npad, ws.P, ws.Pp, ws.jsplit, p->F, p->Ir, ws.L,
+            p->n, p->npad, ws.P, ws.Pp, ws.jsplit, p->P1, p->F, p->Ir, ws.L,
             static_cast<const float *>(ws.Ypart), f_rho_t, f_gamma_t);
     return hipGetLastError();
 }
@@ -535,24 +550,24 @@ hipError_t launch_assemble(vv10_plan *p, const vv10_nuclear_outputs &out, bool w
             const WeightIn<double> wt = {static_cast<const double *>(ww.Ypart), ww.Lw, ww.Ze, ww.Rw};
             if (weighted)
                 k_resp<double, true><<<nb, 256, 0, p->stream>>>(
-                    n, p->npad, ws.P, ws.Pp, ws.jsplit, p->atom_of, p->F, p->I, ws.L,
+                    n, p->npad, ws.P, ws.Pp, ws.jsplit, p->atom_of, p->P1, p->F, p->I, ws.L,
                     static_cast<const double *>(ws.Ypart), ws.Y, ws.Z, wt, out.resp_rho,
                     out.resp_gamma, out.fock_rho, out.fock_gamma);
             else
                 k_resp<double, false><<<nb, 256, 0, p->stream>>>(
-                    n, p->npad, ws.P, ws.Pp, ws.jsplit, p->atom_of, p->F, p->I, ws.L,
+                    n, p->npad, ws.P, ws.Pp, ws.jsplit, p->atom_of, p->P1, p->F, p->I, ws.L,
                     static_cast<const double *>(ws.Ypart), ws.Y, ws.Z, wt, out.resp_rho,
                     out.resp_gamma, out.fock_rho, out.fock_gamma);
         } else {
             const WeightIn<float> wt = {static_cast<const float *>(ww.Ypart), ww.Lw, ww.Ze, ww.Rw};
             if (weighted)
                 k_resp<float, true><<<nb, 256, 0, p->stream>>>(
-                    n, p->npad, ws.P, ws.Pp, ws.jsplit, p->atom_of, p->F, p->I, ws.L,
+                    n, p->npad, ws.P, ws.Pp, ws.jsplit, p->atom_of, p->P1, p->F, p->I, ws.L,
                     static_cast<const float *>(ws.Ypart), ws.Y, ws.Z, wt, out.resp_rho,
                     out.resp_gamma, out.fock_rho, out.fock_gamma);
             else
                 k_resp<float, false><<<nb, 256, 0, p->stream>>>(
-                    n, p->npad, ws.P, ws.Pp, ws.jsplit, p->atom_of, p->F, p->I, ws.L,
+                    n, p->npad, ws.P, ws.Pp, ws.jsplit, p->atom_of, p->P1, p->F, p->I, ws.L,
                     static_cast<const float *>(ws.Ypart), ws.Y, ws.Z, wt, out.resp_rho,
                     out.resp_gamma, out.fock_rho, out.fock_gamma);
         }

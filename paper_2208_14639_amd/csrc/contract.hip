@@ -94,6 +94,9 @@ __device__ __forceinline__ void tile_f64(int64_t npad, int64_t jlen, int32_t Pp,
             *reinterpret_cast<double2 *>(sX + row * NC + 2 * cc) = v;
         }
         __syncthreads();
+        // the chunk that holds this wave's outer points leaves out the self pair
+        const bool diag = ibase < j0 + kJC && ibase + 16 > j0;
+        const int dself = diag ? (int)(ibase - j0) + m - kq : -1;
 #pragma unroll kJJUnroll
         for (int jj = 0; jj < kJC; jj += 4) {
             const int jl = jj + kq;
@@ -110,7 +113,8 @@ __device__ __forceinline__ void tile_f64(int64_t npad, int64_t jlen, int32_t Pp,
             const double Pgp = -phi * (igp + is);
             const double Pgg = 2.0 * phi * __builtin_fma(ig, igp, is * is);
             const double cj = b1.z;
-            const double kpp = phi + ci * Pg + cj * __builtin_fma(ci, Pgg, Pgp);
+            const double kpp0 = phi + ci * Pg + cj * __builtin_fma(ci, Pgg, Pgp);
+            const double kpp = jj == dself ? 0.0 : kpp0;
             const double kpq = R2 * __builtin_fma(ci, Pgg, Pgp);
             const double kqp = R2 * __builtin_fma(cj, Pgg, Pg);
             const double kqq = R2 * R2 * Pgg;
@@ -214,11 +218,15 @@ __device__ __forceinline__ void tile_f32(int64_t npad, int64_t jlen, int32_t Pp,
             *reinterpret_cast<float4 *>(sX + row * NC + 4 * cc) = v;
         }
         __syncthreads();
+        // the chunk that holds this wave's outer points leaves out the self pair
+        const bool diag = ibase < j0 + kJC && ibase + 16 > j0;
+        const int dself = diag ? (int)(ibase - j0) + m - kq : -1;
 #pragma unroll kJJUnroll
         for (int jj = 0; jj < kJC; jj += 4) {
             const int jl = jj + kq;
             float kpp, kpq, kqp, kqq;
             pair_K(a0, a1, sA[jl], sB[jl], kpp, kpq, kqp, kqq);
+            kpp = jj == dself ? 0.f : kpp;
             const float *xr = sX + (jl * 2) * NC + m;
             const uint32_t mw = SCR ? mask[((j0 + jj) >> 4) * ((Pp >> 4) / NCB) + grp] : 0u;
 #pragma unroll
@@ -294,6 +302,15 @@ __device__ __forceinline__ Aops form_A(const float4 a0, const float4 a1, const f
     A.qh = __builtin_bit_cast(bf16x8, (uint4){qh[0], qh[1], qh[2], qh[3]});
     A.ql = __builtin_bit_cast(bf16x8, (uint4){ql[0], ql[1], ql[2], ql[3]});
     return A;
+}
+
+// Clear K_pp of the self pair in the A operands of the diagonal block (lane
+// (m, g) forms pairs (ibase + m, ibase + 4 g + e), e = 0..3; K_pp is the low
+// half of word e of ph and pl).
+__device__ __forceinline__ void mask_self(Aops &A, int m, int g) {
+    const uint4 k = bf16_clear_mask(g == (m >> 2), m & 3, false);
+    A.ph = bf16_apply_mask(A.ph, k);
+    A.pl = bf16_apply_mask(A.pl, k);
 }
 
 // Software pipeline per wave, one 16-point j block per stage:
@@ -378,6 +395,10 @@ __device__ __forceinline__ void tile_bf16x3(int64_t npad, int64_t jlen, int32_t 
     __syncthreads();
     int buf = 0;
     for (int64_t j0 = jbeg; j0 < jend; j0 += 16) {
+        // the diagonal block: the self pair (i, i) of lane (m, g = m/4) is its
+        // pair m mod 4, whose K_pp (the low half of word m mod 4 of ph, pl) is
+        // cleared; K_pq, K_qp, K_qq vanish there (R = 0)
+        if (j0 == ibase) mask_self(cur, m, g);
         const bool more = j0 + 16 < jend;
         if (more) load_x(j0 + 16);
         const bf16x8 *hp = sH[buf] + m * 4 + g;
@@ -763,12 +784,30 @@ __global__ __launch_bounds__(256, 2) void k_contract_bf16x3_w(
             A[sb].qh = __builtin_bit_cast(bf16x8, (uint4){nh[sb][0], nh[sb][1], nh[sb][2], nh[sb][3]});
             A[sb].ql = __builtin_bit_cast(bf16x8, (uint4){nl[sb][0], nl[sb][1], nl[sb][2], nl[sb][3]});
         }
-        const bf16x8 wph = __builtin_bit_cast(bf16x8, (uint4){vph[0], vph[1], vph[2], vph[3]});
-        const bf16x8 wpl = __builtin_bit_cast(bf16x8, (uint4){vpl[0], vpl[1], vpl[2], vpl[3]});
+        bf16x8 wph = __builtin_bit_cast(bf16x8, (uint4){vph[0], vph[1], vph[2], vph[3]});
+        bf16x8 wpl = __builtin_bit_cast(bf16x8, (uint4){vpl[0], vpl[1], vpl[2], vpl[3]});
         const bf16x8 wqh = __builtin_bit_cast(bf16x8, (uint4){vqh[0], vqh[1], vqh[2], vqh[3]});
         const bf16x8 wql = __builtin_bit_cast(bf16x8, (uint4){vql[0], vql[1], vql[2], vql[3]});
-        const bf16x8 wvh = __builtin_bit_cast(bf16x8, (uint4){vvh[0], vvh[1], vvh[2], vvh[3]});
-        const bf16x8 wvl = __builtin_bit_cast(bf16x8, (uint4){vvl[0], vvl[1], vvl[2], vvl[3]});
+        bf16x8 wvh = __builtin_bit_cast(bf16x8, (uint4){vvh[0], vvh[1], vvh[2], vvh[3]});
+        bf16x8 wvl = __builtin_bit_cast(bf16x8, (uint4){vvl[0], vvl[1], vvl[2], vvl[3]});
+        if (j0 == (ibase & ~(int64_t)31)) {
+            // the stage that holds the outer points: the self pair (i, i) is
+            // point off = ibase - j0 + m of the stage, formed by lane group
+            // (off mod 16)/4 as main pair off mod 4 of sub-block off/16 (K_pp
+            // cleared) and as weight K entry e = 4 (off/16) + off mod 4 (the
+            // rows r - c_i A and r cleared; -R^2 A vanishes there)
+            const int off = (int)(ibase - j0) + m, sb = off >> 4, jj = off & 3;
+            const bool mine = g == ((off & 15) >> 2);
+            const uint4 km = bf16_clear_mask(mine, jj, false);
+            A[sb].ph = bf16_apply_mask(A[sb].ph, km);
+            A[sb].pl = bf16_apply_mask(A[sb].pl, km);
+            const int e = 4 * sb + jj;
+            const uint4 kw = bf16_clear_mask(mine, e >> 1, e & 1);
+            wph = bf16_apply_mask(wph, kw);
+            wpl = bf16_apply_mask(wpl, kw);
+            wvh = bf16_apply_mask(wvh, kw);
+            wvl = bf16_apply_mask(wvl, kw);
+        }
         const bf16x8 *xb = sX + buf * TOT + m * 4 + g;
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {

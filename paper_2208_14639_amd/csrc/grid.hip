@@ -26,7 +26,9 @@
 //
 // The same pass also accumulates the pair integrals E, U, W, A, B, C of the
 // Hessian call (over every j, the outer point's own atom included), so the
-// pair geometry and its reciprocal are evaluated once per pair.
+// pair geometry and its reciprocal are evaluated once per pair.  The self
+// pair j = i is left out of the loops and added in FP64 (from the FP64
+// point data Pd) by the workgroup whose atom group holds the own atom.
 //
 // One wave per (tile of 64 outer points, group of atoms B); tiles never
 // straddle atoms, so the D sums are plain wave reductions in a fixed order.
@@ -155,8 +157,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     int32_t n_atom, int32_t Pp, int32_t bgroups, int64_t npad, const int64_t *__restrict__ seg,
     const int32_t *__restrict__ tile_i0, const int32_t *__restrict__ tile_n,
     const int32_t *__restrict__ tile_atom, const T4 *__restrict__ P0,
-    const T4 *__restrict__ P1, double *__restrict__ Z, double *__restrict__ Ze,
-    double *__restrict__ Dpart, double *__restrict__ Ipart) {
+    const T4 *__restrict__ P1, const double4 *__restrict__ Pd, double *__restrict__ Z,
+    double *__restrict__ Ze, double *__restrict__ Dpart, double *__restrict__ Ipart) {
     __shared__ T4 sA[TG], sB[TG];
     const int t = blockIdx.x, grp = blockIdx.y, lane = threadIdx.x;
     const int A = tile_atom[t];
@@ -180,11 +182,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
             const int cnt = (int)min((int64_t)TG, je - j0);
             T pc[6] = {};
             if (B == A) {
-                // own atom: pair integrals only (grid-position terms vanish)
+                // own atom: pair integrals only (grid-position terms vanish);
+                // the chunk of the tile's own points leaves out the self pair
+                if (j0 == tile_i0[t]) {
 #pragma unroll 4
-                for (int jj = 0; jj < cnt; ++jj) {
-                    const PairGeo<T> q = pair_geo<T>(a0, a1, sA[jj], sB[jj]);
-                    add_pair_integrals(q, pc);
+                    for (int jj = 0; jj < cnt; ++jj) {
+                        PairGeo<T> q = pair_geo<T>(a0, a1, sA[jj], sB[jj]);
+                        q.p = jj == lane ? T(0) : q.p;
+                        add_pair_integrals(q, pc);
+                    }
+                } else {
+#pragma unroll 4
+                    for (int jj = 0; jj < cnt; ++jj) {
+                        const PairGeo<T> q = pair_geo<T>(a0, a1, sA[jj], sB[jj]);
+                        add_pair_integrals(q, pc);
+                    }
                 }
             } else {
                 T c[16] = {};
@@ -234,9 +246,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
         }
     }
     if (INTS && live) {
+        // the group that holds the own atom adds the self pair in FP64:
+        // E += a Phi, U += -a Phi h, A += 2 a Phi m (W, B, C get none)
+        double self[6] = {0, 0, 0, 0, 0, 0};
+        if (A % bgroups == grp) {
+            const double4 pd = Pd[i];
+            const SelfPair q = self_pair(pd.x);
+            self[0] = pd.y * q.phi;
+            self[1] = -pd.y * q.phi * q.h;
+            self[3] = 2.0 * pd.y * q.phi * q.m;
+        }
         const double sc[6] = {-1.5, 1.5, 1.5, -3.0, -3.0, -3.0};
 #pragma unroll
-        for (int k = 0; k < 6; ++k) Ipart[((int64_t)grp * NI + k) * npad + i] = sc[k] * pint[k];
+        for (int k = 0; k < 6; ++k)
+            Ipart[((int64_t)grp * NI + k) * npad + i] = sc[k] * pint[k] + self[k];
     }
 }
 
@@ -268,7 +291,8 @@ __global__ __launch_bounds__(64) void k_grid_grad(
     int32_t n_atom, int32_t bgroups, int64_t npad, const int64_t *__restrict__ seg,
     const int32_t *__restrict__ tile_i0, const int32_t *__restrict__ tile_n,
     const int32_t *__restrict__ tile_atom, const T4 *__restrict__ P0,
-    const T4 *__restrict__ P1, double *__restrict__ Gpart, double *__restrict__ Ipart) {
+    const T4 *__restrict__ P1, const double4 *__restrict__ Pd, double *__restrict__ Gpart,
+    double *__restrict__ Ipart) {
     __shared__ T4 sA[TG], sB[TG];
     const int t = blockIdx.x, grp = blockIdx.y, lane = threadIdx.x;
     const int A = tile_atom[t];
@@ -300,11 +324,14 @@ __global__ __launch_bounds__(64) void k_grid_grad(
             const int cnt = (int)min((int64_t)TG, je - j0);
             T pc[3] = {}, c[3] = {};
             if (!gsum) {
+                // the chunk of the tile's own points leaves out the self pair
+                const int jself = (B == A && j0 == tile_i0[t]) ? lane : -1;
 #pragma unroll 4
                 for (int jj = 0; jj < cnt; ++jj) {
                     const PairGeo<T> q = pair_geo<T>(a0, a1, sA[jj], sB[jj]);
-                    const T ph = q.p * q.h;
-                    pc[0] += q.p;
+                    const T pj = jj == jself ? T(0) : q.p;
+                    const T ph = pj * q.h;
+                    pc[0] += pj;
                     pc[1] += ph;
                     pc[2] += ph * q.R2;
                 }
@@ -339,9 +366,17 @@ __global__ __launch_bounds__(64) void k_grid_grad(
         }
     }
     if (INTS && live) {
+        // self pair in FP64 (group of the own atom): E += a Phi, U += -a Phi h
+        double self[3] = {0, 0, 0};
+        if (A % bgroups == grp) {
+            const double4 pd = Pd[i];
+            const SelfPair q = self_pair(pd.x);
+            self[0] = pd.y * q.phi;
+            self[1] = -pd.y * q.phi * q.h;
+        }
         const double sc[3] = {-1.5, 1.5, 1.5};
 #pragma unroll
-        for (int k = 0; k < 3; ++k) Ipart[((int64_t)grp * 3 + k) * npad + i] = sc[k] * pint[k];
+        for (int k = 0; k < 3; ++k) Ipart[((int64_t)grp * 3 + k) * npad + i] = sc[k] * pint[k] + self[k];
     }
 }
 
@@ -354,11 +389,11 @@ void grid_terms_launch(vv10_plan *p, double *Ze) {
     if (p->prec == VV10_FP64)
         k_grid<double, double4, INTS, ZE><<<grid, TG, 0, p->stream>>>(
             p->n_atom, ws.Pp, ws.bgroups, p->npad, p->d_seg, p->d_tile_i0, p->d_tile_n,
-            p->d_tile_atom, p->P0, p->P1, ws.Z, Ze, ws.Dpart, ws.Igrp);
+            p->d_tile_atom, p->P0, p->P1, p->P1, ws.Z, Ze, ws.Dpart, ws.Igrp);
     else
         k_grid<float, float4, INTS, ZE><<<grid, TG, 0, p->stream>>>(
             p->n_atom, ws.Pp, ws.bgroups, p->npad, p->d_seg, p->d_tile_i0, p->d_tile_n,
-            p->d_tile_atom, p->P0f, p->P1f, ws.Z, Ze, ws.Dpart, ws.Igrp);
+            p->d_tile_atom, p->P0f, p->P1f, p->P1, ws.Z, Ze, ws.Dpart, ws.Igrp);
 }
 
 template <bool INTS>
@@ -374,11 +409,11 @@ void grid_grad_mode(vv10_plan *p) {
     if (p->prec == VV10_FP64)
         k_grid_grad<double, double4, INTS><<<grid, TG, 0, p->stream>>>(
             p->n_atom, gw.bgroups, p->npad, p->d_seg, p->d_tile_i0, p->d_tile_n, p->d_tile_atom,
-            p->P0, p->P1, gw.Gpart, gw.Igrp);
+            p->P0, p->P1, p->P1, gw.Gpart, gw.Igrp);
     else
         k_grid_grad<float, float4, INTS><<<grid, TG, 0, p->stream>>>(
             p->n_atom, gw.bgroups, p->npad, p->d_seg, p->d_tile_i0, p->d_tile_n, p->d_tile_atom,
-            p->P0f, p->P1f, gw.Gpart, gw.Igrp);
+            p->P0f, p->P1f, p->P1, gw.Gpart, gw.Igrp);
 }
 
 hipError_t launch_grid_terms(vv10_plan *p, double *Ze, int ints_from) {

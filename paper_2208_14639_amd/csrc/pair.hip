@@ -5,7 +5,8 @@
 //   W_i = -sum_j a_j Phi_ij R^2 h_ij
 //   {A,B,C}_i = sum_j 2 a_j Phi_ij (R^2)^{0,1,2} m_ij,
 //                                        m = 1/(g+g')^2 + 1/((g+g')g) + 1/g^2
-// with a_j = w_j rho_j and every j (j = i included).  One lane owns one
+// with a_j = w_j rho_j and every j (j = i included: its term is added in
+// FP64, the loops run over j != i).  One lane owns one
 // outer point i; j points stream through LDS and are read as wave-wide
 // broadcasts.  All 1/g, 1/g', 1/(g+g') come from one reciprocal
 // r = 1/(g g' (g+g')); the loop sums p = a_j r times h, R^2 h and
@@ -22,21 +23,59 @@ namespace {
 
 constexpr int JC = 256;   // j points staged per block step; wave w takes [64 w, 64 w + 64)
 
+// Sums of one wave's 64 j of an LDS chunk.  SELF: the chunk holds the
+// outer points themselves (lane l's own point at jj = jself), whose pair is
+// left out (added in FP64 at the end).
+template <typename T, typename T4, bool HESS, bool SELF>
+__device__ __forceinline__ void pair_run(const T4 a0, const T4 a1, const T4 *s0, const T4 *s1,
+                                         int jbeg, int jself, T *c) {
+#pragma unroll 8
+    for (int jj = jbeg; jj < jbeg + 64; ++jj) {
+        const T4 b0 = s0[jj], b1 = s1[jj];
+        const T dx = a0.x - b0.x, dy = a0.y - b0.y, dz = a0.z - b0.z;
+        const T R2 = dx * dx + dy * dy + dz * dz;
+        const T g = a0.w * R2 + a1.x;
+        const T gp = b0.w * R2 + b1.x;
+        const T s = g + gp, t = g * gp;
+        T r;
+        if constexpr (sizeof(T) == 8) r = rcp64(t * s); else r = rcp32(t * s);
+        T pj = b1.y * r;
+        if (SELF) pj = jj == jself ? T(0) : pj;
+        const T ig = gp * (s * r), is = t * r;
+        const T h = ig + is;
+        const T ph = pj * h;
+        c[0] += pj;
+        c[1] += ph;
+        c[2] += ph * R2;
+        if (HESS) {
+            const T pm = pj * (h * h - is * ig);
+            const T pmR2 = pm * R2;
+            c[3] += pm;
+            c[4] += pmR2;
+            c[5] += pmR2 * R2;
+        }
+    }
+}
+
 // One workgroup = 4 waves sharing 64 outer points (one per lane); each wave
 // takes a quarter of every 256-point j chunk, and the four partial sums are
 // added in wave order at the end.  blockIdx.y selects a contiguous j range
 // (a split); splits write partial integrals [split][6][npad] that
 // k_sum_integrals adds in split order.  Mixed mode evaluates in FP32 and
-// adds each 64-point run into FP64 accumulators.
+// adds each 64-point run into FP64 accumulators.  The self pair is left out
+// of the loops; the split that holds the outer points adds it in FP64 from
+// the FP64 point data Pd (kappa, a = w rho).
 template <typename T, typename T4, bool HESS>
 __global__ __launch_bounds__(256) void k_pair(int64_t npad, int64_t jlen,
                                               const T4 *__restrict__ P0,
                                               const T4 *__restrict__ P1,
+                                              const double4 *__restrict__ Pd,
                                               double *__restrict__ Ipart) {
     __shared__ T4 s0[JC], s1[JC];
     __shared__ double red[4][6][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+    const int64_t tb = (int64_t)blockIdx.x * 64;
+    const int64_t i = tb + lane;
     const int64_t jbeg = (int64_t)blockIdx.y * jlen;
     const int64_t jend = min(npad, jbeg + jlen);
     const T4 a0 = P0[i], a1 = P1[i];
@@ -46,39 +85,18 @@ __global__ __launch_bounds__(256) void k_pair(int64_t npad, int64_t jlen,
         s0[threadIdx.x] = P0[j0 + threadIdx.x];
         s1[threadIdx.x] = P1[j0 + threadIdx.x];
         __syncthreads();
-        T e = 0, uu = 0, ww = 0, aa = 0, bb = 0, cc = 0;
-#pragma unroll 8
-        for (int jj = 64 * wave; jj < 64 * wave + 64; ++jj) {
-            const T4 b0 = s0[jj], b1 = s1[jj];
-            const T dx = a0.x - b0.x, dy = a0.y - b0.y, dz = a0.z - b0.z;
-            const T R2 = dx * dx + dy * dy + dz * dz;
-            const T g = a0.w * R2 + a1.x;
-            const T gp = b0.w * R2 + b1.x;
-            const T s = g + gp, t = g * gp;
-            T r;
-            if constexpr (sizeof(T) == 8) r = rcp64(t * s); else r = rcp32(t * s);
-            const T pj = b1.y * r;
-            const T ig = gp * (s * r), is = t * r;
-            const T h = ig + is;
-            const T ph = pj * h;
-            e += pj;
-            uu += ph;
-            ww += ph * R2;
-            if (HESS) {
-                const T pm = pj * (h * h - is * ig);
-                const T pmR2 = pm * R2;
-                aa += pm;
-                bb += pmR2;
-                cc += pmR2 * R2;
-            }
-        }
-        E += (double)e;
-        U += (double)uu;
-        W += (double)ww;
+        T c[6] = {0, 0, 0, 0, 0, 0};
+        if (j0 + 64 * wave == tb)   // this wave's run holds the outer points
+            pair_run<T, T4, HESS, true>(a0, a1, s0, s1, 64 * wave, 64 * wave + lane, c);
+        else
+            pair_run<T, T4, HESS, false>(a0, a1, s0, s1, 64 * wave, 0, c);
+        E += (double)c[0];
+        U += (double)c[1];
+        W += (double)c[2];
         if (HESS) {
-            A += (double)aa;
-            B += (double)bb;
-            C += (double)cc;
+            A += (double)c[3];
+            B += (double)c[4];
+            C += (double)c[5];
         }
     }
     red[wave][0][lane] = E;
@@ -89,10 +107,21 @@ __global__ __launch_bounds__(256) void k_pair(int64_t npad, int64_t jlen,
     red[wave][5][lane] = C;
     __syncthreads();
     const int nout = HESS ? 6 : 3;
+    // self pair (W, B, C have a factor R^2 and get none): E += a Phi,
+    // U += -a Phi h, A += 2 a Phi m
+    const bool own = tb >= jbeg && tb < jend;
+    double self[6] = {0, 0, 0, 0, 0, 0};
+    if (own) {
+        const double4 pd = Pd[i];
+        const SelfPair q = self_pair(pd.x);
+        self[0] = pd.y * q.phi;
+        self[1] = -pd.y * q.phi * q.h;
+        self[3] = 2.0 * pd.y * q.phi * q.m;
+    }
     for (int k = wave; k < nout; k += 4) {
         const double sc = k == 0 ? -1.5 : (k < 3 ? 1.5 : -3.0);   // E; U, W; A, B, C
         const double v = sc * (red[0][k][lane] + red[1][k][lane] + red[2][k][lane] + red[3][k][lane]);
-        Ipart[((int64_t)blockIdx.y * NI + k) * npad + i] = v;
+        Ipart[((int64_t)blockIdx.y * NI + k) * npad + i] = v + self[k];
     }
 }
 
@@ -180,14 +209,18 @@ hipError_t launch_pair_integrals(vv10_plan *p, bool hessian_mode, double *I_out)
     double *Ipart = S == 1 ? I_out : p->Ipart;
     if (p->prec == VV10_FP64) {
         if (hessian_mode)
-            k_pair<double, double4, true><<<grid, 256, 0, p->stream>>>(p->npad, jlen, p->P0, p->P1, Ipart);
+            k_pair<double, double4, true><<<grid, 256, 0, p->stream>>>(p->npad, jlen, p->P0, p->P1,
+                                                                       p->P1, Ipart);
         else
-            k_pair<double, double4, false><<<grid, 256, 0, p->stream>>>(p->npad, jlen, p->P0, p->P1, Ipart);
+            k_pair<double, double4, false><<<grid, 256, 0, p->stream>>>(p->npad, jlen, p->P0, p->P1,
+                                                                        p->P1, Ipart);
     } else {
         if (hessian_mode)
-            k_pair<float, float4, true><<<grid, 256, 0, p->stream>>>(p->npad, jlen, p->P0f, p->P1f, Ipart);
+            k_pair<float, float4, true><<<grid, 256, 0, p->stream>>>(p->npad, jlen, p->P0f, p->P1f,
+                                                                     p->P1, Ipart);
         else
-            k_pair<float, float4, false><<<grid, 256, 0, p->stream>>>(p->npad, jlen, p->P0f, p->P1f, Ipart);
+            k_pair<float, float4, false><<<grid, 256, 0, p->stream>>>(p->npad, jlen, p->P0f, p->P1f,
+                                                                      p->P1, Ipart);
     }
     if (S > 1) {
         const int nout = hessian_mode ? 6 : 3;

@@ -205,11 +205,17 @@ __global__ __launch_bounds__(256, 2) void k_wcontract(int64_t npad, int64_t jlen
             sX[e] = X[(j0 + row) * Pp + col0 + cc];
         }
         __syncthreads();
+        // the chunk that holds this wave's outer points leaves out the self
+        // pair (its rows Phi + c_i Phi_g and Phi; R^2 Phi_g vanishes there)
+        const bool diag = ibase < j0 + kJC && ibase + 16 > j0;
+        const int dself = diag ? (int)(ibase - j0) + m - kq : -1;
 #pragma unroll 2
         for (int jj = 0; jj < kJC; jj += 4) {
             const int jl = jj + kq;
             T kpv, kqv, kvv;
             pair_w(a0, a1, sA[jl], sB[jl], kpv, kqv, kvv);
+            kpv = jj == dself ? T(0) : kpv;
+            kvv = jj == dself ? T(0) : kvv;
             const T *xr = sX + jl * NC + m;
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) {
@@ -356,6 +362,19 @@ __global__ __launch_bounds__(256, 2) void k_wcontract_bf16x3(int64_t npad, int64
     __syncthreads();
     int buf = 0;
     for (int64_t j0 = jbeg; j0 < jend; j0 += 32) {
+        if (j0 == (ibase & ~(int64_t)31)) {
+            // the block that holds the outer points: the self pair is point
+            // off = ibase - j0 + m of the block, K entry e = (off mod 16) mod 4
+            // + 4 (off/16) of lane group (off mod 16)/4; its rows r - c_i A
+            // and r are cleared (-R^2 A vanishes there)
+            const int off = (int)(ibase - j0) + m;
+            const int e = (off & 3) + ((off >> 4) << 2);
+            const uint4 k = bf16_clear_mask(g == ((off & 15) >> 2), e >> 1, e & 1);
+            cur.ph = bf16_apply_mask(cur.ph, k);
+            cur.pl = bf16_apply_mask(cur.pl, k);
+            cur.vh = bf16_apply_mask(cur.vh, k);
+            cur.vl = bf16_apply_mask(cur.vl, k);
+        }
         const bool more = j0 + 32 < jend;
         if (more) load_x(j0 + 32);
         const WAops nxt = form_wA(a0, a1, n0, nk);

@@ -441,6 +441,58 @@ def make_problem(n_water: int, n_pa: int, seed: int, with_derivatives=True,
                          weight_hessian)
 
 
+def device_fields(mol: Molecule, atom_of, coords, torch, device):
+    """rho [N], grad rho [N, 3], rho^x [P, N] and (grad rho)^x [P, N, 3] of
+    the model density evaluated with torch on `device` (the same formulas as
+    model_density and density_derivatives; a GPU builds a large problem in
+    milliseconds).  atom_of and coords are host arrays."""
+    f64 = torch.float64
+    X = torch.as_tensor(np.ascontiguousarray(coords), dtype=f64).to(device)
+    own_of = torch.as_tensor(np.asarray(atom_of, dtype=np.int64)).to(device)
+    n, na = X.shape[0], mol.n_atom
+    eye = torch.eye(3, dtype=f64, device=device)
+    terms = []
+    rho = torch.zeros(n, dtype=f64, device=device)
+    grad = torch.zeros((n, 3), dtype=f64, device=device)
+    hess = torch.zeros((n, 3, 3), dtype=f64, device=device)
+    for A in range(na):
+        z = float(mol.zeta[A])
+        d = X - torch.as_tensor(mol.R[A], dtype=f64, device=device)
+        r = torch.clamp(torch.linalg.vector_norm(d, dim=1), min=1e-300)
+        f = float(mol.Z[A]) * z ** 3 / math.pi * torch.exp(-2.0 * z * r)
+        u = d / r[:, None]
+        g = (-2.0 * z * f)[:, None] * u
+        uu = u[:, :, None] * u[:, None, :]
+        H = f[:, None, None] * (4.0 * z * z * uu - (2.0 * z / r)[:, None, None] * (eye - uu))
+        rho += f
+        grad += g
+        hess += H
+        terms.append((g, H))
+    rho_x = torch.empty((3 * na, n), dtype=f64, device=device)
+    grad_x = torch.empty((3 * na, n, 3), dtype=f64, device=device)
+    for A, (gA, HA) in enumerate(terms):
+        own = (own_of == A).to(f64)
+        for a in range(3):
+            rho_x[3 * A + a] = -gA[:, a] + own * grad[:, a]
+            grad_x[3 * A + a] = -HA[:, a, :] + own[:, None] * hess[:, a, :]
+    return rho, grad, rho_x, grad_x
+
+
+def make_problem_on_device(n_water: int, n_pa: int, seed: int, torch, device) -> Problem:
+    """make_problem's molecule and grid (same seed, same sample) with the
+    density and its nuclear derivatives built on `device` (device_fields):
+    rho, grad_rho, rho_x and grad_rho_x are torch tensors there; coords,
+    weights and atom_of stay host arrays."""
+    rng = np.random.default_rng(seed)
+    mol = water_cluster(n_water, rng)
+    atom_of, offsets, radii = atom_grid(mol.n_atom, n_pa, rng)
+    coords = np.ascontiguousarray(mol.R[atom_of] + offsets)
+    rho, grad, rho_x, grad_x = device_fields(mol, atom_of, coords, torch, device)
+    return Problem(mol=mol, atom_of=np.ascontiguousarray(atom_of, dtype=np.int32),
+                   offsets=offsets, coords=coords, weights=grid_weights(radii), rho=rho,
+                   grad_rho=grad, radii=radii, rho_x=rho_x, grad_rho_x=grad_x, seed=seed)
+
+
 def make_workload(name: str, with_derivatives=True, weights: str = "atomic",
                   radial_order: bool = False) -> Problem:
     cfg = WORKLOADS[name]

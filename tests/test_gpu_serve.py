@@ -1,12 +1,26 @@
 """Continuous batching on the GPU: every result is identical alone and in
 the mix (each request has its own plan and workspace; same kernels, same
-tiles), requests overlap, and the budget holds."""
+tiles), every served result meets the mixed bounds against the FP64
+oracle (energy, Hessian terms, gradient, trial response: Sections II.A and
+II.B), requests overlap, and the budget holds."""
 import sys
 
 import numpy as np
 import pytest
 
+import oracle
+from gpu_util import normwise, relerr
 from paper_2208_14639_amd import inputs
+
+E_REL, H_ABS, V_NORM, R_NORM = 1e-6, 1e-5, 1e-5, 5e-5
+
+
+def _oracle_hessian(p):
+    g, gx = oracle.problem_inputs(p)
+    H0, _ = oracle.hessian_terms(p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b, p.C,
+                                 p.rho_x, gx)
+    e0, _, _ = oracle.energy_potential(p.coords, p.weights, p.rho, g, p.b, p.C)
+    return e0, H0
 
 pytestmark = pytest.mark.gpu
 
@@ -30,10 +44,15 @@ def test_served_results_equal_alone():
     order = [0, 1, 2, 3, 4, 0, 2, 1, 3, 4, 0]
     futs = [srv.submit(Request(k, f"m{m}", pool[m]), at=0.0005 * k) for k, m in enumerate(order)]
     srv.run_until_idle(timeout_s=120)
+    ref = {m: _oracle_hessian(pool[m]) for m in set(order)}
     for k, m in enumerate(order):
         e, H = futs[k].result()
         assert e == alone[m][0]
         assert np.array_equal(H, alone[m][1])
+        # the served result against the oracle, not only against itself alone
+        e0, H0 = ref[m]
+        assert relerr(e, e0) <= E_REL, (k, m, relerr(e, e0))
+        assert np.max(np.abs(H - H0)) <= H_ABS, (k, m, np.max(np.abs(H - H0)))
     st = srv.stats()
     print("served stats", st, file=sys.stderr, flush=True)
     assert st["completed"] == len(order)
@@ -74,10 +93,26 @@ def test_served_kinds_equal_alone():
     srv.run_until_idle(timeout_s=120)
     hessian_before = set()
     for f, (m, kind) in zip(futs, plan):
+        p = pool[m]
+        g, gx = oracle.problem_inputs(p)
         if kind == "hessian":
             hessian_before.add(m)
+            e, H = f.result()
+            e0, H0 = _oracle_hessian(p)
+            assert relerr(e, e0) <= E_REL and np.max(np.abs(H - H0)) <= H_ABS, m
             continue
         got = f.result()
+        # the served result against the oracle
+        if kind == "gradient":
+            G0 = oracle.gradient(p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b, p.C,
+                                 p.rho_x, gx)
+            e0, _, _ = oracle.energy_potential(p.coords, p.weights, p.rho, g, p.b, p.C)
+            assert relerr(got[0], e0) <= E_REL and normwise(got[1], G0) <= V_NORM, m
+        else:
+            rt, gt = trial[m]
+            Yr, Yg = oracle.response_rows(0, p.n_grid, p.coords, p.weights, p.rho, g, p.b, p.C,
+                                          rt, oracle.gamma_x(p.grad_rho, gt))
+            assert normwise(got[0], Yr) <= R_NORM and normwise(got[1], Yg) <= R_NORM, m
         for a, b in zip(got, alone[m, kind]):
             a, b = np.asarray(a), np.asarray(b)
             if kind == "gradient" and m in hessian_before:

@@ -182,3 +182,18 @@ def test_becke_sparse_and_general_paths_agree(becke_dimer):
     assert np.max(np.abs(w1 - w2)) <= 1e-14 * np.max(np.abs(w2))
     assert np.max(np.abs(wx1 - wx2)) <= 1e-13 * np.max(np.abs(wx2))
     assert np.array_equal(wx2, p.w_x) or np.max(np.abs(wx2 - p.w_x)) <= 1e-13 * np.max(np.abs(wx2))
+
+
+def test_device_fields_match_host_generator():
+    """The torch builder of the density and its nuclear derivatives (run here
+    on the CPU) agrees with the numpy one on the same molecule and grid."""
+    import torch
+    p = inputs.make_problem(2, 40, 91)
+    q = inputs.make_problem_on_device(2, 40, 91, torch, torch.device("cpu"))
+    assert np.array_equal(p.coords, q.coords) and np.array_equal(p.weights, q.weights)
+    assert np.array_equal(p.atom_of, q.atom_of)
+    for a, b in ((p.rho, q.rho), (p.grad_rho, q.grad_rho), (p.rho_x, q.rho_x),
+                 (p.grad_rho_x, q.grad_rho_x)):
+        b = b.numpy()
+        assert a.shape == b.shape
+        assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(a))

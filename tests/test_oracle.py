@@ -564,3 +564,22 @@ def test_weight_integrals_row_range(small_dimer):
     part = oracle.weight_integrals(p.coords, p.rho, g, p.b, p.C, wx, 17, 40)
     for a, b in zip(full, part):
         assert np.array_equal(a[:, 17:40], b)
+
+
+def test_row_ranges_match_full_passes(small_dimer):
+    """The row-range entry points (used to check large grids on sampled rows)
+    give the same rows as the whole-grid evaluations: potential and inner
+    integrals, and response rows from a middle range."""
+    p = small_dimer
+    g, gx = oracle.problem_inputs(p)
+    e, fr, fg, ints = oracle.energy_potential(p.coords, p.weights, p.rho, g, p.b, p.C,
+                                              with_integrals=True)
+    i0, i1 = 101, 137
+    fr2, fg2, ints2 = oracle.potential_rows(i0, i1, p.coords, p.weights, p.rho, g, p.b, p.C)
+    assert np.array_equal(fr2, fr[i0:i1]) and np.array_equal(fg2, fg[i0:i1])
+    assert np.array_equal(ints2, ints[:, i0:i1])
+    Yr, Yg = oracle.response_rows(0, p.n_grid, p.coords, p.weights, p.rho, g, p.b, p.C,
+                                  p.rho_x, gx)
+    Yr2, Yg2 = oracle.response_rows(i0, i1, p.coords, p.weights, p.rho, g, p.b, p.C,
+                                    p.rho_x, gx)
+    assert np.array_equal(Yr2, Yr[:, i0:i1]) and np.array_equal(Yg2, Yg[:, i0:i1])
