@@ -215,6 +215,48 @@ vv10_status vv10_hessian_terms(vv10_plan *plan, int32_t n_pert, const double *rh
 vv10_status vv10_gradient(vv10_plan *plan, int32_t n_pert, const double *rho_x,
                           const double *grad_rho_x, const double *w_x, double *grad);
 
+/*
+ * vv10_energy_potential_noalloc -- for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): vv10_prepare + vv10_energy_potential + vv10_destroy as
+ * one call that allocates nothing and never synchronises.  Same inputs as
+ * vv10_prepare, same outputs as vv10_energy_potential (bitwise: the same
+ * kernels and launch shapes run).
+ *
+ * Its working memory (packed point data, per-point fields, pair integrals,
+ * reduction scratch, validation flag) is one library-owned device array of
+ * VV10_NOALLOC_SCRATCH_BYTES on each device the call runs on, held until the
+ * process ends.  Grids that need more (vv10_noalloc_bytes) are rejected with
+ * VV10_E_ARG before any work; the limit is about 250000 points.  All calls on
+ * one device share that array: calls that overlap in time on one device
+ * (several streams, several host threads) race and must be ordered by the
+ * caller.  The first call on a device resolves the array's address (a HIP
+ * symbol query, not an allocation).
+ *
+ *  params, n_grid, n_atom, coords, weights, atom_of, rho, grad_rho, prec,
+ *  stream     as vv10_prepare (DEVICE inputs; the call is asynchronous on
+ *             `stream`).
+ *  energy     [1] DEVICE output (required); f_rho, f_gamma [N] DEVICE or NULL.
+ *  status     [1] DEVICE int32 or NULL: receives VV10_OK, or the status
+ *             vv10_prepare would return for invalid inputs (VV10_E_DENSITY,
+ *             VV10_E_GRID_ORDER, VV10_E_ARG), in which case nothing was
+ *             written to energy, f_rho, f_gamma.
+ * Errors (returned): VV10_E_ARG (null pointer, bad size or parameters, grid
+ * larger than the scratch), VV10_E_HIP (launch or symbol query failed).
+ */
+#define VV10_NOALLOC_SCRATCH_BYTES (64u << 20)
+vv10_status vv10_energy_potential_noalloc(const vv10_params *params, int64_t n_grid,
+                                          int32_t n_atom, const double *coords,
+                                          const double *weights, const int32_t *atom_of,
+                                          const double *rho, const double *grad_rho,
+                                          vv10_precision prec, hipStream_t stream,
+                                          double *energy, double *f_rho, double *f_gamma,
+                                          int32_t *status);
+
+/* Bytes of the scratch array vv10_energy_potential_noalloc needs for a grid
+ * (at most VV10_NOALLOC_SCRATCH_BYTES is available); 0 for invalid sizes. */
+size_t vv10_noalloc_bytes(int64_t n_grid, int32_t n_atom);
+
 /* Largest n_t accepted by vv10_trial_response. */
 #define VV10_MAX_TRIAL 65536
 

@@ -149,8 +149,10 @@ __global__ __launch_bounds__(256) void k_potential(int64_t n, int64_t npad, doub
                                                    const double *__restrict__ I,
                                                    double *__restrict__ f_rho,
                                                    double *__restrict__ f_gamma,
-                                                   double *__restrict__ epart) {
+                                                   double *__restrict__ epart,
+                                                   const int32_t *__restrict__ valid) {
     __shared__ double s[256];
+    if (valid && *valid != 0) return;   // invalid inputs: no output is written
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     double e = 0.0;
     if (i < n) {
@@ -176,8 +178,10 @@ __global__ __launch_bounds__(256) void k_potential(int64_t n, int64_t npad, doub
 
 // Sum of the block partials in block order (one block).
 __global__ __launch_bounds__(256) void k_sum_partials(int64_t nb, const double *__restrict__ part,
-                                                      double *__restrict__ out) {
+                                                      double *__restrict__ out,
+                                                      const int32_t *__restrict__ valid) {
     __shared__ double s[256];
+    if (valid && *valid != 0) return;
     double a = 0.0;
     // each thread sums a contiguous run so the order is fixed
     const int64_t per = (nb + 255) / 256;
@@ -230,12 +234,13 @@ hipError_t launch_pair_integrals(vv10_plan *p, bool hessian_mode, double *I_out)
     return hipGetLastError();
 }
 
-hipError_t launch_potential(vv10_plan *p, double *energy, double *f_rho, double *f_gamma) {
+hipError_t launch_potential(vv10_plan *p, double *energy, double *f_rho, double *f_gamma,
+                            const int32_t *valid) {
     const int64_t nb = p->npad / 256;
     double *epart = p->red;               // [nb] partials, then the energy at red[nb]
     k_potential<<<(unsigned)nb, 256, 0, p->stream>>>(p->n, p->npad, p->beta, p->P1, p->F, p->I,
-                                                     f_rho, f_gamma, epart);
-    k_sum_partials<<<1, 256, 0, p->stream>>>(nb, epart, energy ? energy : p->red + nb);
+                                                     f_rho, f_gamma, epart, valid);
+    k_sum_partials<<<1, 256, 0, p->stream>>>(nb, epart, energy ? energy : p->red + nb, valid);
     return hipGetLastError();
 }
 

@@ -73,6 +73,12 @@ size_t workspace_bytes(int64_t npad, int32_t n_atom, int32_t ntiles, vv10_precis
     return b;
 }
 
+size_t reduction_doubles(int64_t npad) {
+    // the coordinate partial sums of 64 blocks and the centroid, or the
+    // energy's block partials and the energy
+    return std::max<size_t>((size_t)(npad / 256) + 2, 3 * 64 + 3);
+}
+
 size_t response_bytes(int64_t npad, vv10_precision prec, const Workspace &ws) {
     const size_t ch = (size_t)npad * 2 * ws.Pp;
     size_t b = ch * sizeof(double);                           // L
@@ -86,11 +92,6 @@ size_t response_bytes(int64_t npad, vv10_precision prec, const Workspace &ws) {
 
 namespace {
 
-constexpr int kCentroidBlocks = 64;
-
-size_t reduction_doubles(int64_t npad) {
-    return std::max<size_t>((size_t)(npad / 256) + 2, 3 * kCentroidBlocks + 3);
-}
 
 size_t base_bytes(int64_t npad, int32_t n_atom, int64_t ntiles_bound) {
     size_t b = 2 * (size_t)npad * sizeof(double4) + 2 * (size_t)npad * sizeof(float4);
@@ -99,7 +100,7 @@ size_t base_bytes(int64_t npad, int32_t n_atom, int64_t ntiles_bound) {
         b += (size_t)vv10::pair_splits(npad) * vv10::NI * npad * sizeof(double);
     b += (size_t)npad * sizeof(int32_t) + (size_t)(n_atom + 1) * sizeof(int64_t);
     b += (size_t)(3 * ntiles_bound + n_atom + 1) * sizeof(int32_t);
-    b += reduction_doubles(npad) * sizeof(double) + (size_t)(n_atom + 2) * sizeof(int32_t);
+    b += vv10::reduction_doubles(npad) * sizeof(double) + (size_t)(n_atom + 2) * sizeof(int32_t);
     return b;
 }
 
@@ -439,7 +440,7 @@ vv10_status vv10_prepare(const vv10_params *params, int64_t n_grid, int32_t n_at
     if (e == hipSuccess && vv10::pair_splits(npad) > 1)
         e = dalloc(&p->Ipart, (size_t)vv10::pair_splits(npad) * vv10::NI * npad);
     if (e == hipSuccess) e = dalloc(&p->atom_of, npad);
-    if (e == hipSuccess) e = dalloc(&p->red, reduction_doubles(npad));
+    if (e == hipSuccess) e = dalloc(&p->red, vv10::reduction_doubles(npad));
     if (e == hipSuccess) e = dalloc(&p->flag, (size_t)n_atom + 2);
     if (e != hipSuccess) {
         vv10_status st = hip_status(e);

@@ -179,13 +179,18 @@ void dev_release_cached();
 
 // j splits of the pair-integral kernel for a padded grid size.
 int pair_splits(int64_t npad);
+// Doubles of a plan's reduction scratch (centroid partials, energy partials).
+size_t reduction_doubles(int64_t npad);
 
 // Kernel launchers (each enqueues on plan->stream and returns hipGetLastError()).
 hipError_t launch_prepare(vv10_plan *p, const double *coords, const double *w,
                           const int32_t *atom_of, const double *rho,
                           const double *grad_rho);
 hipError_t launch_pair_integrals(vv10_plan *p, bool hessian_mode, double *I_out);
-hipError_t launch_potential(vv10_plan *p, double *energy, double *f_rho, double *f_gamma);
+// valid (device, or null): when *valid != 0 (a failed input validation)
+// nothing is written to energy, f_rho, f_gamma.
+hipError_t launch_potential(vv10_plan *p, double *energy, double *f_rho, double *f_gamma,
+                            const int32_t *valid = nullptr);
 // screen: also the block maxima and the contraction mask (ws.bmax etc. allocated).
 hipError_t launch_pert_prep(vv10_plan *p, const Workspace &ws, const double *rho_x,
                             const double *grad_rho_x, bool screen = false);

@@ -24,6 +24,8 @@ VV10_E_OOM = -4
 VV10_E_HIP = -5
 VV10_E_STATE = -6
 
+VV10_NOALLOC_SCRATCH_BYTES = 64 << 20   # static scratch of vv10_energy_potential_noalloc
+
 VV10_FP64 = 0
 VV10_MIXED_FP32 = 1
 VV10_MIXED_BF16X3 = 2
@@ -116,6 +118,11 @@ def load() -> ctypes.CDLL:
     lib.vv10_set_timing_stages.argtypes = [P, ctypes.c_uint32]
     lib.vv10_stage_times.restype = st
     lib.vv10_stage_times.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
+    lib.vv10_energy_potential_noalloc.restype = st
+    lib.vv10_energy_potential_noalloc.argtypes = [ctypes.POINTER(vv10_params), i64, i32, P, P, P,
+                                                  P, P, st, P, P, P, P, P]
+    lib.vv10_noalloc_bytes.restype = ctypes.c_size_t
+    lib.vv10_noalloc_bytes.argtypes = [i64, i32]
     _lib = lib
     return lib
 
@@ -175,6 +182,24 @@ def vv10_energy_potential(plan: int, energy, f_rho=None, f_gamma=None) -> None:
     st = load().vv10_energy_potential(plan, _ptr(energy), _ptr(f_rho), _ptr(f_gamma))
     if st != VV10_OK:
         raise VV10Error(st, "vv10_energy_potential")
+
+
+def vv10_energy_potential_noalloc(b: float, C: float, n_grid: int, n_atom: int, coords, weights,
+                                  atom_of, rho, grad_rho, prec: int, stream, energy, f_rho=None,
+                                  f_gamma=None, status=None) -> None:
+    """vv10_prepare + vv10_energy_potential without device allocation (the
+    library's static scratch array); status: device int32 [1] or None."""
+    prm = vv10_params(b, C)
+    st = load().vv10_energy_potential_noalloc(ctypes.byref(prm), n_grid, n_atom, _ptr(coords),
+                                              _ptr(weights), _ptr(atom_of), _ptr(rho),
+                                              _ptr(grad_rho), prec, _stream(stream), _ptr(energy),
+                                              _ptr(f_rho), _ptr(f_gamma), _ptr(status))
+    if st != VV10_OK:
+        raise VV10Error(st, "vv10_energy_potential_noalloc")
+
+
+def vv10_noalloc_bytes(n_grid: int, n_atom: int) -> int:
+    return int(load().vv10_noalloc_bytes(n_grid, n_atom))
 
 
 def vv10_hessian_terms(plan: int, n_pert: int, rho_x, grad_rho_x, hess, grad=None,
