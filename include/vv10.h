@@ -257,6 +257,11 @@ vv10_status vv10_energy_potential_noalloc(const vv10_params *params, int64_t n_g
  * (at most VV10_NOALLOC_SCRATCH_BYTES is available); 0 for invalid sizes. */
 size_t vv10_noalloc_bytes(int64_t n_grid, int32_t n_atom);
 
+/* Device bytes that vv10_gradient adds to a plan (its tile sums and
+ * per-group pair integrals, and the owner slots of w^x), an upper bound
+ * over devices; 0 for invalid sizes. */
+size_t vv10_gradient_footprint_bytes(int64_t n_grid, int32_t n_atom);
+
 /* Largest n_t accepted by vv10_trial_response. */
 #define VV10_MAX_TRIAL 65536
 

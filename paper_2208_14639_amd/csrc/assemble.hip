@@ -391,6 +391,12 @@ __global__ __launch_bounds__(256) void k_dsum(int32_t n_atom, const int32_t *__r
     if (k >= (int64_t)n_atom * n_atom * 9) return;
     const int A = (int)(k / (9LL * n_atom));
     const int rem = (int)(k - (int64_t)A * 9 * n_atom);   // B * 9 + c
+    // the own-atom slot (B = A) is never formed by the grid pass (its terms
+    // follow from translational invariance in k_finish): zero, not read
+    if (rem / 9 == A) {
+        DS[k] = 0.0;
+        return;
+    }
     double v = 0.0;
 #pragma unroll 8
     for (int t = tile_first[A]; t < tile_first[A + 1]; ++t) v += Dpart[(int64_t)t * n_atom * 9 + rem];

@@ -681,6 +681,17 @@ vv10_status vv10_trial_response(vv10_plan *p, int32_t n_t, const double *rho_t,
     return VV10_OK;
 }
 
+size_t vv10_gradient_footprint_bytes(int64_t n_grid, int32_t n_atom) {
+    if (n_grid < 1 || n_atom < 1) return 0;
+    const int64_t npad = ((n_grid + vv10::kPad - 1) / vv10::kPad) * vv10::kPad;
+    const int64_t ntiles = (n_grid + vv10::kGridTile - 1) / vv10::kGridTile + n_atom;
+    Workspace ws;
+    vv10::plan_workspace_shape(npad, n_atom, (int32_t)ntiles, 256, VV10_FP64, ws);
+    // Gpart [tiles][atoms][3] and Igrp [bgroups][3][npad] (ensure_gradient_work)
+    return ((size_t)ntiles * n_atom * 3 + (size_t)ws.bgroups * 3 * npad) * sizeof(double) +
+           (size_t)npad * 3 * sizeof(double);   // owner slots of w^x (only with weight derivatives)
+}
+
 size_t vv10_response_footprint_bytes(int64_t n_grid, int32_t n_t, vv10_precision prec) {
     if (n_grid < 1 || n_t < 1) return 0;
     const int64_t npad = ((n_grid + vv10::kPad - 1) / vv10::kPad) * vv10::kPad;

@@ -301,10 +301,14 @@ class GpuExecutor:
         prec = self.vv10.PRECISIONS[self.prec]
         return self.vv10.vv10_response_footprint_bytes(n, n_t, prec) + 8 * n * n_t * (4 + 2)
 
+    def _grad_bytes(self, n, na) -> int:
+        return self.vv10.vv10_gradient_footprint_bytes(n, na)
+
     def footprint(self, req) -> int:
         """Device bytes of the molecule's state once it has served `req`: plan
-        and workspace (upper bound), inputs, and for a response the response
-        workspace, trial densities and outputs."""
+        and workspace (upper bound), inputs, and for a gradient the gradient
+        pass's buffers, for a response the response workspace, trial
+        densities and outputs."""
         req = as_request(req)
         problem = req.problem
         n, na = int(problem.n_grid), int(problem.n_atom)
@@ -312,13 +316,20 @@ class GpuExecutor:
         b = self.vv10.vv10_footprint_bytes(n, na, self.vv10.PRECISIONS[self.prec]) + inputs
         if req.kind == "response":
             b += self._resp_bytes(n, req.n_cols)
+        elif req.kind == "gradient":
+            b += self._grad_bytes(n, na)
         return b
 
     def extra_bytes(self, state, req) -> int:
-        """Bytes `req` adds to a resident state (a larger response workspace)."""
-        if req.kind != "response":
-            return 0
-        return max(0, self._resp_bytes(int(req.problem.n_grid), req.n_cols) - state.get("resp_bytes", 0))
+        """Bytes `req` adds to a resident state: a larger response workspace,
+        or the gradient pass's buffers the first time the molecule serves a
+        gradient."""
+        n = int(req.problem.n_grid)
+        if req.kind == "response":
+            return max(0, self._resp_bytes(n, req.n_cols) - state.get("resp_bytes", 0))
+        if req.kind == "gradient" and not state.get("grad_bytes"):
+            return self._grad_bytes(n, int(req.problem.n_atom))
+        return 0
 
     def load(self, mol_id, problem):
         torch = self.torch
@@ -358,6 +369,7 @@ class GpuExecutor:
                 # energy and Hessian terms from one pass over the pairs
                 vv.vv10_nuclear_terms(plan.handle, P, state["rx"], state["gx"], hess=res, energy=e)
             else:
+                state["grad_bytes"] = self._grad_bytes(plan.n, plan.n_atom)
                 vv.vv10_energy_potential(plan.handle, e)
                 vv.vv10_gradient(plan.handle, P, state["rx"], state["gx"], res)
             out.update(e=e, res=res)

@@ -83,6 +83,8 @@ def load() -> ctypes.CDLL:
     lib.vv10_trial_response.argtypes = [P, i32, P, P, P, P]
     lib.vv10_response_footprint_bytes.restype = ctypes.c_size_t
     lib.vv10_response_footprint_bytes.argtypes = [i64, i32, st]
+    lib.vv10_gradient_footprint_bytes.restype = ctypes.c_size_t
+    lib.vv10_gradient_footprint_bytes.argtypes = [i64, i32]
     lib.vv10_destroy.restype = None
     lib.vv10_destroy.argtypes = [P]
     lib.vv10_status_string.restype = ctypes.c_char_p
@@ -236,6 +238,10 @@ def vv10_trial_response(plan: int, n_t: int, rho_t, grad_rho_t, f_rho_t, f_gamma
 
 def vv10_response_footprint_bytes(n_grid: int, n_t: int, prec: int = VV10_FP64) -> int:
     return int(load().vv10_response_footprint_bytes(n_grid, n_t, prec))
+
+
+def vv10_gradient_footprint_bytes(n_grid: int, n_atom: int) -> int:
+    return int(load().vv10_gradient_footprint_bytes(n_grid, n_atom))
 
 
 def vv10_set_tiles(plan: int, jsplit: int = 0, bgroups: int = 0) -> None:
