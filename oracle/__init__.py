@@ -19,7 +19,10 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "vv10_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# VV10_ORACLE_LIBRARY selects another build of the same source (the
+# AddressSanitizer/UBSan build of build_sanitized(), for example)
+_LIB = os.environ.get("VV10_ORACLE_LIBRARY") or os.path.join(_HERE, "liboracle.so")
+SAN_LIB = os.path.join(_HERE, "liboracle_san.so")
 _lib = None
 
 PT_FIELDS = ("omega", "kappa", "omega_r", "omega_g", "kappa_r", "omega_rr",
@@ -33,6 +36,20 @@ def build(force: bool = True) -> str:
         subprocess.run(cmd, check=True)
         os.replace(_LIB + ".tmp", _LIB)
     return _LIB
+
+
+def build_sanitized() -> str:
+    """The oracle built with clang's AddressSanitizer and UndefinedBehavior-
+    Sanitizer (any report aborts), for the host sanitizer run of the CPU
+    test suite; load it with VV10_ORACLE_LIBRARY and the ASan runtime
+    preloaded."""
+    cmd = ["/opt/rocm/llvm/bin/clang", "-O1", "-g", "-fno-omit-frame-pointer",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fopenmp",
+           "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-Wall",
+           "-o", SAN_LIB + ".tmp", _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(SAN_LIB + ".tmp", SAN_LIB)
+    return SAN_LIB
 
 
 def _load():

@@ -14,7 +14,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libvv10.so")
+# VV10_LIBRARY selects another build of the same sources (the host-sanitized
+# libvv10_san.so, for example)
+LIB_PATH = os.environ.get("VV10_LIBRARY") or os.path.join(HERE, "libvv10.so")
 
 VV10_OK = 0
 VV10_E_ARG = -1
