@@ -326,7 +326,7 @@ __device__ __forceinline__ void mask_self(Aops &A, int m, int g) {
 template <int NCB>
 constexpr int smem_bf16x3() { return 2 * 2 * NCB * 16 * 4 * (int)sizeof(bf16x8); }
 
-template <int NCB, bool SCR = false>
+template <int NCB, bool SCR = false, int WAVES = 4>
 __device__ __forceinline__ void tile_bf16x3(int64_t npad, int64_t jlen, int32_t Pp,
                                             const float4 *__restrict__ P0,
                                             const float4 *__restrict__ P1,
@@ -337,13 +337,14 @@ __device__ __forceinline__ void tile_bf16x3(int64_t npad, int64_t jlen, int32_t 
                                             const uint32_t *__restrict__ mask = nullptr) {
     constexpr int NC = NCB * 16;
     constexpr int UNITS = NC * 4;                       // 8-bf16 units per block and array
-    constexpr int PER = (UNITS + 255) / 256;            // units per thread and array
+    constexpr int NT = 64 * WAVES;                      // threads of the workgroup
+    constexpr int PER = (UNITS + NT - 1) / NT;          // units per thread and array
     typedef bf16x8 Buf[UNITS];
     Buf *sH = reinterpret_cast<Buf *>(smem);            // [buffer][col][g]
     Buf *sL = sH + 2;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m = lane & 15, g = lane >> 4;
-    const int64_t ibase = itile * 64 + wave * 16;
+    const int64_t ibase = itile * (16 * WAVES) + wave * 16;
     const int col0 = grp * NC;
     const int64_t jbeg = (int64_t)split * jlen;
     const int64_t jend = min(npad, jbeg + jlen);
@@ -354,13 +355,13 @@ __device__ __forceinline__ void tile_bf16x3(int64_t npad, int64_t jlen, int32_t 
         accp[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
         accq[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
     }
-    // X block staging: thread tid moves units tid + 256 k of the block
+    // X block staging: thread tid moves units tid + NT k of the block
     bf16x8 rh[PER], rl[PER];
     auto load_x = [&](int64_t blk) {
         const int64_t base = ((blk / 16) * Pp + col0) * 4;
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
-            const int e = tid + 256 * k;
+            const int e = tid + NT * k;
             if (e < UNITS) {
                 rh[k] = Xhi[base + e];
                 rl[k] = Xlo[base + e];
@@ -370,7 +371,7 @@ __device__ __forceinline__ void tile_bf16x3(int64_t npad, int64_t jlen, int32_t 
     auto store_x = [&](int buf) {
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
-            const int e = tid + 256 * k;
+            const int e = tid + NT * k;
             if (e < UNITS) {
                 sH[buf][e] = rh[k];
                 sL[buf][e] = rl[k];
@@ -387,6 +388,78 @@ __device__ __forceinline__ void tile_bf16x3(int64_t npad, int64_t jlen, int32_t 
             n1[jj] = P1[jq + jj];
         }
     };
+    if constexpr (!SCR && WAVES == 8) {
+        // Stages of 32 points: the X of two 16-point blocks is staged at
+        // once and the two blocks' MFMAs run between one pair of barriers.
+        // The A operands alternate between two register sets, each formed
+        // while the other's MFMAs run.
+        typedef bf16x8 Buf2[2 * UNITS];                 // [sub-block][col][g]
+        Buf2 *tH = reinterpret_cast<Buf2 *>(smem);      // [buffer]
+        Buf2 *tL = tH + 2;
+        constexpr int PER2 = (2 * UNITS + NT - 1) / NT;
+        bf16x8 sh2[PER2], sl2[PER2];
+        auto load2 = [&](int64_t j) {   // X of points j .. j + 31
+#pragma unroll
+            for (int k = 0; k < PER2; ++k) {
+                const int e = tid + NT * k;
+                if (e < 2 * UNITS) {
+                    const int sub = e >= UNITS;
+                    const int64_t src = ((j / 16 + sub) * Pp + col0) * 4 + (e - sub * UNITS);
+                    sh2[k] = Xhi[src];
+                    sl2[k] = Xlo[src];
+                }
+            }
+        };
+        auto store2 = [&](int b) {
+#pragma unroll
+            for (int k = 0; k < PER2; ++k) {
+                const int e = tid + NT * k;
+                if (e < 2 * UNITS) {
+                    tH[b][e] = sh2[k];
+                    tL[b][e] = sl2[k];
+                }
+            }
+        };
+        auto mfmas = [&](const Aops &A, const bf16x8 *hp, const bf16x8 *lp) {
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                const bf16x8 bh = hp[cb * 64], bl = lp[cb * 64];
+                accp[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.ph, bh, accp[cb], 0, 0, 0);
+                accq[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.qh, bh, accq[cb], 0, 0, 0);
+                accp[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.pl, bh, accp[cb], 0, 0, 0);
+                accq[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.ql, bh, accq[cb], 0, 0, 0);
+                accp[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.ph, bl, accp[cb], 0, 0, 0);
+                accq[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.qh, bl, accq[cb], 0, 0, 0);
+            }
+        };
+        load_pts(jbeg);
+        load2(jbeg);
+        Aops cur = form_A(a0, a1, n0, n1);
+        load_pts(jbeg + 16);
+        store2(0);
+        __syncthreads();
+        int b = 0;
+        // a split holds a whole number of 32-point stages (jbeg and jlen are
+        // multiples of 32, npad of 256)
+        for (int64_t j0 = jbeg; j0 < jend; j0 += 32) {
+            const bool more = j0 + 32 < jend;
+            if (more) load2(j0 + 32);
+            // the diagonal block: the self pair (i, i) of lane (m, g = m/4) is
+            // its pair m mod 4, whose K_pp (the low half of word m mod 4 of ph,
+            // pl) is cleared; K_pq, K_qp, K_qq vanish there (R = 0)
+            if (j0 == ibase) mask_self(cur, m, g);
+            Aops alt = form_A(a0, a1, n0, n1);      // points j0 + 16 ..
+            load_pts(j0 + 32);
+            mfmas(cur, tH[b] + m * 4 + g, tL[b] + m * 4 + g);
+            if (j0 + 16 == ibase) mask_self(alt, m, g);
+            cur = form_A(a0, a1, n0, n1);           // points j0 + 32 ..
+            load_pts(j0 + 48);
+            mfmas(alt, tH[b] + UNITS + m * 4 + g, tL[b] + UNITS + m * 4 + g);
+            if (more) store2(b ^ 1);
+            __syncthreads();
+            b ^= 1;
+        }
+    } else {
     load_pts(jbeg);
     load_x(jbeg);
     Aops cur = form_A(a0, a1, n0, n1);
@@ -460,6 +533,7 @@ __device__ __forceinline__ void tile_bf16x3(int64_t npad, int64_t jlen, int32_t 
         __syncthreads();
         buf ^= 1;
     }
+    }
     float *Yb = Yout + (int64_t)split * npad * 2 * Pp;
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
@@ -498,17 +572,31 @@ __global__ __launch_bounds__(256, 2) void k_contract_f32(int64_t npad, int64_t j
                        mask);
 }
 
+// Waves (16 outer points each) of the standalone split-BF16 kernel, by
+// column blocks: with eight or more blocks the MFMA work per pair dominates
+// and eight waves share each staged X block in 32-point stages (one barrier
+// per two MFMA blocks: 56.5 -> 53.0 ms on the 20-water grid); with fewer,
+// four waves in 16-point stages keep three to four waves per SIMD (the
+// 32-point stages' registers would drop it to two).
+template <int NCB>
+constexpr int bf16_waves() { return NCB >= 8 ? 8 : 4; }
+
+// LDS of the standalone kernel: with eight waves, two 32-point stages
+// (double buffered); with four, two 16-point blocks.
+template <int NCB>
+constexpr int smem_bf16x3_k() { return (bf16_waves<NCB>() == 8 ? 2 : 1) * smem_bf16x3<NCB>(); }
+
 template <int NCB, bool SCR>
-__global__ __launch_bounds__(256, 2) void k_contract_bf16x3(int64_t npad, int64_t jlen, int32_t Pp,
+__global__ __launch_bounds__(64 * bf16_waves<NCB>(), 8 / bf16_waves<NCB>()) void k_contract_bf16x3(int64_t npad, int64_t jlen, int32_t Pp,
                                                             const float4 *__restrict__ P0,
                                                             const float4 *__restrict__ P1,
                                                             const bf16x8 *__restrict__ Xhi,
                                                             const bf16x8 *__restrict__ Xlo,
                                                             float *__restrict__ Yout,
                                                             const uint32_t *__restrict__ mask) {
-    __shared__ __attribute__((aligned(16))) char smem[smem_bf16x3<NCB>()];
-    tile_bf16x3<NCB, SCR>(npad, jlen, Pp, P0, P1, Xhi, Xlo, Yout, blockIdx.x, blockIdx.y,
-                          blockIdx.z, smem, mask);
+    __shared__ __attribute__((aligned(16))) char smem[smem_bf16x3_k<NCB>()];
+    tile_bf16x3<NCB, SCR, bf16_waves<NCB>()>(npad, jlen, Pp, P0, P1, Xhi, Xlo, Yout,
+                                             blockIdx.x, blockIdx.y, blockIdx.z, smem, mask);
 }
 
 template <int NCB, bool SCR>
@@ -529,7 +617,9 @@ hipError_t run_mode(vv10_plan *p, const Workspace &ws) {
     } else {
         const bf16x8 *xh = static_cast<const bf16x8 *>(ws.X);
         const bf16x8 *xl = xh + (size_t)p->npad * ws.Pp * 2 / 8;
-        k_contract_bf16x3<NCB, SCR><<<grid, 256, 0, p->stream>>>(
+        constexpr int W = bf16_waves<NCB>();
+        dim3 gridb((unsigned)(p->npad / (16 * W)), (unsigned)ws.ngroups, (unsigned)ws.jsplit);
+        k_contract_bf16x3<NCB, SCR><<<gridb, 64 * W, 0, p->stream>>>(
             p->npad, ws.jlen, ws.Pp, p->P0f, p->P1f, xh, xl, static_cast<float *>(ws.Ypart), mask);
     }
     return hipGetLastError();
@@ -552,7 +642,9 @@ int occupancy(vv10_precision prec) {
     } else if (prec == VV10_MIXED_FP32) {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_contract_f32<NCB, false>, 256, 0);
     } else {
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_contract_bf16x3<NCB, false>, 256, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_contract_bf16x3<NCB, false>,
+                                                         64 * bf16_waves<NCB>(), 0);
+        nb *= bf16_waves<NCB>() / 4;   // in units of 64-point tiles, as the other modes
     }
     if (e != hipSuccess) {
         (void)hipGetLastError();
