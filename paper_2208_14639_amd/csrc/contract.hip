@@ -334,7 +334,8 @@ __device__ __forceinline__ void tile_bf16x3(int64_t npad, int64_t jlen, int32_t 
                                             const bf16x8 *__restrict__ Xlo,
                                             float *__restrict__ Yout, int64_t itile, int grp,
                                             int split, char *smem,
-                                            const uint32_t *__restrict__ mask = nullptr) {
+                                            const uint32_t *__restrict__ mask = nullptr,
+                                            char *smem2 = nullptr) {
     constexpr int NC = NCB * 16;
     constexpr int UNITS = NC * 4;                       // 8-bf16 units per block and array
     constexpr int NT = 64 * WAVES;                      // threads of the workgroup
@@ -393,30 +394,34 @@ __device__ __forceinline__ void tile_bf16x3(int64_t npad, int64_t jlen, int32_t 
         // once and the two blocks' MFMAs run between one pair of barriers.
         // The A operands alternate between two register sets, each formed
         // while the other's MFMAs run.
+        // The two stage buffers are distinct LDS arrays (smem: buffer 0,
+        // smem2: buffer 1), each hi then lo of two 16-point blocks; with the
+        // stages unrolled in pairs the compiler sees that a stage's LDS reads
+        // and its loads into the other buffer never alias, and waits for
+        // those loads only at the stage's end.
         typedef bf16x8 Buf2[2 * UNITS];                 // [sub-block][col][g]
-        Buf2 *tH = reinterpret_cast<Buf2 *>(smem);      // [buffer]
-        Buf2 *tL = tH + 2;
+        Buf2 &H0 = *reinterpret_cast<Buf2 *>(smem), &L0 = *(reinterpret_cast<Buf2 *>(smem) + 1);
+        Buf2 &H1 = *reinterpret_cast<Buf2 *>(smem2), &L1 = *(reinterpret_cast<Buf2 *>(smem2) + 1);
         constexpr int PER2 = (2 * UNITS + NT - 1) / NT;
-        bf16x8 sh2[PER2], sl2[PER2];
-        auto load2 = [&](int64_t j) {   // X of points j .. j + 31
+        // X of points j .. j + 31 straight from global memory into LDS
+        // (global_load_lds_dwordx4: lane l of a wave writes the 16 bytes at
+        // the wave's LDS base + 16 l, so unit e = tid + NT k lands at unit e)
+        auto load2 = [&](int64_t j, Buf2 &H, Buf2 &L) {
 #pragma unroll
             for (int k = 0; k < PER2; ++k) {
-                const int e = tid + NT * k;
-                if (e < 2 * UNITS) {
+                const int e0 = wave * 64 + NT * k;      // first unit of this wave (uniform)
+                if (e0 < 2 * UNITS) {                    // 2 UNITS is a multiple of 64
+                    const int e = e0 + lane;
                     const int sub = e >= UNITS;
                     const int64_t src = ((j / 16 + sub) * Pp + col0) * 4 + (e - sub * UNITS);
-                    sh2[k] = Xhi[src];
-                    sl2[k] = Xlo[src];
-                }
-            }
-        };
-        auto store2 = [&](int b) {
-#pragma unroll
-            for (int k = 0; k < PER2; ++k) {
-                const int e = tid + NT * k;
-                if (e < 2 * UNITS) {
-                    tH[b][e] = sh2[k];
-                    tL[b][e] = sl2[k];
+                    __builtin_amdgcn_global_load_lds(
+                        static_cast<const void *>(Xhi + src),
+                        reinterpret_cast<__attribute__((address_space(3))) void *>(
+                            reinterpret_cast<uintptr_t>(&H[e0])), 16, 0, 0);
+                    __builtin_amdgcn_global_load_lds(
+                        static_cast<const void *>(Xlo + src),
+                        reinterpret_cast<__attribute__((address_space(3))) void *>(
+                            reinterpret_cast<uintptr_t>(&L[e0])), 16, 0, 0);
                 }
             }
         };
@@ -433,31 +438,33 @@ __device__ __forceinline__ void tile_bf16x3(int64_t npad, int64_t jlen, int32_t 
             }
         };
         load_pts(jbeg);
-        load2(jbeg);
+        load2(jbeg, H0, L0);
         Aops cur = form_A(a0, a1, n0, n1);
         load_pts(jbeg + 16);
-        store2(0);
+        __builtin_amdgcn_s_waitcnt(0);   // this wave's LDS loads are done
         __syncthreads();
-        int b = 0;
-        // a split holds a whole number of 32-point stages (jbeg and jlen are
-        // multiples of 32, npad of 256)
-        for (int64_t j0 = jbeg; j0 < jend; j0 += 32) {
-            const bool more = j0 + 32 < jend;
-            if (more) load2(j0 + 32);
+        // one 32-point stage on buffer (Hc, Lc), loading the next into (Hn, Ln)
+        auto stage = [&](int64_t j0, Buf2 &Hc, Buf2 &Lc, Buf2 &Hn, Buf2 &Ln) {
+            if (j0 + 32 < jend) load2(j0 + 32, Hn, Ln);   // every wave finished reading it
             // the diagonal block: the self pair (i, i) of lane (m, g = m/4) is
             // its pair m mod 4, whose K_pp (the low half of word m mod 4 of ph,
             // pl) is cleared; K_pq, K_qp, K_qq vanish there (R = 0)
             if (j0 == ibase) mask_self(cur, m, g);
             Aops alt = form_A(a0, a1, n0, n1);      // points j0 + 16 ..
             load_pts(j0 + 32);
-            mfmas(cur, tH[b] + m * 4 + g, tL[b] + m * 4 + g);
+            mfmas(cur, Hc + m * 4 + g, Lc + m * 4 + g);
             if (j0 + 16 == ibase) mask_self(alt, m, g);
             cur = form_A(a0, a1, n0, n1);           // points j0 + 32 ..
             load_pts(j0 + 48);
-            mfmas(alt, tH[b] + UNITS + m * 4 + g, tL[b] + UNITS + m * 4 + g);
-            if (more) store2(b ^ 1);
+            mfmas(alt, Hc + UNITS + m * 4 + g, Lc + UNITS + m * 4 + g);
+            __builtin_amdgcn_s_waitcnt(0);   // this wave's LDS loads of the next stage
             __syncthreads();
-            b ^= 1;
+        };
+        // a split holds a whole number of 32-point stages (jbeg and jlen are
+        // multiples of 32, npad of 256)
+        for (int64_t j0 = jbeg; j0 < jend; j0 += 64) {
+            stage(j0, H0, L0, H1, L1);
+            if (j0 + 32 < jend) stage(j0 + 32, H1, L1, H0, L0);
         }
     } else {
     load_pts(jbeg);
@@ -581,11 +588,6 @@ __global__ __launch_bounds__(256, 2) void k_contract_f32(int64_t npad, int64_t j
 template <int NCB>
 constexpr int bf16_waves() { return NCB >= 8 ? 8 : 4; }
 
-// LDS of the standalone kernel: with eight waves, two 32-point stages
-// (double buffered); with four, two 16-point blocks.
-template <int NCB>
-constexpr int smem_bf16x3_k() { return (bf16_waves<NCB>() == 8 ? 2 : 1) * smem_bf16x3<NCB>(); }
-
 template <int NCB, bool SCR>
 __global__ __launch_bounds__(64 * bf16_waves<NCB>(), 8 / bf16_waves<NCB>()) void k_contract_bf16x3(int64_t npad, int64_t jlen, int32_t Pp,
                                                             const float4 *__restrict__ P0,
@@ -594,9 +596,12 @@ __global__ __launch_bounds__(64 * bf16_waves<NCB>(), 8 / bf16_waves<NCB>()) void
                                                             const bf16x8 *__restrict__ Xlo,
                                                             float *__restrict__ Yout,
                                                             const uint32_t *__restrict__ mask) {
-    __shared__ __attribute__((aligned(16))) char smem[smem_bf16x3_k<NCB>()];
+    __shared__ __attribute__((aligned(16))) char smem[smem_bf16x3<NCB>()];
+    // the second stage buffer of the eight-wave form (a one-byte dummy otherwise)
+    __shared__ __attribute__((aligned(16))) char smem2[bf16_waves<NCB>() == 8 ? smem_bf16x3<NCB>() : 1];
     tile_bf16x3<NCB, SCR, bf16_waves<NCB>()>(npad, jlen, Pp, P0, P1, Xhi, Xlo, Yout,
-                                             blockIdx.x, blockIdx.y, blockIdx.z, smem, mask);
+                                             blockIdx.x, blockIdx.y, blockIdx.z, smem, mask,
+                                             smem2);
 }
 
 template <int NCB, bool SCR>
