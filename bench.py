@@ -292,8 +292,9 @@ def bench_batch(args, torch, np, inputs, vv10):
                    "precision": args.prec, "work_items": n_items, "persistent_workgroups": n_wg},
         "roofline": None, "cpu_baseline": None,
     }
-    # every molecule against the FP64 path (the same batch, one untimed launch)
-    if args.prec != "fp64":
+    # every molecule against the FP64 path (the same batch, one untimed launch;
+    # --compare none skips it, e.g. for a kernel profile of the timed path alone)
+    if args.prec != "fp64" and args.compare != "none":
         with vv10.Batch(probs, prec="fp64", tiles="auto") as b:
             t0 = time.perf_counter()
             b.run()

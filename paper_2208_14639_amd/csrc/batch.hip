@@ -2,11 +2,12 @@
 //
 // Every molecule keeps its own plan and workspace (prepared and validated
 // eagerly).  vv10_batch_run captures, once, one HIP graph:
-//   fork -> per molecule: grid terms + pair integrals, potential and energy,
-//           perturbation packing (independent branches on side streams)
-//   join -> one persistent contraction kernel over the work list of all
-//           molecules (largest items first)
-//   fork -> per molecule: Hessian assembly -> join
+//   fork -> per molecule: perturbation packing (branches on side streams)
+//   join -> one persistent kernel over the work list of all molecules: the
+//           grid-pass items (grid-position intermediates with the pair
+//           integrals), then the contraction items, each kind largest first
+//   fork -> per molecule: pair integrals summed over atom groups, potential
+//           and energy, Hessian assembly -> join
 // and replays it while the caller's pointers stay the same.
 #include <algorithm>
 #include <new>
@@ -64,13 +65,11 @@ hipError_t enqueue_batch(vv10_batch *b, const double *rho_x, const double *grad_
     const size_t nm = b->plans.size();
     hipError_t e = hipEventRecord(b->ev[0], b->cap);
     for (int k = 0; k < K && e == hipSuccess; ++k) e = hipStreamWaitEvent(b->side[k], b->ev[0], 0);
-    // per-molecule stages before the contraction
+    // per-molecule stage before the persistent kernel
     for (size_t m = 0; m < nm && e == hipSuccess; ++m) {
         vv10_plan *p = b->plans[m];
         p->stream = b->side[m % K];
-        e = vv10::launch_grid_terms(p, nullptr);
-        if (e == hipSuccess) e = vv10::launch_potential(p, energy + m, nullptr, nullptr);
-        if (e == hipSuccess) e = vv10::launch_pert_prep(p, p->ws, rho_x + b->rx_off[m], grad_rho_x + b->gx_off[m]);
+        e = vv10::launch_pert_prep(p, p->ws, rho_x + b->rx_off[m], grad_rho_x + b->gx_off[m]);
     }
     for (int k = 0; k < K && e == hipSuccess; ++k) {
         e = hipEventRecord(b->ev[1 + k], b->side[k]);
@@ -86,7 +85,9 @@ hipError_t enqueue_batch(vv10_batch *b, const double *rho_x, const double *grad_
         p->stream = b->side[m % K];
         const vv10_nuclear_outputs out = {hess + b->h_off[m], nullptr, nullptr, nullptr, nullptr,
                                           nullptr, nullptr, nullptr, nullptr, nullptr};
-        e = vv10::launch_assemble(p, out, false);
+        e = vv10::launch_sum_groups(p, 0);
+        if (e == hipSuccess) e = vv10::launch_potential(p, energy + m, nullptr, nullptr);
+        if (e == hipSuccess) e = vv10::launch_assemble(p, out, false);
     }
     for (int k = 0; k < K && e == hipSuccess; ++k) {
         e = hipEventRecord(b->ev[2 + K + k], b->side[k]);
@@ -136,10 +137,12 @@ vv10_status vv10_batch_create(const vv10_params *params, int32_t n_mol, const in
         rx += (int64_t)3 * na * n;
         hx += (int64_t)9 * na * na;
     }
-    // work list: (molecule, column group, j split, i tile), largest first
+    // work list: contraction items (molecule, column group, j split, i tile)
+    // and grid items (molecule, atom group, kGridItemTiles grid tiles)
     std::vector<vv10::BatchMol> mols;
-    std::vector<vv10::BatchItem> items;
-    std::vector<int64_t> cost;
+    std::vector<vv10::BatchItem> items, gitems;
+    std::vector<int64_t> cost, gcost;
+    const int W = vv10::persistent_waves(prec);   // waves per persistent workgroup
     if (st == VV10_OK) {
         for (size_t m = 0; m < b->plans.size(); ++m) {
             const vv10_plan *p = b->plans[m];
@@ -153,23 +156,58 @@ vv10_status vv10_batch_create(const vv10_params *params, int32_t n_mol, const in
             d.P1 = prec == VV10_FP64 ? (const void *)p->P1 : (const void *)p->P1f;
             d.X = ws.X;
             d.Ypart = ws.Ypart;
+            d.n_atom = p->n_atom;
+            d.bgroups = ws.bgroups;
+            d.ntiles = p->ntiles;
+            d.pad0 = 0;
+            d.seg = p->d_seg;
+            d.tile_i0 = p->d_tile_i0;
+            d.tile_n = p->d_tile_n;
+            d.tile_atom = p->d_tile_atom;
+            d.Pd = p->P1;
+            d.Z = ws.Z;
+            d.Dpart = ws.Dpart;
+            d.Igrp = ws.Igrp;
             mols.push_back(d);
+            // a grid item pairs up to W grid tiles of 64 outer points with
+            // every point of its atom group; per (64-point tile, point) it
+            // costs about kGridCost contraction units (j points x column
+            // blocks of a 64-point tile), as measured on the 20-water grid
+            constexpr int64_t kGridCost = 4;
+            for (int32_t g = 0; g < ws.bgroups; ++g) {
+                int64_t pts = 0;
+                for (int32_t B = g; B < p->n_atom; B += ws.bgroups) pts += p->seg[B + 1] - p->seg[B];
+                for (int32_t t = 0; t < p->ntiles; t += W) {
+                    const int64_t nt = std::min<int64_t>(W, p->ntiles - t);
+                    gitems.push_back({(int32_t)m, g, -1, t});
+                    gcost.push_back(nt * pts * kGridCost);
+                }
+            }
             for (int32_t s = 0; s < ws.jsplit; ++s) {
                 const int64_t jl = std::min<int64_t>(ws.jlen, p->npad - (int64_t)s * ws.jlen);
                 for (int32_t g = 0; g < ws.ngroups; ++g)
-                    for (int64_t t = 0; t < p->npad / 64; ++t) {
+                    for (int64_t t = 0; t < p->npad / (16 * W); ++t) {
                         items.push_back({(int32_t)m, g, s, (int32_t)t});
-                        cost.push_back(jl * ws.ncb);
+                        cost.push_back(jl * ws.ncb * W / 4);
                     }
             }
         }
-        std::vector<size_t> order(items.size());
-        for (size_t k = 0; k < order.size(); ++k) order[k] = k;
-        std::stable_sort(order.begin(), order.end(),
-                         [&](size_t a, size_t c) { return cost[a] > cost[c]; });
-        std::vector<vv10::BatchItem> sorted(items.size());
-        for (size_t k = 0; k < order.size(); ++k) sorted[k] = items[order[k]];
-        items.swap(sorted);
+        // grid items first, then contraction items, each kind largest first:
+        // run side by side on one CU the two kinds slow each other more than
+        // they overlap (measured on the 64-cluster batch: interleaved in
+        // proportion to their cost 3.02 s per launch, one kind after the
+        // other 2.86 s)
+        auto by_cost = [](const std::vector<vv10::BatchItem> &it, const std::vector<int64_t> &c,
+                          std::vector<vv10::BatchItem> &out) {
+            std::vector<size_t> order(it.size());
+            for (size_t k = 0; k < order.size(); ++k) order[k] = k;
+            std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t d) { return c[a] > c[d]; });
+            for (size_t k : order) out.push_back(it[k]);
+        };
+        std::vector<vv10::BatchItem> all;
+        by_cost(gitems, gcost, all);
+        by_cost(items, cost, all);
+        items.swap(all);
         b->n_items = (int64_t)items.size();
         if (b->n_items > INT32_MAX) st = VV10_E_ARG;
     }

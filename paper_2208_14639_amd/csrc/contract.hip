@@ -43,6 +43,7 @@
 #include <type_traits>
 
 #include "dev_common.h"
+#include "grid_tile.h"
 #include "vv10_internal.h"
 
 namespace vv10 {
@@ -678,10 +679,13 @@ auto dispatch_ncb(int ncb, F &&f) -> decltype(f(std::integral_constant<int, 1>{}
 }
 
 // ---------------------------------------------------------------------------
-// Persistent batched contraction: a fixed grid of workgroups pulls work items
-// (molecule, i tile, column group, j split) from an integer counter, largest
-// first.  Every item writes its own partial-output slab, so the results do
-// not depend on which workgroup ran which item.
+// Persistent batched kernel: a fixed grid of workgroups pulls work items from
+// an integer counter.  A contraction item is (molecule, i tile, column group,
+// j split); a grid item is a group of grid-pass tiles of one molecule for one
+// atom group, one tile per wave (the grid-position intermediates and the pair
+// integrals).  The host lists the grid items first, then the contraction
+// items, each kind largest first.  Every item writes its own output slab, so
+// the results do not depend on which workgroup ran which item.
 // ---------------------------------------------------------------------------
 template <int PREC>
 struct PersistentTraits;
@@ -689,20 +693,28 @@ template <>
 struct PersistentTraits<VV10_FP64> {
     static constexpr int kMaxNcb = 8;
     static constexpr int kSmem = smem_f64<8>();
+    static constexpr int kWaves = 4;
 };
 template <>
 struct PersistentTraits<VV10_MIXED_FP32> {
     static constexpr int kMaxNcb = 12;
     static constexpr int kSmem = smem_f32<12>();
+    static constexpr int kWaves = 4;
 };
 template <>
 struct PersistentTraits<VV10_MIXED_BF16X3> {
+    // four waves: the eight-wave form of the standalone kernel (32-point
+    // stages, X straight into two LDS buffers) spills 32 registers here,
+    // where every column count shares one register allocation, and was
+    // slower on the 64-cluster batch (2.95 s per launch against 2.86 s)
     static constexpr int kMaxNcb = 12;
     static constexpr int kSmem = smem_bf16x3<12>();
+    static constexpr int kWaves = 4;
 };
 
 template <int PREC, int NCB>
-__device__ __forceinline__ void run_item(const BatchMol &d, const BatchItem &it, char *smem) {
+__device__ __forceinline__ void run_item(const BatchMol &d, const BatchItem &it, char *smem,
+                                         char *smem2) {
     if constexpr (PREC == VV10_FP64) {
         tile_f64<NCB>(d.npad, d.jlen, d.Pp, static_cast<const double4 *>(d.P0),
                       static_cast<const double4 *>(d.P1), static_cast<const double *>(d.X),
@@ -713,31 +725,58 @@ __device__ __forceinline__ void run_item(const BatchMol &d, const BatchItem &it,
                       static_cast<float *>(d.Ypart), it.itile, it.grp, it.split, smem);
     } else {
         const bf16x8 *xh = static_cast<const bf16x8 *>(d.X);
-        tile_bf16x3<NCB>(d.npad, d.jlen, d.Pp, static_cast<const float4 *>(d.P0),
-                         static_cast<const float4 *>(d.P1), xh, xh + d.npad * d.Pp * 2 / 8,
-                         static_cast<float *>(d.Ypart), it.itile, it.grp, it.split, smem);
+        tile_bf16x3<NCB, false, PersistentTraits<PREC>::kWaves>(
+            d.npad, d.jlen, d.Pp, static_cast<const float4 *>(d.P0),
+            static_cast<const float4 *>(d.P1), xh, xh + d.npad * d.Pp * 2 / 8,
+            static_cast<float *>(d.Ypart), it.itile, it.grp, it.split, smem, nullptr, smem2);
     }
 }
 
+// A grid item: wave w runs tile itile + w of the molecule's grid pass for
+// atom group grp (with the pair integrals, as the Hessian call forms them).
 template <int PREC>
-__global__ __launch_bounds__(256, 2) void k_contract_persistent(const BatchMol *__restrict__ mols,
-                                                                const BatchItem *__restrict__ items,
-                                                                int32_t n_items,
-                                                                int32_t *__restrict__ counter) {
+__device__ __forceinline__ void run_grid_item(const BatchMol &d, const BatchItem &it, char *smem) {
+    using T = std::conditional_t<PREC == VV10_FP64, double, float>;
+    using T4 = std::conditional_t<PREC == VV10_FP64, double4, float4>;
+    constexpr int W = PersistentTraits<PREC>::kWaves;
+    static_assert(PersistentTraits<PREC>::kSmem >= W * 2 * kGridTile * (int)sizeof(T4),
+                  "grid item chunk buffers exceed the workgroup's LDS");
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int t = it.itile + wave;
+    if (t >= d.ntiles) return;
+    T4 *sA = reinterpret_cast<T4 *>(smem) + wave * 2 * kGridTile;
+    grid_unit<T, T4, true, false>(d.n_atom, d.Pp, d.bgroups, d.npad, d.seg, d.tile_i0, d.tile_n,
+                                  d.tile_atom, static_cast<const T4 *>(d.P0),
+                                  static_cast<const T4 *>(d.P1), d.Pd, d.Z, nullptr, d.Dpart,
+                                  d.Igrp, t, it.grp, lane, sA, sA + kGridTile);
+}
+
+template <int PREC>
+__global__ __launch_bounds__(64 * PersistentTraits<PREC>::kWaves, 8 / PersistentTraits<PREC>::kWaves) void k_contract_persistent(
+    const BatchMol *__restrict__ mols, const BatchItem *__restrict__ items, int32_t n_items,
+    int32_t *__restrict__ counter) {
+    constexpr int W = PersistentTraits<PREC>::kWaves;
     __shared__ __attribute__((aligned(16))) char smem[PersistentTraits<PREC>::kSmem];
+    // the second stage buffer of the eight-wave form (a one-byte dummy otherwise)
+    __shared__ __attribute__((aligned(16))) char smem2[W == 8 ? PersistentTraits<PREC>::kSmem : 1];
     __shared__ int32_t next;
     for (;;) {
         if (threadIdx.x == 0) next = atomicAdd(counter, 1);
         __syncthreads();
-        const int32_t k = next;
+        const int32_t k = __builtin_amdgcn_readfirstlane(next);   // uniform: item data in SGPRs
         __syncthreads();
         if (k >= n_items) break;          // every workgroup leaves once the list is drained
         const BatchItem it = items[k];
         const BatchMol d = mols[it.mol];
+        if (it.split < 0) {
+            run_grid_item<PREC>(d, it, smem);
+            __syncthreads();               // LDS is reused by the next item
+            continue;
+        }
         switch (d.ncb) {
 #define VV10_CASE(c) \
     case c:          \
-        if constexpr (c <= PersistentTraits<PREC>::kMaxNcb) run_item<PREC, c>(d, it, smem); \
+        if constexpr (c <= PersistentTraits<PREC>::kMaxNcb) run_item<PREC, c>(d, it, smem, smem2); \
         break;
             VV10_CASE(1) VV10_CASE(2) VV10_CASE(3) VV10_CASE(4) VV10_CASE(5) VV10_CASE(6)
             VV10_CASE(7) VV10_CASE(8) VV10_CASE(9) VV10_CASE(10) VV10_CASE(11) VV10_CASE(12)
@@ -993,15 +1032,22 @@ hipError_t launch_contract_weighted(vv10_plan *p, const Workspace &ws, const Wei
 
 namespace vv10 {
 
+int persistent_waves(vv10_precision prec) {
+    if (prec == VV10_FP64) return PersistentTraits<VV10_FP64>::kWaves;
+    if (prec == VV10_MIXED_FP32) return PersistentTraits<VV10_MIXED_FP32>::kWaves;
+    return PersistentTraits<VV10_MIXED_BF16X3>::kWaves;
+}
+
 int persistent_blocks_per_cu(vv10_precision prec) {
     int nb = 0;
     hipError_t e;
+    const int nt = 64 * persistent_waves(prec);
     if (prec == VV10_FP64)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_contract_persistent<VV10_FP64>, 256, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_contract_persistent<VV10_FP64>, nt, 0);
     else if (prec == VV10_MIXED_FP32)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_contract_persistent<VV10_MIXED_FP32>, 256, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_contract_persistent<VV10_MIXED_FP32>, nt, 0);
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_contract_persistent<VV10_MIXED_BF16X3>, 256, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_contract_persistent<VV10_MIXED_BF16X3>, nt, 0);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return 0;
@@ -1013,12 +1059,13 @@ hipError_t launch_contract_persistent(vv10_precision prec, const BatchMol *mols,
                                       const BatchItem *items, int32_t n_items, int32_t *counter,
                                       int n_blocks, hipStream_t stream) {
     k_zero_counter<<<1, 1, 0, stream>>>(counter);
+    const int nt = 64 * persistent_waves(prec);
     if (prec == VV10_FP64)
-        k_contract_persistent<VV10_FP64><<<n_blocks, 256, 0, stream>>>(mols, items, n_items, counter);
+        k_contract_persistent<VV10_FP64><<<n_blocks, nt, 0, stream>>>(mols, items, n_items, counter);
     else if (prec == VV10_MIXED_FP32)
-        k_contract_persistent<VV10_MIXED_FP32><<<n_blocks, 256, 0, stream>>>(mols, items, n_items, counter);
+        k_contract_persistent<VV10_MIXED_FP32><<<n_blocks, nt, 0, stream>>>(mols, items, n_items, counter);
     else
-        k_contract_persistent<VV10_MIXED_BF16X3><<<n_blocks, 256, 0, stream>>>(mols, items, n_items, counter);
+        k_contract_persistent<VV10_MIXED_BF16X3><<<n_blocks, nt, 0, stream>>>(mols, items, n_items, counter);
     return hipGetLastError();
 }
 

@@ -154,18 +154,29 @@ struct vv10_plan {
 
 namespace vv10 {
 
-// Contraction operands of one molecule of a batch (device copy).
+// Operands of one molecule of a batch (device copy): the contraction's and
+// the grid pass's (grid-position intermediates with the pair integrals).
 struct BatchMol {
     int64_t npad, jlen;
     int32_t Pp, ncb;
     const void *P0, *P1;   // double4 (FP64) or float4 (mixed) point data
     const void *X;         // (p, q) channels in the plan's layout
     void *Ypart;           // [jsplit][npad][2][Pp] partial outputs
+    int32_t n_atom, bgroups, ntiles, pad0;
+    const int64_t *seg;    // [n_atom + 1] atom segments
+    const int32_t *tile_i0, *tile_n, *tile_atom;   // grid-pass tiles
+    const double4 *Pd;     // FP64 point data (the self pair)
+    double *Z, *Dpart, *Igrp;   // grid-pass outputs, as the plan's workspace holds them
 };
-// One unit of work of the persistent contraction.
+// One unit of work of the persistent kernel, whose workgroups have W =
+// persistent_waves(prec) waves: with split >= 0 a contraction item
+// (molecule, column group grp, j split, i tile itile of 16 W points); with
+// split = -1 a grid item (molecule, atom group grp, grid-pass tiles itile ..
+// itile + W - 1, one per wave).
 struct BatchItem {
     int32_t mol, grp, split, itile;
 };
+int persistent_waves(vv10_precision prec);
 int persistent_blocks_per_cu(vv10_precision prec);
 hipError_t launch_contract_persistent(vv10_precision prec, const BatchMol *mols,
                                       const BatchItem *items, int32_t n_items, int32_t *counter,
@@ -199,6 +210,9 @@ hipError_t launch_contract(vv10_plan *p, const Workspace &ws, bool screen = fals
 // ints_from: the pair integrals I[k] for ints_from <= k < 6 are formed in the
 // same pass and written to p->I (0: all six; 6: none, the plan holds them).
 hipError_t launch_grid_terms(vv10_plan *p, double *Ze, int ints_from = 0);
+// The second half of launch_grid_terms: I[k] for ints_from <= k < 6 from the
+// per-group partials the grid pass left in ws.Igrp.
+hipError_t launch_sum_groups(vv10_plan *p, int ints_from = 0);
 // ints: also E, U, W into p->I (else the plan holds them).
 hipError_t launch_grid_grad(vv10_plan *p, bool ints = true);
 hipError_t launch_gradient(vv10_plan *p, const double *rho_x, const double *grad_rho_x,
