@@ -290,7 +290,8 @@ vv10_status vv10_trial_response(vv10_plan *plan, int32_t n_t, const double *rho_
                                 const double *grad_rho_t, double *f_rho_t, double *f_gamma_t);
 
 /* Device bytes that vv10_trial_response adds to a plan for n_t trial
- * densities (upper bound over devices); 0 for invalid sizes. */
+ * densities (an upper bound for automatic tiles and for tiles whose j-split
+ * count is at most twice the automatic one); 0 for invalid sizes. */
 size_t vv10_response_footprint_bytes(int64_t n_grid, int32_t n_t, vv10_precision prec);
 
 /* Stages of the library's launch sequence, for vv10_stage_times. */
@@ -429,7 +430,10 @@ vv10_status vv10_batch_info(const vv10_batch *batch, int64_t *n_items, int32_t *
 void vv10_batch_destroy(vv10_batch *batch);
 
 /* Device bytes a plan for this size holds once vv10_hessian_terms has run
- * (an upper bound; vv10_energy_potential alone needs less). */
+ * (an upper bound for automatic tiles and for tiles whose j-split count is at
+ * most twice the automatic one, as the autotuner's are; the contraction
+ * partials are FP64, one [N][2][P] block per j split; vv10_energy_potential
+ * alone needs less). */
 size_t vv10_footprint_bytes(int64_t n_grid, int32_t n_atom, vv10_precision prec);
 
 /* Destroy a plan (NULL is accepted).  Waits for the plan's stream to finish

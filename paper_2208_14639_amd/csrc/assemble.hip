@@ -99,8 +99,8 @@ struct WeightIn {
     double *Rw;            // [npad][Pp] output
 };
 
-// One wave per point; the partials are FP64 or FP32 ([S][npad][2][Pp]; for
-// FP64 with one split they alias Y, read before R is written in place).
+// One wave per point; the partials are FP64 ([S][npad][2][Pp]; with one
+// split they alias Y, read before R is written in place).
 template <typename T, bool WT>
 __global__ __launch_bounds__(256) void k_resp(
     int64_t n, int64_t npad, int32_t P, int32_t Pp, int32_t S, const int32_t *__restrict__ atom_of,
@@ -534,14 +534,10 @@ hipError_t launch_gradient(vv10_plan *p, const double *rho_x, const double *grad
 hipError_t launch_trial_response(vv10_plan *p, double *f_rho_t, double *f_gamma_t) {
     const Workspace &ws = p->rws;
     dim3 grid((unsigned)((p->n + TRI - 1) / TRI), (unsigned)((ws.P + TRX - 1) / TRX));
-    if (p->prec == VV10_FP64)
-        k_trial_resp<double><<<grid, 256, 0, p->stream>>>(
-            p->n, p->npad, ws.P, ws.Pp, ws.jsplit, p->P1, p->F, p->Ir, ws.L,
-            static_cast<const double *>(ws.Ypart), f_rho_t, f_gamma_t);
-    else
-        k_trial_resp<float><<<grid, 256, 0, p->stream>>>(
-            p->n, p->npad, ws.P, ws.Pp, ws.jsplit, p->P1, p->F, p->Ir, ws.L,
-            static_cast<const float *>(ws.Ypart), f_rho_t, f_gamma_t);
+    // the contraction partials are FP64 in every mode
+    k_trial_resp<double><<<grid, 256, 0, p->stream>>>(
+        p->n, p->npad, ws.P, ws.Pp, ws.jsplit, p->P1, p->F, p->Ir, ws.L,
+        static_cast<const double *>(ws.Ypart), f_rho_t, f_gamma_t);
     return hipGetLastError();
 }
 
@@ -552,31 +548,18 @@ hipError_t launch_assemble(vv10_plan *p, const vv10_nuclear_outputs &out, bool w
     double *hess = out.hess, *grad = out.grad;
     {
         const unsigned nb = (unsigned)((n + 3) / 4);
-        if (p->prec == VV10_FP64) {
-            const WeightIn<double> wt = {static_cast<const double *>(ww.Ypart), ww.Lw, ww.Ze, ww.Rw};
-            if (weighted)
-                k_resp<double, true><<<nb, 256, 0, p->stream>>>(
-                    n, p->npad, ws.P, ws.Pp, ws.jsplit, p->atom_of, p->P1, p->F, p->I, ws.L,
-                    static_cast<const double *>(ws.Ypart), ws.Y, ws.Z, wt, out.resp_rho,
-                    out.resp_gamma, out.fock_rho, out.fock_gamma);
-            else
-                k_resp<double, false><<<nb, 256, 0, p->stream>>>(
-                    n, p->npad, ws.P, ws.Pp, ws.jsplit, p->atom_of, p->P1, p->F, p->I, ws.L,
-                    static_cast<const double *>(ws.Ypart), ws.Y, ws.Z, wt, out.resp_rho,
-                    out.resp_gamma, out.fock_rho, out.fock_gamma);
-        } else {
-            const WeightIn<float> wt = {static_cast<const float *>(ww.Ypart), ww.Lw, ww.Ze, ww.Rw};
-            if (weighted)
-                k_resp<float, true><<<nb, 256, 0, p->stream>>>(
-                    n, p->npad, ws.P, ws.Pp, ws.jsplit, p->atom_of, p->P1, p->F, p->I, ws.L,
-                    static_cast<const float *>(ws.Ypart), ws.Y, ws.Z, wt, out.resp_rho,
-                    out.resp_gamma, out.fock_rho, out.fock_gamma);
-            else
-                k_resp<float, false><<<nb, 256, 0, p->stream>>>(
-                    n, p->npad, ws.P, ws.Pp, ws.jsplit, p->atom_of, p->P1, p->F, p->I, ws.L,
-                    static_cast<const float *>(ws.Ypart), ws.Y, ws.Z, wt, out.resp_rho,
-                    out.resp_gamma, out.fock_rho, out.fock_gamma);
-        }
+        // the contraction partials are FP64 in every mode
+        const WeightIn<double> wt = {static_cast<const double *>(ww.Ypart), ww.Lw, ww.Ze, ww.Rw};
+        if (weighted)
+            k_resp<double, true><<<nb, 256, 0, p->stream>>>(
+                n, p->npad, ws.P, ws.Pp, ws.jsplit, p->atom_of, p->P1, p->F, p->I, ws.L,
+                static_cast<const double *>(ws.Ypart), ws.Y, ws.Z, wt, out.resp_rho,
+                out.resp_gamma, out.fock_rho, out.fock_gamma);
+        else
+            k_resp<double, false><<<nb, 256, 0, p->stream>>>(
+                n, p->npad, ws.P, ws.Pp, ws.jsplit, p->atom_of, p->P1, p->F, p->I, ws.L,
+                static_cast<const double *>(ws.Ypart), ws.Y, ws.Z, wt, out.resp_rho,
+                out.resp_gamma, out.fock_rho, out.fock_gamma);
     }
     if (!hess && !grad) return hipGetLastError();
     const int64_t slice = (n + ws.gsplit - 1) / ws.gsplit;

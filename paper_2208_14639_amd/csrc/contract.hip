@@ -38,8 +38,10 @@
 //   A = r (1/g + 1/s),  A' = r (1/g' + 1/s),  Q = 2 r (1/s^2 + 1/(g g')),
 //   t1 = c_i Q - A',  t2 = c_j Q - A,
 //   K_pp = r - c_i A + c_j t1,  K_pq = R^2 t1,  K_qp = R^2 t2,  K_qq = R^4 Q.
-// They accumulate one j-split in FP32 and write FP32 partials, which the
-// assembly sums over splits in FP64.
+// They accumulate at most kFp32Run consecutive j points in FP32 (the MFMA
+// accumulators) and then add those sums into the split's FP64 partials; the
+// assembly sums the partials over splits in FP64.  So the sums are FP32
+// within a tile of kFp32Run points and FP64 across tiles and splits.
 #include <type_traits>
 
 #include "dev_common.h"
@@ -185,10 +187,11 @@ template <int NCB, bool SCR = false>
 __device__ __forceinline__ void tile_f32(int64_t npad, int64_t jlen, int32_t Pp,
                                          const float4 *__restrict__ P0,
                                          const float4 *__restrict__ P1,
-                                         const float *__restrict__ X, float *__restrict__ Yout,
+                                         const float *__restrict__ X, double *__restrict__ Yout,
                                          int64_t itile, int grp, int split, char *smem,
                                          const uint32_t *__restrict__ mask = nullptr) {
     constexpr int NC = NCB * 16;
+    static_assert(kFp32Run % kJC == 0, "FP32 runs end on chunk boundaries");
     float4 *sA = reinterpret_cast<float4 *>(smem);
     float4 *sB = sA + kJC;
     float *sX = reinterpret_cast<float *>(sB + kJC);
@@ -206,6 +209,33 @@ __device__ __forceinline__ void tile_f32(int64_t npad, int64_t jlen, int32_t Pp,
         accp[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
         accq[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
     }
+    // D layout of the FP32 MFMAs (measured on gfx950): item r of lane l holds
+    // row 4 (l/16) + r, column l%16.  The FP32 sums of each run of kFp32Run
+    // points go into this split's FP64 partials.
+    double *Yb = Yout + (int64_t)split * npad * 2 * Pp;
+    bool first = true;
+    auto flush = [&]() {
+        // one base address formed here (the empty asm keeps it from being
+        // hoisted out of the loop)
+        int64_t off = (ibase + 4 * kq) * 2 * Pp + col0 + m;
+        asm volatile("" : "+v"(off));
+        double *y = Yb + off;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                add_partial(y + (2 * r + 0) * (int64_t)Pp + cb * 16, accp[cb][r], first);
+                add_partial(y + (2 * r + 1) * (int64_t)Pp + cb * 16, accq[cb][r], first);
+            }
+            mem_order();
+        }
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+            accp[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
+            accq[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
+        }
+        first = false;
+    };
     for (int64_t j0 = jbeg; j0 < jend; j0 += kJC) {
         __syncthreads();
         if (tid < kJC) {
@@ -245,18 +275,9 @@ __device__ __forceinline__ void tile_f32(int64_t npad, int64_t jlen, int32_t Pp,
                 accq[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(kqq, xq, accq[cb], 0, 0, 0);
             }
         }
+        if ((j0 + kJC - jbeg) % kFp32Run == 0 && j0 + kJC < jend) flush();
     }
-    // D layout of the FP32 MFMAs (measured on gfx950): item r of lane l holds
-    // row 4 (l/16) + r, column l%16
-    float *Yb = Yout + (int64_t)split * npad * 2 * Pp;
-#pragma unroll
-    for (int cb = 0; cb < NCB; ++cb)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t row = ibase + 4 * kq + r;
-            Yb[(row * 2 + 0) * Pp + col0 + cb * 16 + m] = accp[cb][r];
-            Yb[(row * 2 + 1) * Pp + col0 + cb * 16 + m] = accq[cb][r];
-        }
+    flush();
 }
 
 // ---------------------------------------------------------------------------
@@ -333,11 +354,12 @@ __device__ __forceinline__ void tile_bf16x3(int64_t npad, int64_t jlen, int32_t 
                                             const float4 *__restrict__ P1,
                                             const bf16x8 *__restrict__ Xhi,
                                             const bf16x8 *__restrict__ Xlo,
-                                            float *__restrict__ Yout, int64_t itile, int grp,
+                                            double *__restrict__ Yout, int64_t itile, int grp,
                                             int split, char *smem,
                                             const uint32_t *__restrict__ mask = nullptr,
                                             char *smem2 = nullptr) {
     constexpr int NC = NCB * 16;
+    static_assert(kFp32Run % 32 == 0, "FP32 runs end on stage boundaries");
     constexpr int UNITS = NC * 4;                       // 8-bf16 units per block and array
     constexpr int NT = 64 * WAVES;                      // threads of the workgroup
     constexpr int PER = (UNITS + NT - 1) / NT;          // units per thread and array
@@ -357,6 +379,32 @@ __device__ __forceinline__ void tile_bf16x3(int64_t npad, int64_t jlen, int32_t 
         accp[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
         accq[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
     }
+    // the FP32 sums of each run of kFp32Run points go into this split's FP64
+    // partials (D layout: item r of lane (m, g) is row 4 g + r, column m)
+    double *Yb = Yout + (int64_t)split * npad * 2 * Pp;
+    bool first = true;
+    auto flush = [&]() {
+        // one base address formed here (the empty asm keeps it from being
+        // hoisted out of the loop: 2 x 4 x NCB addresses would stay live)
+        int64_t off = (ibase + 4 * g) * 2 * Pp + col0 + m;
+        asm volatile("" : "+v"(off));
+        double *y = Yb + off;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                add_partial(y + (2 * r + 0) * (int64_t)Pp + cb * 16, accp[cb][r], first);
+                add_partial(y + (2 * r + 1) * (int64_t)Pp + cb * 16, accq[cb][r], first);
+            }
+            mem_order();
+        }
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+            accp[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
+            accq[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
+        }
+        first = false;
+    };
     // X block staging: thread tid moves units tid + NT k of the block
     bf16x8 rh[PER], rl[PER];
     auto load_x = [&](int64_t blk) {
@@ -463,9 +511,11 @@ __device__ __forceinline__ void tile_bf16x3(int64_t npad, int64_t jlen, int32_t 
         };
         // a split holds a whole number of 32-point stages (jbeg and jlen are
         // multiples of 32, npad of 256)
+        static_assert(kFp32Run % 64 == 0, "FP32 runs end on stage pairs");
         for (int64_t j0 = jbeg; j0 < jend; j0 += 64) {
             stage(j0, H0, L0, H1, L1);
             if (j0 + 32 < jend) stage(j0 + 32, H1, L1, H0, L0);
+            if ((j0 + 64 - jbeg) % kFp32Run == 0 && j0 + 64 < jend) flush();
         }
     } else {
     load_pts(jbeg);
@@ -538,19 +588,12 @@ __device__ __forceinline__ void tile_bf16x3(int64_t npad, int64_t jlen, int32_t 
         }
         cur = nxt;
         if (more) store_x(buf ^ 1);
+        if ((j0 + 16 - jbeg) % kFp32Run == 0 && more) flush();
         __syncthreads();
         buf ^= 1;
     }
     }
-    float *Yb = Yout + (int64_t)split * npad * 2 * Pp;
-#pragma unroll
-    for (int cb = 0; cb < NCB; ++cb)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t row = ibase + 4 * g + r;
-            Yb[(row * 2 + 0) * Pp + col0 + cb * 16 + m] = accp[cb][r];
-            Yb[(row * 2 + 1) * Pp + col0 + cb * 16 + m] = accq[cb][r];
-        }
+    flush();
 }
 
 // One workgroup per (i tile, column group, j split): blockIdx = (tile, group, split).
@@ -573,7 +616,7 @@ __global__ __launch_bounds__(256, 2) void k_contract_f32(int64_t npad, int64_t j
                                                          const float4 *__restrict__ P0,
                                                          const float4 *__restrict__ P1,
                                                          const float *__restrict__ X,
-                                                         float *__restrict__ Yout,
+                                                         double *__restrict__ Yout,
                                                          const uint32_t *__restrict__ mask) {
     __shared__ __attribute__((aligned(16))) char smem[smem_f32<NCB>()];
     tile_f32<NCB, SCR>(npad, jlen, Pp, P0, P1, X, Yout, blockIdx.x, blockIdx.y, blockIdx.z, smem,
@@ -595,7 +638,7 @@ __global__ __launch_bounds__(64 * bf16_waves<NCB>(), 8 / bf16_waves<NCB>()) void
                                                             const float4 *__restrict__ P1,
                                                             const bf16x8 *__restrict__ Xhi,
                                                             const bf16x8 *__restrict__ Xlo,
-                                                            float *__restrict__ Yout,
+                                                            double *__restrict__ Yout,
                                                             const uint32_t *__restrict__ mask) {
     __shared__ __attribute__((aligned(16))) char smem[smem_bf16x3<NCB>()];
     // the second stage buffer of the eight-wave form (a one-byte dummy otherwise)
@@ -619,14 +662,14 @@ hipError_t run_mode(vv10_plan *p, const Workspace &ws) {
     } else if (p->prec == VV10_MIXED_FP32) {
         k_contract_f32<NCB, SCR><<<grid, 256, 0, p->stream>>>(
             p->npad, ws.jlen, ws.Pp, p->P0f, p->P1f, static_cast<const float *>(ws.X),
-            static_cast<float *>(ws.Ypart), mask);
+            static_cast<double *>(ws.Ypart), mask);
     } else {
         const bf16x8 *xh = static_cast<const bf16x8 *>(ws.X);
         const bf16x8 *xl = xh + (size_t)p->npad * ws.Pp * 2 / 8;
         constexpr int W = bf16_waves<NCB>();
         dim3 gridb((unsigned)(p->npad / (16 * W)), (unsigned)ws.ngroups, (unsigned)ws.jsplit);
         k_contract_bf16x3<NCB, SCR><<<gridb, 64 * W, 0, p->stream>>>(
-            p->npad, ws.jlen, ws.Pp, p->P0f, p->P1f, xh, xl, static_cast<float *>(ws.Ypart), mask);
+            p->npad, ws.jlen, ws.Pp, p->P0f, p->P1f, xh, xl, static_cast<double *>(ws.Ypart), mask);
     }
     return hipGetLastError();
 }
@@ -722,13 +765,13 @@ __device__ __forceinline__ void run_item(const BatchMol &d, const BatchItem &it,
     } else if constexpr (PREC == VV10_MIXED_FP32) {
         tile_f32<NCB>(d.npad, d.jlen, d.Pp, static_cast<const float4 *>(d.P0),
                       static_cast<const float4 *>(d.P1), static_cast<const float *>(d.X),
-                      static_cast<float *>(d.Ypart), it.itile, it.grp, it.split, smem);
+                      static_cast<double *>(d.Ypart), it.itile, it.grp, it.split, smem);
     } else {
         const bf16x8 *xh = static_cast<const bf16x8 *>(d.X);
         tile_bf16x3<NCB, false, PersistentTraits<PREC>::kWaves>(
             d.npad, d.jlen, d.Pp, static_cast<const float4 *>(d.P0),
             static_cast<const float4 *>(d.P1), xh, xh + d.npad * d.Pp * 2 / 8,
-            static_cast<float *>(d.Ypart), it.itile, it.grp, it.split, smem, nullptr, smem2);
+            static_cast<double *>(d.Ypart), it.itile, it.grp, it.split, smem, nullptr, smem2);
     }
 }
 
@@ -837,8 +880,8 @@ template <int NCB>
 __global__ __launch_bounds__(256, 2) void k_contract_bf16x3_w(
     int64_t npad, int64_t jlen, int32_t Pp, const float4 *__restrict__ P0,
     const float4 *__restrict__ P1, const bf16x8 *__restrict__ Xhi, const bf16x8 *__restrict__ Xlo,
-    const bf16x8 *__restrict__ Vhi, const bf16x8 *__restrict__ Vlo, float *__restrict__ Yout,
-    float *__restrict__ Ywout) {
+    const bf16x8 *__restrict__ Vhi, const bf16x8 *__restrict__ Vlo, double *__restrict__ Yout,
+    double *__restrict__ Ywout) {
     constexpr int NC = NCB * 16;
     constexpr int UNITS = NC * 4;           // 8-bf16 units of one array and block
     constexpr int NARR = 6;                 // main hi (2 sub-blocks), main lo (2), weight hi, lo
@@ -862,6 +905,39 @@ __global__ __launch_bounds__(256, 2) void k_contract_bf16x3_w(
         awq[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
         awv[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
     }
+    // the FP32 sums of each run of kFp32Run points go into this split's FP64
+    // partials (D layout: item r of lane l holds row 4 (l/16) + r, column l%16)
+    double *Yb = Yout + (int64_t)blockIdx.z * npad * 2 * Pp;
+    double *Yw = Ywout + (int64_t)blockIdx.z * npad * 3 * Pp;
+    bool first = true;
+    auto flush = [&]() {
+        // base addresses formed here (the empty asm keeps them from being
+        // hoisted out of the loop)
+        int64_t ob = (ibase + 4 * g) * 2 * Pp + m, ow = (ibase + 4 * g) * 3 * Pp + m;
+        asm volatile("" : "+v"(ob), "+v"(ow));
+        double *yb = Yb + ob, *yw = Yw + ow;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                add_partial(yb + (2 * r + 0) * (int64_t)Pp + cb * 16, accp[cb][r], first);
+                add_partial(yb + (2 * r + 1) * (int64_t)Pp + cb * 16, accq[cb][r], first);
+                add_partial(yw + (3 * r + 0) * (int64_t)Pp + cb * 16, awp[cb][r], first);
+                add_partial(yw + (3 * r + 1) * (int64_t)Pp + cb * 16, awq[cb][r], first);
+                add_partial(yw + (3 * r + 2) * (int64_t)Pp + cb * 16, awv[cb][r], first);
+            }
+            mem_order();
+        }
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+            accp[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
+            accq[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
+            awp[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
+            awq[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
+            awv[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
+        }
+        first = false;
+    };
     bf16x8 rx[PER];
     float4 rp = {0.f, 0.f, 0.f, 0.f};
     // unit e = a UNITS + u of a block: a = 0, 1 main hi of sub-block 0, 1;
@@ -969,24 +1045,11 @@ __global__ __launch_bounds__(256, 2) void k_contract_bf16x3_w(
             awv[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wvh, vl, awv[cb], 0, 0, 0);
         }
         if (more) store(buf ^ 1);
+        if ((j0 + 32 - jbeg) % kFp32Run == 0 && more) flush();
         __syncthreads();
         buf ^= 1;
     }
-    // D layout: item r of lane l holds row 4 (l/16) + r, column l%16
-    float *Yb = Yout + (int64_t)blockIdx.z * npad * 2 * Pp;
-    float *Yw = Ywout + (int64_t)blockIdx.z * npad * 3 * Pp;
-#pragma unroll
-    for (int cb = 0; cb < NCB; ++cb)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t row = ibase + 4 * g + r;
-            const int64_t col = cb * 16 + m;
-            Yb[(row * 2 + 0) * Pp + col] = accp[cb][r];
-            Yb[(row * 2 + 1) * Pp + col] = accq[cb][r];
-            Yw[(row * 3 + 0) * Pp + col] = awp[cb][r];
-            Yw[(row * 3 + 1) * Pp + col] = awq[cb][r];
-            Yw[(row * 3 + 2) * Pp + col] = awv[cb][r];
-        }
+    flush();
 }
 
 template <int NCB>
@@ -997,8 +1060,8 @@ hipError_t run_weighted(vv10_plan *p, const Workspace &ws, const WeightWork &ww)
     const bf16x8 *vh = static_cast<const bf16x8 *>(ww.Xv);
     const bf16x8 *vl = vh + (size_t)p->npad * ws.Pp / 8;
     k_contract_bf16x3_w<NCB><<<grid, 256, 0, p->stream>>>(
-        p->npad, ws.jlen, ws.Pp, p->P0f, p->P1f, xh, xl, vh, vl, static_cast<float *>(ws.Ypart),
-        static_cast<float *>(ww.Ypart));
+        p->npad, ws.jlen, ws.Pp, p->P0f, p->P1f, xh, xl, vh, vl, static_cast<double *>(ws.Ypart),
+        static_cast<double *>(ww.Ypart));
     return hipGetLastError();
 }
 

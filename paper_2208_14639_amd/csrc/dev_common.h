@@ -19,6 +19,24 @@ __device__ __forceinline__ double rcp64(double x) {
     return r;
 }
 
+// The mixed contractions sum at most kFp32Run consecutive j points of a tile
+// in FP32 (the MFMA accumulators) and then add those sums into the tile's
+// rows of the split's FP64 partials: FP32 within a tile, FP64 across tiles.
+constexpr int kFp32Run = 4096;
+
+// Adds a tile's FP32 sum v into its FP64 partial y; first: y is written,
+// not read.  Each partial element has a single writer (one lane of one
+// workgroup), so a plain read-add-write suffices and the order of the
+// additions, and the result, are fixed.
+__device__ __forceinline__ void add_partial(double *y, float v, bool first) {
+    *y = first ? (double)v : *y + (double)v;
+}
+
+// Barrier for the compiler only: the memory accesses before it are issued
+// before those after it (a flush adds one row of a tile at a time, so that
+// its loads do not all occupy registers at once).
+__device__ __forceinline__ void mem_order() { asm volatile("" ::: "memory"); }
+
 // 1/x in FP32 (hardware estimate, about 1 ulp).
 __device__ __forceinline__ float rcp32(float x) { return __builtin_amdgcn_rcpf(x); }
 

@@ -26,13 +26,14 @@ void plan_workspace_shape(int64_t npad, int32_t n_atom, int32_t ntiles, int num_
     ws.Pp = 16 * ws.ncb * ws.ngroups;
 
     // j splits of the contraction: fill the last round of resident
-    // workgroups; the mixed modes accumulate one split in FP32, so they
-    // also cap a split at 16384 points.
+    // workgroups (every mode keeps FP64 partials per split; the mixed modes
+    // sum at most kFp32Run points in FP32 before adding into them, so a
+    // split may be as long as the grid).
     int per_cu = contract_blocks_per_cu(prec, ws.ncb);
     if (per_cu <= 0) per_cu = 2;
     const int64_t units = (npad / 64) * ws.ngroups;
     const int64_t slots = (int64_t)per_cu * num_cu;
-    const int min_split = prec == VV10_FP64 ? 1 : (int)((npad + 16383) / 16384);
+    const int min_split = 1;
     double best = -1.0;
     ws.jsplit = min_split;
     for (int S = min_split; S <= min_split + 15; ++S) {
@@ -64,7 +65,7 @@ size_t workspace_bytes(int64_t npad, int32_t n_atom, int32_t ntiles, vv10_precis
     const size_t ch = (size_t)npad * 2 * ws.Pp;
     size_t b = 3 * ch * sizeof(double);                       // L, Y, Z
     b += ch * (prec == VV10_FP64 ? 8 : 4);                    // X (FP64, FP32, or BF16 hi + lo)
-    const bool alias = prec == VV10_FP64 && ws.jsplit == 1;   // partials written straight into Y
+    const bool alias = ws.jsplit == 1;   // partials written straight into Y
     if (!alias) b += (size_t)ws.jsplit * ch * partial_elem(prec);
     b += (size_t)ntiles * n_atom * 9 * sizeof(double);
     b += (size_t)ws.bgroups * NI * npad * sizeof(double);
@@ -224,7 +225,7 @@ vv10_status vv10::ensure_workspace(vv10_plan *p) {
     if (e == hipSuccess) e = dalloc(&ws.L, ch);
     if (e == hipSuccess) e = dalloc(&ws.Y, ch);
     if (e == hipSuccess) {
-        if (p->prec == VV10_FP64 && ws.jsplit == 1) {
+        if (ws.jsplit == 1) {
             ws.Ypart = ws.Y;
         } else {
             e = dalloc(&yp, ch * ws.jsplit * vv10::partial_elem(p->prec));
@@ -397,7 +398,9 @@ size_t vv10_footprint_bytes(int64_t n_grid, int32_t n_atom, vv10_precision prec)
     const int64_t ntiles = (n_grid + vv10::kGridTile - 1) / vv10::kGridTile + n_atom;
     Workspace ws;
     vv10::plan_workspace_shape(npad, n_atom, (int32_t)ntiles, 256, prec, ws);
-    ws.jsplit = std::max(ws.jsplit, 16);   // upper bound over devices and occupancies
+    // tuned tiles take at most twice the automatic j-split count (the
+    // autotuner's candidates); one split writes the partials into Y itself
+    ws.jsplit = (int32_t)std::min<int64_t>(2 * (int64_t)ws.jsplit, std::max<int64_t>(1, npad / 256));
     return base_bytes(npad, n_atom, ntiles) +
            vv10::workspace_bytes(npad, n_atom, (int32_t)ntiles, prec, ws);
 }
@@ -697,7 +700,8 @@ size_t vv10_response_footprint_bytes(int64_t n_grid, int32_t n_t, vv10_precision
     const int64_t npad = ((n_grid + vv10::kPad - 1) / vv10::kPad) * vv10::kPad;
     Workspace ws;
     vv10::plan_workspace_shape(npad, 1, 1, 256, prec, ws, 0, 0, n_t);
-    ws.jsplit = std::max(ws.jsplit, 16);   // upper bound over devices and occupancies
+    // tuned tiles take at most twice the automatic j-split count
+    ws.jsplit = (int32_t)std::min<int64_t>(2 * (int64_t)ws.jsplit, std::max<int64_t>(1, npad / 256));
     return vv10::response_bytes(npad, prec, ws);
 }
 

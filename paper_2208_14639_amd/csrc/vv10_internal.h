@@ -45,7 +45,7 @@ struct Workspace {
     void *X = nullptr;           // (p, q) channels: FP64 or FP32 [npad][2][Pp];
                                  // BF16X3: hi then lo, each [npad/16][Pp][32] bf16
     double *L = nullptr;         // [npad][2][Pp] (rho^x, gamma^x)
-    void *Ypart = nullptr;       // [jsplit][npad][2][Pp] contraction partials (FP64 or FP32)
+    void *Ypart = nullptr;       // [jsplit][npad][2][Pp] contraction partials (FP64; Y itself with one split)
     double *Y = nullptr;         // [npad][2][Pp] summed contraction, then R in place
     double *Z = nullptr;         // [npad][2][Pp] grid-position channels
     double *Dpart = nullptr;     // [ntiles][n_atom][9] tile sums of a_i D^B_i (6) and a_i E^{Bgr}_i (3)
@@ -76,7 +76,7 @@ struct WeightWork {
     double *Wown = nullptr;      // [npad][3] owner-atom slot of w^x
     void *Xv = nullptr;          // v = w^x rho: FP64/FP32 [npad][Pp]; BF16X3 hi, lo [npad/32][Pp][32]
     double *Lw = nullptr;        // [npad][Pp] w^x with the owner slot filled
-    void *Ypart = nullptr;       // [jsplit][npad][3][Pp] (Y_pv, Y_qv, Y_vv) partials
+    void *Ypart = nullptr;       // [jsplit][npad][3][Pp] (Y_pv, Y_qv, Y_vv) partials, FP64
     double *Ze = nullptr;        // [npad][Pp] E^{Bgr}_i (grid pass)
     double *Rw = nullptr;        // [npad][Pp] right factor of the w^x rows of the GEMM
     double *Hpart = nullptr;     // [gsplit][Pp + 1][Pp] GEMM slices of the w^x rows
@@ -248,7 +248,8 @@ int contract_blocks_per_cu(vv10_precision prec, int ncb);
 inline int max_ncb(vv10_precision prec) { return prec == VV10_FP64 ? 8 : 12; }
 // Max 16-column blocks per weight-contraction workgroup (three outputs).
 inline int max_wncb(vv10_precision prec) { return prec == VV10_FP64 ? 4 : 8; }
-// Bytes of one element of the contraction partials / operand.
-inline size_t partial_elem(vv10_precision prec) { return prec == VV10_FP64 ? 8 : 4; }
+// Bytes of one element of the contraction partials: FP64 in every mode (the
+// mixed modes add their FP32 tile sums into them).
+inline size_t partial_elem(vv10_precision) { return sizeof(double); }
 
 }  // namespace vv10

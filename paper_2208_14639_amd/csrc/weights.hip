@@ -172,10 +172,11 @@ template <typename T, int NCB>
 __global__ __launch_bounds__(256, 2) void k_wcontract(int64_t npad, int64_t jlen, int32_t Pp,
                                                       const typename WTraits<T>::P4 *__restrict__ P0,
                                                       const typename WTraits<T>::P4 *__restrict__ P1,
-                                                      const T *__restrict__ X, T *__restrict__ Yout) {
+                                                      const T *__restrict__ X, double *__restrict__ Yout) {
     typedef typename WTraits<T>::P4 P4;
     typedef typename WTraits<T>::Acc Acc;
     constexpr int NC = NCB * 16;
+    static_assert(kFp32Run % kJC == 0, "FP32 runs end on chunk boundaries");
     __shared__ __attribute__((aligned(16))) char smem[smem_w<T, NCB>()];
     P4 *sA = reinterpret_cast<P4 *>(smem);
     P4 *sB = sA + kJC;
@@ -194,6 +195,37 @@ __global__ __launch_bounds__(256, 2) void k_wcontract(int64_t npad, int64_t jlen
         accq[cb] = (Acc){0, 0, 0, 0};
         accv[cb] = (Acc){0, 0, 0, 0};
     }
+    // the partials are FP64: FP64 sums are stored once at the end; FP32 sums
+    // go in after each run of kFp32Run points
+    double *Yb = Yout + (int64_t)blockIdx.z * npad * 3 * Pp;
+    bool first = true;
+    auto flush = [&]() {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = ibase + WTraits<T>::row(r, kq);
+                const int64_t col = col0 + cb * 16 + m;
+                if constexpr (sizeof(T) == 8) {
+                    Yb[(row * 3 + 0) * Pp + col] = accp[cb][r];
+                    Yb[(row * 3 + 1) * Pp + col] = accq[cb][r];
+                    Yb[(row * 3 + 2) * Pp + col] = accv[cb][r];
+                } else {
+                    add_partial(Yb + (row * 3 + 0) * Pp + col, accp[cb][r], first);
+                    add_partial(Yb + (row * 3 + 1) * Pp + col, accq[cb][r], first);
+                    add_partial(Yb + (row * 3 + 2) * Pp + col, accv[cb][r], first);
+                }
+            }
+            mem_order();
+        }
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+            accp[cb] = (Acc){0, 0, 0, 0};
+            accq[cb] = (Acc){0, 0, 0, 0};
+            accv[cb] = (Acc){0, 0, 0, 0};
+        }
+        first = false;
+    };
     for (int64_t j0 = jbeg; j0 < jend; j0 += kJC) {
         __syncthreads();
         if (tid < kJC) {
@@ -225,18 +257,10 @@ __global__ __launch_bounds__(256, 2) void k_wcontract(int64_t npad, int64_t jlen
                 accv[cb] = WTraits<T>::mfma(kvv, xv, accv[cb]);
             }
         }
+        if constexpr (sizeof(T) == 4)
+            if ((j0 + kJC - jbeg) % kFp32Run == 0 && j0 + kJC < jend) flush();
     }
-    T *Yb = Yout + (int64_t)blockIdx.z * npad * 3 * Pp;
-#pragma unroll
-    for (int cb = 0; cb < NCB; ++cb)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t row = ibase + WTraits<T>::row(r, kq);
-            const int64_t col = col0 + cb * 16 + m;
-            Yb[(row * 3 + 0) * Pp + col] = accp[cb][r];
-            Yb[(row * 3 + 1) * Pp + col] = accq[cb][r];
-            Yb[(row * 3 + 2) * Pp + col] = accv[cb][r];
-        }
+    flush();
 }
 
 // ---------------------------------------------------------------------------
@@ -296,8 +320,9 @@ __global__ __launch_bounds__(256, 2) void k_wcontract_bf16x3(int64_t npad, int64
                                                              const float4 *__restrict__ P1,
                                                              const bf16x8 *__restrict__ Xhi,
                                                              const bf16x8 *__restrict__ Xlo,
-                                                             float *__restrict__ Yout) {
+                                                             double *__restrict__ Yout) {
     constexpr int NC = NCB * 16;
+    static_assert(kFp32Run % 32 == 0, "FP32 runs end on block boundaries");
     constexpr int UNITS = NC * 4;                       // 8-bf16 units per block and array
     constexpr int PER = (UNITS + 255) / 256;
     typedef bf16x8 Buf[UNITS];
@@ -318,6 +343,34 @@ __global__ __launch_bounds__(256, 2) void k_wcontract_bf16x3(int64_t npad, int64
         accq[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
         accv[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
     }
+    // the FP32 sums of each run of kFp32Run points go into this split's FP64
+    // partials (D layout: item r of lane l holds row 4 (l/16) + r, column l%16)
+    double *Yb = Yout + (int64_t)blockIdx.z * npad * 3 * Pp;
+    bool first = true;
+    auto flush = [&]() {
+        // one base address formed here (the empty asm keeps it from being
+        // hoisted out of the loop)
+        int64_t off = (ibase + 4 * g) * 3 * Pp + col0 + m;
+        asm volatile("" : "+v"(off));
+        double *y = Yb + off;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                add_partial(y + (3 * r + 0) * (int64_t)Pp + cb * 16, accp[cb][r], first);
+                add_partial(y + (3 * r + 1) * (int64_t)Pp + cb * 16, accq[cb][r], first);
+                add_partial(y + (3 * r + 2) * (int64_t)Pp + cb * 16, accv[cb][r], first);
+            }
+            mem_order();
+        }
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+            accp[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
+            accq[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
+            accv[cb] = (v4f){0.f, 0.f, 0.f, 0.f};
+        }
+        first = false;
+    };
     bf16x8 rh[PER], rl[PER];
     auto load_x = [&](int64_t blk) {
         const int64_t base = ((blk / 32) * Pp + col0) * 4;
@@ -396,21 +449,11 @@ __global__ __launch_bounds__(256, 2) void k_wcontract_bf16x3(int64_t npad, int64
         }
         cur = nxt;
         if (more) store_x(buf ^ 1);
+        if ((j0 + 32 - jbeg) % kFp32Run == 0 && more) flush();
         __syncthreads();
         buf ^= 1;
     }
-    // D layout: item r of lane l holds row 4 (l/16) + r, column l%16
-    float *Yb = Yout + (int64_t)blockIdx.z * npad * 3 * Pp;
-#pragma unroll
-    for (int cb = 0; cb < NCB; ++cb)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t row = ibase + 4 * g + r;
-            const int64_t col = col0 + cb * 16 + m;
-            Yb[(row * 3 + 0) * Pp + col] = accp[cb][r];
-            Yb[(row * 3 + 1) * Pp + col] = accq[cb][r];
-            Yb[(row * 3 + 2) * Pp + col] = accv[cb][r];
-        }
+    flush();
 }
 
 template <int NCB>
@@ -427,12 +470,12 @@ hipError_t run_w(vv10_plan *p, const WeightWork &ww) {
     } else if (p->prec == VV10_MIXED_FP32) {
         k_wcontract<float, NCB><<<grid, 256, 0, p->stream>>>(
             p->npad, ws.jlen, ws.Pp, p->P0f, p->P1f, static_cast<const float *>(ww.Xv),
-            static_cast<float *>(ww.Ypart));
+            static_cast<double *>(ww.Ypart));
     } else {
         const bf16x8 *xh = static_cast<const bf16x8 *>(ww.Xv);
         const bf16x8 *xl = xh + (size_t)p->npad * ws.Pp / 8;
         k_wcontract_bf16x3<NCB><<<grid, 256, 0, p->stream>>>(
-            p->npad, ws.jlen, ws.Pp, p->P0f, p->P1f, xh, xl, static_cast<float *>(ww.Ypart));
+            p->npad, ws.jlen, ws.Pp, p->P0f, p->P1f, xh, xl, static_cast<double *>(ww.Ypart));
     }
     return hipGetLastError();
 }

@@ -1,0 +1,141 @@
+"""Mixed-precision contractions whose j splits span several FP32 runs.
+
+The mixed modes sum at most 4096 consecutive j points of a tile in FP32 and
+then add those sums into the split's FP64 partials (a store for the first
+run, read-add-writes for the later ones).  One j split over a 13500-point
+grid therefore takes the FP32 -> FP64 step four times.  Every kernel form
+that does it is checked here against the FP64 oracle at the stated bounds
+(Section II.A energy and potential; Section II.B E_{G,G}, E_{G,gr},
+E_{gr,gr}, and with moving weights the weight terms), one split against the
+automatic splits, the screened path against the unscreened one, and the
+batch's persistent kernel against the single path, bitwise."""
+import functools
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import normwise, relerr
+from paper_2208_14639_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+E_REL, H_ABS, V_NORM = 1e-6, 1e-5, 1e-5
+RUN = 4096                 # j points summed in FP32 before the FP64 partials
+# (n_water, points per atom, seed): 3 waters, P = 27, two 16-column blocks
+# (the four-wave split-BF16 form), N = 13500; 13 waters, P = 117, eight
+# blocks (the eight-wave form), N = 11700
+CASES = {"two_blocks": (3, 1500, 41), "eight_blocks": (13, 300, 43)}
+# one split against the automatic ones: the same sums in another order
+ORDER_NORM = 1e-6
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+@functools.lru_cache(maxsize=4)
+def case(name):
+    p = inputs.make_problem(*CASES[name])
+    g, gx = oracle.problem_inputs(p)
+    args = (p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b, p.C, p.rho_x, gx)
+    H, _ = oracle.hessian_terms(*args)
+    e, fr, fg = oracle.energy_potential(p.coords, p.weights, p.rho, g, p.b, p.C)
+    return p, dict(hess=H, energy=e, f_rho=fr, f_gamma=fg)
+
+
+def _run(torch, p, prec, tiles=None, tau=0.0, w_x=None):
+    from paper_2208_14639_amd import vv10
+    with vv10.Plan(p, prec=prec, tiles=tiles, screening=tau) as pl:
+        out = pl.nuclear_terms(p.rho_x, p.grad_rho_x, hess=True, energy=True, potential=True,
+                               w_x=w_x)
+        used = vv10.vv10_get_tiles(pl.handle)
+        torch.cuda.synchronize()
+        res = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in out.items()}
+    return res, used
+
+
+def _errs(res, ref):
+    return dict(energy=relerr(float(np.asarray(res["energy"]).reshape(-1)[0]), ref["energy"]),
+                f_rho=normwise(res["f_rho"], ref["f_rho"]),
+                f_gamma=normwise(res["f_gamma"], ref["f_gamma"]),
+                hess_abs=float(np.max(np.abs(res["hess"] - ref["hess"]))))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_one_split_several_runs_vs_oracle(torch, name, prec):
+    p, ref = case(name)
+    one, used = _run(torch, p, prec, tiles=(1, 0))
+    assert used[0] == 1 and p.n_grid > 2 * RUN, (used, p.n_grid)
+    auto, used_auto = _run(torch, p, prec)
+    e1, ea = _errs(one, ref), _errs(auto, ref)
+    d = normwise(one["hess"], auto["hess"])
+    _say("   ", name, prec, "one split", e1, "auto", used_auto, ea, "one vs auto", d)
+    for errs in (e1, ea):
+        assert errs["energy"] <= E_REL, errs
+        assert errs["hess_abs"] <= H_ABS, errs
+        assert errs["f_rho"] <= V_NORM and errs["f_gamma"] <= V_NORM, errs
+    assert np.array_equal(one["hess"], one["hess"].T)
+    assert d <= ORDER_NORM, d
+
+
+def test_screened_one_split(torch):
+    """The screened split-BF16 form with one split of 14400 points (shell
+    order): close to the unscreened one split, and within the bounds of the
+    oracle."""
+    p = inputs.make_problem(6, 800, 45, radial_order=True)
+    a, _ = _run(torch, p, "bf16x3", tiles=(1, 0))
+    b, used = _run(torch, p, "bf16x3", tiles=(1, 0), tau=1e-8)
+    assert used[0] == 1
+    d = normwise(b["hess"], a["hess"])
+    g, gx = oracle.problem_inputs(p)
+    H0, _ = oracle.hessian_terms(p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b, p.C,
+                                 p.rho_x, gx)
+    err = float(np.max(np.abs(b["hess"] - H0)))
+    _say("    screened vs unscreened", d, "screened vs oracle", err)
+    assert d <= 3e-6 and err <= H_ABS
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_weighted_one_split(torch, prec):
+    """Moving (Becke) weights with one split of 6600 points: the weight
+    contraction (split-BF16: fused with the main one) takes the FP32 -> FP64
+    step too; the Hessian with its weight terms against the oracle."""
+    p = inputs.make_problem(2, 1100, 47, weights="becke")
+    res, used = _run(torch, p, prec, tiles=(1, 0), w_x=p.w_x)
+    assert used[0] == 1 and p.n_grid > RUN
+    g, gx = oracle.problem_inputs(p)
+    H0, _ = oracle.hessian_terms(p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b, p.C,
+                                 p.rho_x, gx, w_x=p.w_x)
+    err = float(np.max(np.abs(res["hess"] - H0)))
+    _say("   ", prec, "weighted, one split: H max abs err", err)
+    assert err <= H_ABS
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_batch_long_splits_bitwise(torch, prec):
+    """The persistent kernel runs the same tile functions: a batch whose
+    molecules each take one split of several FP32 runs equals the single
+    path with the same tiles, bitwise."""
+    from paper_2208_14639_amd import vv10
+    probs = [inputs.make_problem(3, 1500, 41), inputs.make_problem(2, 1200, 49)]
+    tiles = [(1, 0), (1, 0)]
+    with vv10.Batch(probs, prec=prec, tiles=tiles) as b:
+        e, blocks = b.run()
+        torch.cuda.synchronize()
+        Hb = [h.cpu().numpy() for h in blocks]
+    for m, p in enumerate(probs):
+        with vv10.Plan(p, prec=prec, tiles=tiles[m]) as pl:
+            out = pl.hessian_terms(p.rho_x, p.grad_rho_x)
+            torch.cuda.synchronize()
+            H = out["hess"].cpu().numpy()
+        assert np.array_equal(H, Hb[m]), (m, normwise(Hb[m], H))
