@@ -19,11 +19,6 @@ __device__ __forceinline__ double rcp64(double x) {
     return r;
 }
 
-// The mixed contractions sum at most kFp32Run consecutive j points of a tile
-// in FP32 (the MFMA accumulators) and then add those sums into the tile's
-// rows of the split's FP64 partials: FP32 within a tile, FP64 across tiles.
-constexpr int kFp32Run = 4096;
-
 // Adds a tile's FP32 sum v into its FP64 partial y; first: y is written,
 // not read.  Each partial element has a single writer (one lane of one
 // workgroup), so a plain read-add-write suffices and the order of the

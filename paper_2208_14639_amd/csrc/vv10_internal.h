@@ -34,6 +34,12 @@ enum Integral { I_E = 0, I_U, I_W, I_A, I_B, I_C, NI };
 
 constexpr int kPad = 256;        // npad is a multiple of this
 constexpr int kGridTile = 64;    // i points per grid-term tile (one wave)
+// The mixed contractions sum at most kFp32Run consecutive j points of a tile
+// in FP32 (the MFMA accumulators) and then add those sums into the tile's
+// rows of the split's FP64 partials: FP32 within a tile, FP64 across tiles.
+// Each addition after the first re-reads the rows (about 32 N^2 P / kFp32Run
+// bytes over a contraction), which sets the length.
+constexpr int kFp32Run = 8192;
 
 struct Workspace {
     int32_t P = 0, Pp = 0;       // perturbations and padded column count
