@@ -454,21 +454,33 @@ __device__ __forceinline__ void tile_bf16x3(int64_t npad, int64_t jlen, int32_t 
         constexpr int PER2 = (2 * UNITS + NT - 1) / NT;
         // X of points j .. j + 31 straight from global memory into LDS
         // (global_load_lds_dwordx4: lane l of a wave writes the 16 bytes at
-        // the wave's LDS base + 16 l, so unit e = tid + NT k lands at unit e)
+        // the wave's LDS base + 16 l, so unit e = tid + NT k lands at unit e).
+        // The source of piece k is a stage base (uniform, in SGPRs) plus a
+        // per-lane 32-bit offset fixed over the stages; the LDS base is
+        // uniform too, so a piece costs no 64-bit address arithmetic.
+        const int wv = __builtin_amdgcn_readfirstlane(wave);
+        uint32_t xoff[PER2];
+#pragma unroll
+        for (int k = 0; k < PER2; ++k) {
+            const int e = wv * 64 + NT * k + lane;
+            const int sub = e >= UNITS;
+            xoff[k] = (uint32_t)(sub * Pp * 4 + (e - sub * UNITS));
+        }
         auto load2 = [&](int64_t j, Buf2 &H, Buf2 &L) {
+            const int64_t base = ((j / 16) * Pp + col0) * 4;
+            const bf16x8 *bh = Xhi + base, *bl = Xlo + base;
 #pragma unroll
             for (int k = 0; k < PER2; ++k) {
-                const int e0 = wave * 64 + NT * k;      // first unit of this wave (uniform)
-                if (e0 < 2 * UNITS) {                    // 2 UNITS is a multiple of 64
-                    const int e = e0 + lane;
-                    const int sub = e >= UNITS;
-                    const int64_t src = ((j / 16 + sub) * Pp + col0) * 4 + (e - sub * UNITS);
+                const int e0 = wv * 64 + NT * k;        // first unit of this wave (uniform)
+                // 2 UNITS is a multiple of 64; when it is one of NT, every
+                // wave loads PER2 pieces
+                if ((2 * UNITS) % NT == 0 || e0 < 2 * UNITS) {
                     __builtin_amdgcn_global_load_lds(
-                        static_cast<const void *>(Xhi + src),
+                        static_cast<const void *>(bh + xoff[k]),
                         reinterpret_cast<__attribute__((address_space(3))) void *>(
                             reinterpret_cast<uintptr_t>(&H[e0])), 16, 0, 0);
                     __builtin_amdgcn_global_load_lds(
-                        static_cast<const void *>(Xlo + src),
+                        static_cast<const void *>(bl + xoff[k]),
                         reinterpret_cast<__attribute__((address_space(3))) void *>(
                             reinterpret_cast<uintptr_t>(&L[e0])), 16, 0, 0);
                 }
