@@ -222,12 +222,14 @@ __device__ __forceinline__ void tile_f32(int64_t npad, int64_t jlen, int32_t Pp,
         double *y = Yb + off;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
+            float vp[NCB], vq[NCB];
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) {
-                add_partial(y + (2 * r + 0) * (int64_t)Pp + cb * 16, accp[cb][r], first);
-                add_partial(y + (2 * r + 1) * (int64_t)Pp + cb * 16, accq[cb][r], first);
+                vp[cb] = accp[cb][r];
+                vq[cb] = accq[cb][r];
             }
-            mem_order();
+            add_row<NCB>(y + (2 * r + 0) * (int64_t)Pp, vp, first);
+            add_row<NCB>(y + (2 * r + 1) * (int64_t)Pp, vq, first);
         }
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
@@ -391,12 +393,14 @@ __device__ __forceinline__ void tile_bf16x3(int64_t npad, int64_t jlen, int32_t 
         double *y = Yb + off;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
+            float vp[NCB], vq[NCB];
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) {
-                add_partial(y + (2 * r + 0) * (int64_t)Pp + cb * 16, accp[cb][r], first);
-                add_partial(y + (2 * r + 1) * (int64_t)Pp + cb * 16, accq[cb][r], first);
+                vp[cb] = accp[cb][r];
+                vq[cb] = accq[cb][r];
             }
-            mem_order();
+            add_row<NCB>(y + (2 * r + 0) * (int64_t)Pp, vp, first);
+            add_row<NCB>(y + (2 * r + 1) * (int64_t)Pp, vq, first);
         }
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
@@ -405,26 +409,26 @@ __device__ __forceinline__ void tile_bf16x3(int64_t npad, int64_t jlen, int32_t 
         }
         first = false;
     };
-    // X block staging: thread tid moves units tid + NT k of the block
-    bf16x8 rh[PER], rl[PER];
-    auto load_x = [&](int64_t blk) {
+    // X of one 16-point block straight from global memory into LDS buffer b
+    // (global_load_lds_dwordx4: lane l of a wave writes the 16 bytes at the
+    // wave's LDS base + 16 l, so unit e = tid + NT k lands at unit e; the
+    // source is a uniform block base plus the lane's unit)
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    auto dma_x = [&](int64_t blk, int b) {
         const int64_t base = ((blk / 16) * Pp + col0) * 4;
+        const bf16x8 *bh = Xhi + base, *bl = Xlo + base;
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
-            const int e = tid + NT * k;
-            if (e < UNITS) {
-                rh[k] = Xhi[base + e];
-                rl[k] = Xlo[base + e];
-            }
-        }
-    };
-    auto store_x = [&](int buf) {
-#pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            const int e = tid + NT * k;
-            if (e < UNITS) {
-                sH[buf][e] = rh[k];
-                sL[buf][e] = rl[k];
+            const int e0 = wv * 64 + NT * k;            // first unit of this wave (uniform)
+            if (UNITS % NT == 0 || e0 < UNITS) {        // UNITS is a multiple of 64
+                __builtin_amdgcn_global_load_lds(
+                    static_cast<const void *>(bh + e0 + lane),
+                    reinterpret_cast<__attribute__((address_space(3))) void *>(
+                        reinterpret_cast<uintptr_t>(&sH[b][e0])), 16, 0, 0);
+                __builtin_amdgcn_global_load_lds(
+                    static_cast<const void *>(bl + e0 + lane),
+                    reinterpret_cast<__attribute__((address_space(3))) void *>(
+                        reinterpret_cast<uintptr_t>(&sL[b][e0])), 16, 0, 0);
             }
         }
     };
@@ -531,10 +535,10 @@ __device__ __forceinline__ void tile_bf16x3(int64_t npad, int64_t jlen, int32_t 
         }
     } else {
     load_pts(jbeg);
-    load_x(jbeg);
+    dma_x(jbeg, 0);
     Aops cur = form_A(a0, a1, n0, n1);
     load_pts(jbeg + 16);
-    store_x(0);
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's LDS loads are done
     __syncthreads();
     int buf = 0;
     for (int64_t j0 = jbeg; j0 < jend; j0 += 16) {
@@ -543,7 +547,7 @@ __device__ __forceinline__ void tile_bf16x3(int64_t npad, int64_t jlen, int32_t 
         // cleared; K_pq, K_qp, K_qq vanish there (R = 0)
         if (j0 == ibase) mask_self(cur, m, g);
         const bool more = j0 + 16 < jend;
-        if (more) load_x(j0 + 16);
+        if (more) dma_x(j0 + 16, buf ^ 1);   // every wave finished reading it
         const bf16x8 *hp = sH[buf] + m * 4 + g;
         const bf16x8 *lp = sL[buf] + m * 4 + g;
         Aops nxt;
@@ -599,8 +603,8 @@ __device__ __forceinline__ void tile_bf16x3(int64_t npad, int64_t jlen, int32_t 
             load_pts(j0 + 32);
         }
         cur = nxt;
-        if (more) store_x(buf ^ 1);
         if ((j0 + 16 - jbeg) % kFp32Run == 0 && more) flush();
+        __builtin_amdgcn_s_waitcnt(0);   // this wave's LDS loads of the next block
         __syncthreads();
         buf ^= 1;
     }
@@ -930,15 +934,20 @@ __global__ __launch_bounds__(256, 2) void k_contract_bf16x3_w(
         double *yb = Yb + ob, *yw = Yw + ow;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
+            float v[5][NCB];
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) {
-                add_partial(yb + (2 * r + 0) * (int64_t)Pp + cb * 16, accp[cb][r], first);
-                add_partial(yb + (2 * r + 1) * (int64_t)Pp + cb * 16, accq[cb][r], first);
-                add_partial(yw + (3 * r + 0) * (int64_t)Pp + cb * 16, awp[cb][r], first);
-                add_partial(yw + (3 * r + 1) * (int64_t)Pp + cb * 16, awq[cb][r], first);
-                add_partial(yw + (3 * r + 2) * (int64_t)Pp + cb * 16, awv[cb][r], first);
+                v[0][cb] = accp[cb][r];
+                v[1][cb] = accq[cb][r];
+                v[2][cb] = awp[cb][r];
+                v[3][cb] = awq[cb][r];
+                v[4][cb] = awv[cb][r];
             }
-            mem_order();
+            add_row<NCB>(yb + (2 * r + 0) * (int64_t)Pp, v[0], first);
+            add_row<NCB>(yb + (2 * r + 1) * (int64_t)Pp, v[1], first);
+            add_row<NCB>(yw + (3 * r + 0) * (int64_t)Pp, v[2], first);
+            add_row<NCB>(yw + (3 * r + 1) * (int64_t)Pp, v[3], first);
+            add_row<NCB>(yw + (3 * r + 2) * (int64_t)Pp, v[4], first);
         }
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {

@@ -19,18 +19,31 @@ __device__ __forceinline__ double rcp64(double x) {
     return r;
 }
 
-// Adds a tile's FP32 sum v into its FP64 partial y; first: y is written,
-// not read.  Each partial element has a single writer (one lane of one
-// workgroup), so a plain read-add-write suffices and the order of the
-// additions, and the result, are fixed.
-__device__ __forceinline__ void add_partial(double *y, float v, bool first) {
-    *y = first ? (double)v : *y + (double)v;
-}
-
 // Barrier for the compiler only: the memory accesses before it are issued
-// before those after it (a flush adds one row of a tile at a time, so that
-// its loads do not all occupy registers at once).
+// before those after it.
 __device__ __forceinline__ void mem_order() { asm volatile("" ::: "memory"); }
+
+// Adds one tile row's FP32 sums v[0..N) into its FP64 partials y[0], y[16],
+// ..., y[16 (N - 1)] (N column blocks of 16); first: y is written, not read.
+// Each partial element has a single writer (one lane of one workgroup), so a
+// plain read-add-write suffices and the order of the additions, and the
+// result, are fixed.  The row's loads are issued together before the adds
+// (one wait per row), and rows are added one at a time so that their loads
+// do not all occupy registers at once.
+template <int N>
+__device__ __forceinline__ void add_row(double *y, const float *v, bool first) {
+    if (first) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) y[16 * k] = (double)v[k];
+    } else {
+        double t[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) t[k] = y[16 * k];
+#pragma unroll
+        for (int k = 0; k < N; ++k) y[16 * k] = t[k] + (double)v[k];
+    }
+    mem_order();
+}
 
 // 1/x in FP32 (hardware estimate, about 1 ulp).
 __device__ __forceinline__ float rcp32(float x) { return __builtin_amdgcn_rcpf(x); }

@@ -201,22 +201,28 @@ __global__ __launch_bounds__(256, 2) void k_wcontract(int64_t npad, int64_t jlen
     bool first = true;
     auto flush = [&]() {
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) {
+        for (int r = 0; r < 4; ++r) {
+            const int64_t row = ibase + WTraits<T>::row(r, kq);
+            double *y = Yb + row * 3 * Pp + col0 + m;
+            if constexpr (sizeof(T) == 8) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t row = ibase + WTraits<T>::row(r, kq);
-                const int64_t col = col0 + cb * 16 + m;
-                if constexpr (sizeof(T) == 8) {
-                    Yb[(row * 3 + 0) * Pp + col] = accp[cb][r];
-                    Yb[(row * 3 + 1) * Pp + col] = accq[cb][r];
-                    Yb[(row * 3 + 2) * Pp + col] = accv[cb][r];
-                } else {
-                    add_partial(Yb + (row * 3 + 0) * Pp + col, accp[cb][r], first);
-                    add_partial(Yb + (row * 3 + 1) * Pp + col, accq[cb][r], first);
-                    add_partial(Yb + (row * 3 + 2) * Pp + col, accv[cb][r], first);
+                for (int cb = 0; cb < NCB; ++cb) {
+                    y[0 * Pp + cb * 16] = accp[cb][r];
+                    y[1 * Pp + cb * 16] = accq[cb][r];
+                    y[2 * Pp + cb * 16] = accv[cb][r];
                 }
+            } else {
+                float v[3][NCB];
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) {
+                    v[0][cb] = accp[cb][r];
+                    v[1][cb] = accq[cb][r];
+                    v[2][cb] = accv[cb][r];
+                }
+                add_row<NCB>(y + 0 * (int64_t)Pp, v[0], first);
+                add_row<NCB>(y + 1 * (int64_t)Pp, v[1], first);
+                add_row<NCB>(y + 2 * (int64_t)Pp, v[2], first);
             }
-            mem_order();
         }
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
@@ -355,13 +361,16 @@ __global__ __launch_bounds__(256, 2) void k_wcontract_bf16x3(int64_t npad, int64
         double *y = Yb + off;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
+            float v[3][NCB];
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) {
-                add_partial(y + (3 * r + 0) * (int64_t)Pp + cb * 16, accp[cb][r], first);
-                add_partial(y + (3 * r + 1) * (int64_t)Pp + cb * 16, accq[cb][r], first);
-                add_partial(y + (3 * r + 2) * (int64_t)Pp + cb * 16, accv[cb][r], first);
+                v[0][cb] = accp[cb][r];
+                v[1][cb] = accq[cb][r];
+                v[2][cb] = accv[cb][r];
             }
-            mem_order();
+            add_row<NCB>(y + (3 * r + 0) * (int64_t)Pp, v[0], first);
+            add_row<NCB>(y + (3 * r + 1) * (int64_t)Pp, v[1], first);
+            add_row<NCB>(y + (3 * r + 2) * (int64_t)Pp, v[2], first);
         }
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
