@@ -17,9 +17,10 @@
 //
 // This is a dense (2N x 2N) x (2N x P) product whose left operand is never
 // stored: every (i, j) pair is formed once, in registers, directly in the
-// MFMA A-operand layout.  X chunks are staged in LDS and shared by the four
-// waves of a workgroup; every wave owns 16 outer points and all columns of
-// its column group, with accumulators in registers.  Three arithmetic modes:
+// MFMA A-operand layout.  X chunks are staged in LDS and shared by the waves
+// of a workgroup (four, or eight for the split-BF16 form with eight or more
+// column blocks); every wave owns 16 outer points and all columns of its
+// column group, with accumulators in registers.  Three arithmetic modes:
 //
 //  FP64:   one pair per lane per 16 x 4 block, four v_mfma_f64_16x16x4 per
 //          16 columns (K_pp X_p, K_pq X_q into Y_p; K_qp X_p, K_qq X_q into Y_q).
@@ -337,11 +338,12 @@ __device__ __forceinline__ void mask_self(Aops &A, int m, int g) {
     A.pl = bf16_apply_mask(A.pl, k);
 }
 
-// Software pipeline per wave, one 16-point j block per stage:
-//  * the X block (hi and lo, all columns of the group) is double-buffered in
-//    LDS; the next block is loaded into registers while this block's MFMAs
-//    run, stored to the other buffer afterwards, and one barrier per stage
-//    publishes it;
+// Software pipeline per wave (four waves and 16-point stages below eight
+// column blocks; eight waves and 32-point stages from eight on):
+//  * the X of a stage (hi and lo, all columns of the group) is
+//    double-buffered in LDS; the next stage's X goes straight from global
+//    memory into the other buffer (global_load_lds) while this stage's MFMAs
+//    run, and one wait plus one barrier per stage publish it;
 //  * the VALU forms the A operands of the next block from point data loaded
 //    one block ahead straight from global memory; the instruction scheduler
 //    interleaves it with the MFMAs of the current block (measured: forcing a

@@ -1,8 +1,10 @@
 """Parity across the launch shapes of the Hessian call (Section II.B: E_{G,G},
 E_{G,gr}, E_{gr,gr}) through the C ABI, against the FP64 oracle: every
-16-column block count of one column group (1 to 8 waters, P = 9 to 72),
-two column groups in every precision (22 waters, P = 198), and explicit
-tile overrides (j splits of the contraction, atom groups of the grid pass).
+16-column block count of one column group (1 to 21 waters, P = 9 to 189:
+the mixed modes' four-wave and eight-wave split-BF16 forms, FP64 up to
+eight blocks and two groups above), two column groups in every precision
+(22 waters, P = 198), and explicit tile overrides (j splits of the
+contraction, atom groups of the grid pass) for both split-BF16 forms.
 """
 import functools
 import sys
@@ -90,6 +92,18 @@ def test_column_block_counts(torch, n_water, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("n_water", [10, 12, 14, 16, 17, 19, 21])
+def test_column_block_counts_wide(torch, n_water, prec):
+    """Six (P = 90) to twelve (P = 189) 16-column blocks: one column group in
+    the mixed modes (split-BF16: four waves below eight blocks, eight waves
+    in 32-point stages from eight on), two groups of five or six blocks in
+    FP64 above eight; 30 points per atom, every tile ragged."""
+    p, ref = case(n_water, 30, 300 + n_water)
+    res, used = _run(torch, p, prec)
+    _check(res, ref, prec, f"{n_water} waters, tiles {used}")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_two_column_groups(torch, prec):
     """22 waters, 30 points per atom (N = 1980, P = 198, thirteen 16-column
     blocks): two column groups of seven blocks in every precision (a block
@@ -115,3 +129,23 @@ def test_tile_overrides(torch, prec):
                 first = res["hess"]
             else:
                 assert normwise(res["hess"], first) <= (1e-13 if prec == "fp64" else 1e-6)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_tile_overrides_eight_blocks(torch, prec):
+    """14 waters, 40 points per atom (N = 1680, padded to 1792, P = 126:
+    eight 16-column blocks, the eight-wave split-BF16 form): j splits 1, 3
+    (608 points, an odd number of 32-point stages, and a last split of 576)
+    and 7 (256 points), grid-pass atom groups 1 and 7."""
+    p, ref = case(14, 40, 314)
+    assert p.n_grid == 1680
+    first = None
+    for js in (1, 3, 7):
+        for bg in (1, 7):
+            res, used = _run(torch, p, prec, tiles=(js, bg))
+            assert used == (js, bg), used
+            _check(res, ref, prec, f"tiles ({js}, {bg})")
+            if first is None:
+                first = res["hess"]
+            else:
+                assert normwise(res["hess"], first) <= 1e-6
