@@ -3,9 +3,13 @@
 // Every molecule keeps its own plan and workspace (prepared and validated
 // eagerly).  vv10_batch_run captures, once, one HIP graph:
 //   fork -> per molecule: perturbation packing (branches on side streams)
-//   join -> one persistent kernel over the work list of all molecules: the
-//           grid-pass items (grid-position intermediates with the pair
-//           integrals), then the contraction items, each kind largest first
+//   join -> split-BF16 only: an eight-wave persistent kernel over the
+//           contraction items of the molecules with eight or more column
+//           blocks per group (the standalone kernel's form for them);
+//           then one persistent kernel over the work list of all molecules:
+//           the grid-pass items (grid-position intermediates with the pair
+//           integrals), then the other contraction items, each kind largest
+//           first
 //   fork -> per molecule: pair integrals summed over atom groups, potential
 //           and energy, Hessian assembly -> join
 // and replays it while the caller's pointers stay the same.
@@ -24,10 +28,12 @@ struct vv10_batch {
     std::vector<vv10_plan *> plans;
     std::vector<int64_t> rx_off, gx_off, h_off;
     vv10::BatchMol *d_mols = nullptr;
-    vv10::BatchItem *d_items = nullptr;
-    int32_t *d_counter = nullptr;
-    int64_t n_items = 0;
+    vv10::BatchItem *d_items = nullptr;        // the main list, then the wide one
+    int32_t *d_counter = nullptr;              // [2]: main, wide
+    int64_t n_items = 0;                       // main list
+    int64_t n_wide = 0;                        // wide list (split-BF16)
     int32_t n_blocks = 0;
+    int32_t n_wide_blocks = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     const void *cap_ptr[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -75,6 +81,10 @@ hipError_t enqueue_batch(vv10_batch *b, const double *rho_x, const double *grad_
         e = hipEventRecord(b->ev[1 + k], b->side[k]);
         if (e == hipSuccess) e = hipStreamWaitEvent(b->cap, b->ev[1 + k], 0);
     }
+    if (e == hipSuccess && b->n_wide > 0)
+        e = vv10::launch_contract_persistent_wide(b->d_mols, b->d_items + b->n_items,
+                                                  (int32_t)b->n_wide, b->d_counter + 1,
+                                                  b->n_wide_blocks, b->cap);
     if (e == hipSuccess)
         e = vv10::launch_contract_persistent(b->prec, b->d_mols, b->d_items, (int32_t)b->n_items,
                                             b->d_counter, b->n_blocks, b->cap);
@@ -140,8 +150,8 @@ vv10_status vv10_batch_create(const vv10_params *params, int32_t n_mol, const in
     // work list: contraction items (molecule, column group, j split, i tile)
     // and grid items (molecule, atom group, kGridItemTiles grid tiles)
     std::vector<vv10::BatchMol> mols;
-    std::vector<vv10::BatchItem> items, gitems;
-    std::vector<int64_t> cost, gcost;
+    std::vector<vv10::BatchItem> items, gitems, witems;
+    std::vector<int64_t> cost, gcost, wcost;
     const int W = vv10::persistent_waves(prec);   // waves per persistent workgroup
     if (st == VV10_OK) {
         for (size_t m = 0; m < b->plans.size(); ++m) {
@@ -183,12 +193,16 @@ vv10_status vv10_batch_create(const vv10_params *params, int32_t n_mol, const in
                     gcost.push_back(nt * pts * kGridCost);
                 }
             }
+            // split-BF16 with kWideMinNcb or more column blocks: the wide
+            // list, i tiles of 128 points (npad is a multiple of 256)
+            const bool wide = prec == VV10_MIXED_BF16X3 && ws.ncb >= vv10::kWideMinNcb;
+            const int Wc = wide ? 8 : W;
             for (int32_t s = 0; s < ws.jsplit; ++s) {
                 const int64_t jl = std::min<int64_t>(ws.jlen, p->npad - (int64_t)s * ws.jlen);
                 for (int32_t g = 0; g < ws.ngroups; ++g)
-                    for (int64_t t = 0; t < p->npad / (16 * W); ++t) {
-                        items.push_back({(int32_t)m, g, s, (int32_t)t});
-                        cost.push_back(jl * ws.ncb * W / 4);
+                    for (int64_t t = 0; t < p->npad / (16 * Wc); ++t) {
+                        (wide ? witems : items).push_back({(int32_t)m, g, s, (int32_t)t});
+                        (wide ? wcost : cost).push_back(jl * ws.ncb * Wc / 4);
                     }
             }
         }
@@ -207,9 +221,11 @@ vv10_status vv10_batch_create(const vv10_params *params, int32_t n_mol, const in
         std::vector<vv10::BatchItem> all;
         by_cost(gitems, gcost, all);
         by_cost(items, cost, all);
+        b->n_items = (int64_t)all.size();
+        by_cost(witems, wcost, all);
+        b->n_wide = (int64_t)all.size() - b->n_items;
         items.swap(all);
-        b->n_items = (int64_t)items.size();
-        if (b->n_items > INT32_MAX) st = VV10_E_ARG;
+        if (b->n_items > INT32_MAX || b->n_wide > INT32_MAX) st = VV10_E_ARG;
     }
     if (st == VV10_OK) {
         hipError_t e = vv10::dev_alloc(reinterpret_cast<void **>(&b->d_mols),
@@ -217,7 +233,7 @@ vv10_status vv10_batch_create(const vv10_params *params, int32_t n_mol, const in
         if (e == hipSuccess)
             e = vv10::dev_alloc(reinterpret_cast<void **>(&b->d_items),
                                 std::max<size_t>(1, items.size()) * sizeof(vv10::BatchItem));
-        if (e == hipSuccess) e = vv10::dev_alloc(reinterpret_cast<void **>(&b->d_counter), sizeof(int32_t));
+        if (e == hipSuccess) e = vv10::dev_alloc(reinterpret_cast<void **>(&b->d_counter), 2 * sizeof(int32_t));
         if (e == hipSuccess)
             e = hipMemcpy(b->d_mols, mols.data(), mols.size() * sizeof(vv10::BatchMol), hipMemcpyHostToDevice);
         if (e == hipSuccess && !items.empty())
@@ -239,6 +255,12 @@ vv10_status vv10_batch_create(const vv10_params *params, int32_t n_mol, const in
             if (per_cu <= 0) per_cu = 1;
             b->n_blocks = (int32_t)std::min<int64_t>((int64_t)per_cu * b->plans[0]->num_cu,
                                                      std::max<int64_t>(1, b->n_items));
+            if (b->n_wide > 0) {
+                int per_cu_w = vv10::persistent_wide_blocks_per_cu();
+                if (per_cu_w <= 0) per_cu_w = 1;
+                b->n_wide_blocks = (int32_t)std::min<int64_t>(
+                    (int64_t)per_cu_w * b->plans[0]->num_cu, b->n_wide);
+            }
         }
         st = status_of(e);
     }
@@ -286,7 +308,7 @@ vv10_status vv10_batch_run(vv10_batch *b, const double *rho_x, const double *gra
 
 vv10_status vv10_batch_info(const vv10_batch *b, int64_t *n_items, int32_t *n_workgroups) {
     if (!b) return VV10_E_STATE;
-    if (n_items) *n_items = b->n_items;
+    if (n_items) *n_items = b->n_items + b->n_wide;
     if (n_workgroups) *n_workgroups = b->n_blocks;
     return VV10_OK;
 }

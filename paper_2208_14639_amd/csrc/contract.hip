@@ -648,7 +648,7 @@ __global__ __launch_bounds__(256, 2) void k_contract_f32(int64_t npad, int64_t j
 // four waves in 16-point stages keep three to four waves per SIMD (the
 // 32-point stages' registers would drop it to two).
 template <int NCB>
-constexpr int bf16_waves() { return NCB >= 8 ? 8 : 4; }
+constexpr int bf16_waves() { return NCB >= kWideMinNcb ? 8 : 4; }
 
 template <int NCB, bool SCR>
 __global__ __launch_bounds__(64 * bf16_waves<NCB>(), 8 / bf16_waves<NCB>()) void k_contract_bf16x3(int64_t npad, int64_t jlen, int32_t Pp,
@@ -765,9 +765,11 @@ struct PersistentTraits<VV10_MIXED_FP32> {
 template <>
 struct PersistentTraits<VV10_MIXED_BF16X3> {
     // four waves: the eight-wave form of the standalone kernel (32-point
-    // stages, X straight into two LDS buffers) spills 32 registers here,
-    // where every column count shares one register allocation, and was
-    // slower on the 64-cluster batch (2.95 s per launch against 2.86 s)
+    // stages, X straight into two LDS buffers) spilled 32 registers here
+    // when every column count shared one register allocation and was slower
+    // on the 64-cluster batch (2.95 s per launch against 2.86 s); molecules
+    // with kWideMinNcb or more blocks per group run it in a kernel of their
+    // own (k_contract_persistent_wide), the rest and the grid items here
     static constexpr int kMaxNcb = 12;
     static constexpr int kSmem = smem_bf16x3<12>();
     static constexpr int kWaves = 4;
@@ -841,6 +843,47 @@ __global__ __launch_bounds__(64 * PersistentTraits<PREC>::kWaves, 8 / Persistent
         break;
             VV10_CASE(1) VV10_CASE(2) VV10_CASE(3) VV10_CASE(4) VV10_CASE(5) VV10_CASE(6)
             VV10_CASE(7) VV10_CASE(8) VV10_CASE(9) VV10_CASE(10) VV10_CASE(11) VV10_CASE(12)
+#undef VV10_CASE
+            default: break;
+        }
+        __syncthreads();                   // LDS is reused by the next item
+    }
+}
+
+// Wide items of a split-BF16 batch (eight to twelve column blocks): the
+// eight-wave form of the standalone kernel (128-point i tiles, 32-point
+// stages with X straight into two LDS buffers) pulls them from a list and a
+// counter of its own.  Only these column counts share its register
+// allocation, which keeps the form's two waves per SIMD without spills
+// (every column count in one kernel spilled it).
+__global__ __launch_bounds__(512, 1) void k_contract_persistent_wide(
+    const BatchMol *__restrict__ mols, const BatchItem *__restrict__ items, int32_t n_items,
+    int32_t *__restrict__ counter) {
+    static_assert(bf16_waves<kWideMinNcb>() == 8 && bf16_waves<12>() == 8,
+                  "wide items run the eight-wave form");
+    __shared__ __attribute__((aligned(16))) char smem[smem_bf16x3<12>()];
+    __shared__ __attribute__((aligned(16))) char smem2[smem_bf16x3<12>()];
+    __shared__ int32_t next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+        __syncthreads();
+        const int32_t k = __builtin_amdgcn_readfirstlane(next);   // uniform: item data in SGPRs
+        __syncthreads();
+        if (k >= n_items) break;          // every workgroup leaves once the list is drained
+        const BatchItem it = items[k];
+        const BatchMol d = mols[it.mol];
+        const bf16x8 *xh = static_cast<const bf16x8 *>(d.X);
+        const bf16x8 *xl = xh + d.npad * d.Pp * 2 / 8;
+        const float4 *p0 = static_cast<const float4 *>(d.P0);
+        const float4 *p1 = static_cast<const float4 *>(d.P1);
+        double *y = static_cast<double *>(d.Ypart);
+        switch (d.ncb) {
+#define VV10_CASE(c)                                                                         \
+    case c:                                                                                  \
+        tile_bf16x3<c, false, 8>(d.npad, d.jlen, d.Pp, p0, p1, xh, xl, y, it.itile, it.grp, \
+                                 it.split, smem, nullptr, smem2);                            \
+        break;
+            VV10_CASE(8) VV10_CASE(9) VV10_CASE(10) VV10_CASE(11) VV10_CASE(12)
 #undef VV10_CASE
             default: break;
         }
@@ -1141,6 +1184,22 @@ int persistent_blocks_per_cu(vv10_precision prec) {
     return nb;
 }
 
+int persistent_wide_blocks_per_cu() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_contract_persistent_wide, 512, 0) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return nb;
+}
+hipError_t launch_contract_persistent_wide(const BatchMol *mols, const BatchItem *items,
+                                           int32_t n_items, int32_t *counter, int n_blocks,
+                                           hipStream_t stream) {
+    k_zero_counter<<<1, 1, 0, stream>>>(counter);
+    k_contract_persistent_wide<<<n_blocks, 512, 0, stream>>>(mols, items, n_items, counter);
+    return hipGetLastError();
+}
 hipError_t launch_contract_persistent(vv10_precision prec, const BatchMol *mols,
                                       const BatchItem *items, int32_t n_items, int32_t *counter,
                                       int n_blocks, hipStream_t stream) {

@@ -187,6 +187,14 @@ int persistent_blocks_per_cu(vv10_precision prec);
 hipError_t launch_contract_persistent(vv10_precision prec, const BatchMol *mols,
                                       const BatchItem *items, int32_t n_items, int32_t *counter,
                                       int n_blocks, hipStream_t stream);
+// Split-BF16 molecules with at least kWideMinNcb column blocks per group run
+// their contraction items in a second persistent kernel of eight waves
+// (i tiles of 128 points), the standalone kernel's form for these counts.
+constexpr int kWideMinNcb = 8;
+int persistent_wide_blocks_per_cu();
+hipError_t launch_contract_persistent_wide(const BatchMol *mols, const BatchItem *items,
+                                           int32_t n_items, int32_t *counter, int n_blocks,
+                                           hipStream_t stream);
 
 // Device allocations of the library (per-device caching allocator).
 hipError_t dev_alloc(void **ptr, size_t bytes);

@@ -94,6 +94,35 @@ def test_batch_mixed_bounds_vs_oracle(torch):
         assert relerr(e[m], e0) <= 1e-6
 
 
+@pytest.mark.parametrize("tiles", [None, [(3, 0), (1, 0), (1, 0), (2, 0)]])
+def test_batch_wide_items(torch, tiles):
+    """Split-BF16 molecules of eight or more column blocks (14, 17 and 21
+    waters: 8, 10 and 12 blocks) run their contraction items in the
+    eight-wave persistent kernel, a 2-water one in the four-wave kernel with
+    the grid items: every Hessian equals the single path's bitwise (the
+    standalone kernel runs the same eight-wave form), and the largest is
+    within the bounds of the oracle (Section II.B E^{AB})."""
+    from paper_2208_14639_amd import vv10
+    probs = [inputs.make_problem(14, 40, 901), inputs.make_problem(2, 150, 902),
+             inputs.make_problem(21, 30, 903), inputs.make_problem(17, 30, 904)]
+    with vv10.Batch(probs, prec="bf16x3", tiles=tiles) as b:
+        e, blocks = b.run()
+        torch.cuda.synchronize()
+        n_items, n_wg = b.info()
+        _say("wide batch: items", n_items, "workgroups", n_wg)
+        Hb = [h.cpu().numpy() for h in blocks]
+    for m, p in enumerate(probs):
+        with vv10.Plan(p, prec="bf16x3", tiles=None if tiles is None else tiles[m]) as pl:
+            H = pl.hessian_terms(p.rho_x, p.grad_rho_x)["hess"].cpu().numpy()
+            torch.cuda.synchronize()
+        assert np.array_equal(H, Hb[m]), (m, normwise(Hb[m], H))
+    p = probs[2]
+    g, gx = oracle.problem_inputs(p)
+    H0, _ = oracle.hessian_terms(p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b, p.C,
+                                 p.rho_x, gx)
+    assert np.max(np.abs(Hb[2] - H0)) <= 1e-5
+
+
 def test_graph_replays_with_eager_work_between(torch):
     """Each replay of the captured graph equals the first result, with eager
     work (another plan's evaluation and host syncs) between the replays."""
