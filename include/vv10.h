@@ -408,14 +408,14 @@ vv10_status vv10_batch_create(const vv10_params *params, int32_t n_mol, const in
  *  energy      [n_mol] VV10 energies.
  *  hess        molecule m's [3 n_atom_m][3 n_atom_m] block, blocks back to back.
  * The whole evaluation is one HIP graph: the perturbation packing of every
- * molecule; in split-BF16, an eight-wave persistent kernel over the
- * contraction items of the molecules with eight or more 16-column blocks per
- * column group (the standalone contraction's form for them); then a
- * persistent kernel that pulls the other contraction items (molecule, tile,
- * column group, j split) and the grid-pass items (molecule, grid tiles, atom
- * group) of all molecules from one list (the grid items first, each kind
- * largest first); then each molecule's pair-integral sums, energy and
- * assembly as independent branches.
+ * molecule; then persistent kernels, each pulling the items of all
+ * molecules from a list of its own, largest first: in split-BF16 an
+ * eight-wave kernel over the contraction items (molecule, tile, column
+ * group, j split) of the molecules with eight or more 16-column blocks per
+ * column group (the standalone contraction's form for them), a four-wave
+ * kernel over the other contraction items, and a kernel over the grid-pass
+ * items (molecule, grid tile, atom group); then each molecule's
+ * pair-integral sums, energy and assembly as independent branches.
  * The graph is captured on the first call and replayed while the four
  * pointers stay the same.  Asynchronous on the batch's stream.
  * Each molecule's results equal those of vv10_hessian_terms on the same
@@ -425,9 +425,8 @@ vv10_status vv10_batch_create(const vv10_params *params, int32_t n_mol, const in
 vv10_status vv10_batch_run(vv10_batch *batch, const double *rho_x, const double *grad_rho_x,
                            double *energy, double *hess);
 
-/* Work items of the batch (contraction and grid-pass items of both
- * persistent kernels) and workgroups of the kernel that runs the grid
- * items. */
+/* Work items of the batch (contraction and grid-pass items of all its
+ * persistent kernels) and workgroups of its four-wave contraction kernel. */
 vv10_status vv10_batch_info(const vv10_batch *batch, int64_t *n_items, int32_t *n_workgroups);
 
 /* Destroy a batch (waits for its stream); NULL is accepted. */

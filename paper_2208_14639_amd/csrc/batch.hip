@@ -3,13 +3,12 @@
 // Every molecule keeps its own plan and workspace (prepared and validated
 // eagerly).  vv10_batch_run captures, once, one HIP graph:
 //   fork -> per molecule: perturbation packing (branches on side streams)
-//   join -> split-BF16 only: an eight-wave persistent kernel over the
-//           contraction items of the molecules with eight or more column
-//           blocks per group (the standalone kernel's form for them);
-//           then one persistent kernel over the work list of all molecules:
-//           the grid-pass items (grid-position intermediates with the pair
-//           integrals), then the other contraction items, each kind largest
-//           first
+//   join -> persistent kernels over the work lists of all molecules, each
+//           list largest first: split-BF16 only, the contraction items of
+//           the molecules with eight or more column blocks per group (eight
+//           waves, the standalone kernel's form for them); the other
+//           contraction items (four waves); the grid-pass items, one grid
+//           tile each (grid-position intermediates with the pair integrals)
 //   fork -> per molecule: pair integrals summed over atom groups, potential
 //           and energy, Hessian assembly -> join
 // and replays it while the caller's pointers stay the same.
@@ -28,12 +27,14 @@ struct vv10_batch {
     std::vector<vv10_plan *> plans;
     std::vector<int64_t> rx_off, gx_off, h_off;
     vv10::BatchMol *d_mols = nullptr;
-    vv10::BatchItem *d_items = nullptr;        // the main list, then the wide one
-    int32_t *d_counter = nullptr;              // [2]: main, wide
-    int64_t n_items = 0;                       // main list
-    int64_t n_wide = 0;                        // wide list (split-BF16)
+    vv10::BatchItem *d_items = nullptr;        // contraction, wide, grid lists
+    int32_t *d_counter = nullptr;              // [3]: one per list
+    int64_t n_items = 0;                       // contraction items (four waves)
+    int64_t n_wide = 0;                        // wide contraction items (split-BF16)
+    int64_t n_grid = 0;                        // grid items
     int32_t n_blocks = 0;
     int32_t n_wide_blocks = 0;
+    int32_t n_grid_blocks = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     const void *cap_ptr[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -85,9 +86,13 @@ hipError_t enqueue_batch(vv10_batch *b, const double *rho_x, const double *grad_
         e = vv10::launch_contract_persistent_wide(b->d_mols, b->d_items + b->n_items,
                                                   (int32_t)b->n_wide, b->d_counter + 1,
                                                   b->n_wide_blocks, b->cap);
-    if (e == hipSuccess)
+    if (e == hipSuccess && b->n_items > 0)
         e = vv10::launch_contract_persistent(b->prec, b->d_mols, b->d_items, (int32_t)b->n_items,
                                             b->d_counter, b->n_blocks, b->cap);
+    if (e == hipSuccess && b->n_grid > 0)
+        e = vv10::launch_grid_persistent(b->prec, b->d_mols, b->d_items + b->n_items + b->n_wide,
+                                         (int32_t)b->n_grid, b->d_counter + 2, b->n_grid_blocks,
+                                         b->cap);
     if (e == hipSuccess) e = hipEventRecord(b->ev[1 + K], b->cap);
     for (int k = 0; k < K && e == hipSuccess; ++k) e = hipStreamWaitEvent(b->side[k], b->ev[1 + K], 0);
     for (size_t m = 0; m < nm && e == hipSuccess; ++m) {
@@ -147,8 +152,8 @@ vv10_status vv10_batch_create(const vv10_params *params, int32_t n_mol, const in
         rx += (int64_t)3 * na * n;
         hx += (int64_t)9 * na * na;
     }
-    // work list: contraction items (molecule, column group, j split, i tile)
-    // and grid items (molecule, atom group, kGridItemTiles grid tiles)
+    // work lists: contraction items (molecule, column group, j split, i tile)
+    // and grid items (molecule, atom group, grid tile)
     std::vector<vv10::BatchMol> mols;
     std::vector<vv10::BatchItem> items, gitems, witems;
     std::vector<int64_t> cost, gcost, wcost;
@@ -179,18 +184,14 @@ vv10_status vv10_batch_create(const vv10_params *params, int32_t n_mol, const in
             d.Dpart = ws.Dpart;
             d.Igrp = ws.Igrp;
             mols.push_back(d);
-            // a grid item pairs up to W grid tiles of 64 outer points with
-            // every point of its atom group; per (64-point tile, point) it
-            // costs about kGridCost contraction units (j points x column
-            // blocks of a 64-point tile), as measured on the 20-water grid
-            constexpr int64_t kGridCost = 4;
+            // a grid item pairs one grid tile of up to 64 outer points with
+            // every point of its atom group
             for (int32_t g = 0; g < ws.bgroups; ++g) {
                 int64_t pts = 0;
                 for (int32_t B = g; B < p->n_atom; B += ws.bgroups) pts += p->seg[B + 1] - p->seg[B];
-                for (int32_t t = 0; t < p->ntiles; t += W) {
-                    const int64_t nt = std::min<int64_t>(W, p->ntiles - t);
+                for (int32_t t = 0; t < p->ntiles; ++t) {
                     gitems.push_back({(int32_t)m, g, -1, t});
-                    gcost.push_back(nt * pts * kGridCost);
+                    gcost.push_back((int64_t)p->tile_n[t] * pts);
                 }
             }
             // split-BF16 with kWideMinNcb or more column blocks: the wide
@@ -206,9 +207,9 @@ vv10_status vv10_batch_create(const vv10_params *params, int32_t n_mol, const in
                     }
             }
         }
-        // grid items first, then contraction items, each kind largest first:
-        // run side by side on one CU the two kinds slow each other more than
-        // they overlap (measured on the 64-cluster batch: interleaved in
+        // one list per kernel, each largest first: run side by side on one
+        // CU, grid and contraction items slow each other more than they
+        // overlap (measured on the 64-cluster batch: interleaved in
         // proportion to their cost 3.02 s per launch, one kind after the
         // other 2.86 s)
         auto by_cost = [](const std::vector<vv10::BatchItem> &it, const std::vector<int64_t> &c,
@@ -219,13 +220,15 @@ vv10_status vv10_batch_create(const vv10_params *params, int32_t n_mol, const in
             for (size_t k : order) out.push_back(it[k]);
         };
         std::vector<vv10::BatchItem> all;
-        by_cost(gitems, gcost, all);
         by_cost(items, cost, all);
         b->n_items = (int64_t)all.size();
         by_cost(witems, wcost, all);
         b->n_wide = (int64_t)all.size() - b->n_items;
+        by_cost(gitems, gcost, all);
+        b->n_grid = (int64_t)all.size() - b->n_items - b->n_wide;
         items.swap(all);
-        if (b->n_items > INT32_MAX || b->n_wide > INT32_MAX) st = VV10_E_ARG;
+        if (b->n_items > INT32_MAX || b->n_wide > INT32_MAX || b->n_grid > INT32_MAX)
+            st = VV10_E_ARG;
     }
     if (st == VV10_OK) {
         hipError_t e = vv10::dev_alloc(reinterpret_cast<void **>(&b->d_mols),
@@ -233,7 +236,7 @@ vv10_status vv10_batch_create(const vv10_params *params, int32_t n_mol, const in
         if (e == hipSuccess)
             e = vv10::dev_alloc(reinterpret_cast<void **>(&b->d_items),
                                 std::max<size_t>(1, items.size()) * sizeof(vv10::BatchItem));
-        if (e == hipSuccess) e = vv10::dev_alloc(reinterpret_cast<void **>(&b->d_counter), 2 * sizeof(int32_t));
+        if (e == hipSuccess) e = vv10::dev_alloc(reinterpret_cast<void **>(&b->d_counter), 3 * sizeof(int32_t));
         if (e == hipSuccess)
             e = hipMemcpy(b->d_mols, mols.data(), mols.size() * sizeof(vv10::BatchMol), hipMemcpyHostToDevice);
         if (e == hipSuccess && !items.empty())
@@ -255,6 +258,10 @@ vv10_status vv10_batch_create(const vv10_params *params, int32_t n_mol, const in
             if (per_cu <= 0) per_cu = 1;
             b->n_blocks = (int32_t)std::min<int64_t>((int64_t)per_cu * b->plans[0]->num_cu,
                                                      std::max<int64_t>(1, b->n_items));
+            int per_cu_g = vv10::persistent_grid_blocks_per_cu(prec);
+            if (per_cu_g <= 0) per_cu_g = 1;
+            b->n_grid_blocks = (int32_t)std::min<int64_t>((int64_t)per_cu_g * b->plans[0]->num_cu,
+                                                          std::max<int64_t>(1, b->n_grid));
             if (b->n_wide > 0) {
                 int per_cu_w = vv10::persistent_wide_blocks_per_cu();
                 if (per_cu_w <= 0) per_cu_w = 1;
@@ -308,7 +315,7 @@ vv10_status vv10_batch_run(vv10_batch *b, const double *rho_x, const double *gra
 
 vv10_status vv10_batch_info(const vv10_batch *b, int64_t *n_items, int32_t *n_workgroups) {
     if (!b) return VV10_E_STATE;
-    if (n_items) *n_items = b->n_items + b->n_wide;
+    if (n_items) *n_items = b->n_items + b->n_wide + b->n_grid;
     if (n_workgroups) *n_workgroups = b->n_blocks;
     return VV10_OK;
 }

@@ -795,23 +795,35 @@ __device__ __forceinline__ void run_item(const BatchMol &d, const BatchItem &it,
     }
 }
 
-// A grid item: wave w runs tile itile + w of the molecule's grid pass for
-// atom group grp (with the pair integrals, as the Hessian call forms them).
+// Grid items of a batch: one wave per workgroup pulls one grid tile of one
+// molecule and atom group at a time (with the pair integrals, as the Hessian
+// call forms them).  A kernel of its own keeps the grid pass's register
+// allocation (and the standalone grid kernel's waves per SIMD), where the
+// contraction kernels' allocations would hold it to two waves per SIMD.  At
+// four waves per SIMD the mixed form spills 8 registers; three waves without
+// spills measured slower on the 64-cluster batch (2625-2628 ms per launch
+// against 2614-2619).
 template <int PREC>
-__device__ __forceinline__ void run_grid_item(const BatchMol &d, const BatchItem &it, char *smem) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(PREC == VV10_FP64 ? 3 : 4))) void k_grid_persistent(
+    const BatchMol *__restrict__ mols, const BatchItem *__restrict__ items, int32_t n_items,
+    int32_t *__restrict__ counter) {
     using T = std::conditional_t<PREC == VV10_FP64, double, float>;
     using T4 = std::conditional_t<PREC == VV10_FP64, double4, float4>;
-    constexpr int W = PersistentTraits<PREC>::kWaves;
-    static_assert(PersistentTraits<PREC>::kSmem >= W * 2 * kGridTile * (int)sizeof(T4),
-                  "grid item chunk buffers exceed the workgroup's LDS");
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int t = it.itile + wave;
-    if (t >= d.ntiles) return;
-    T4 *sA = reinterpret_cast<T4 *>(smem) + wave * 2 * kGridTile;
-    grid_unit<T, T4, true, false>(d.n_atom, d.Pp, d.bgroups, d.npad, d.seg, d.tile_i0, d.tile_n,
-                                  d.tile_atom, static_cast<const T4 *>(d.P0),
-                                  static_cast<const T4 *>(d.P1), d.Pd, d.Z, nullptr, d.Dpart,
-                                  d.Igrp, t, it.grp, lane, sA, sA + kGridTile);
+    __shared__ T4 sA[kGridTile], sB[kGridTile];
+    const int lane = threadIdx.x;
+    for (;;) {
+        int32_t k = 0;
+        if (lane == 0) k = atomicAdd(counter, 1);
+        k = __builtin_amdgcn_readfirstlane(k);   // lane 0's value, uniform
+        if (k >= n_items) break;                  // every wave leaves once the list is drained
+        const BatchItem it = items[k];
+        const BatchMol d = mols[it.mol];
+        // grid_unit orders its LDS writes after the previous reads itself
+        grid_unit<T, T4, true, false>(d.n_atom, d.Pp, d.bgroups, d.npad, d.seg, d.tile_i0,
+                                      d.tile_n, d.tile_atom, static_cast<const T4 *>(d.P0),
+                                      static_cast<const T4 *>(d.P1), d.Pd, d.Z, nullptr, d.Dpart,
+                                      d.Igrp, it.itile, it.grp, lane, sA, sB);
+    }
 }
 
 template <int PREC>
@@ -831,11 +843,6 @@ __global__ __launch_bounds__(64 * PersistentTraits<PREC>::kWaves, 8 / Persistent
         if (k >= n_items) break;          // every workgroup leaves once the list is drained
         const BatchItem it = items[k];
         const BatchMol d = mols[it.mol];
-        if (it.split < 0) {
-            run_grid_item<PREC>(d, it, smem);
-            __syncthreads();               // LDS is reused by the next item
-            continue;
-        }
         switch (d.ncb) {
 #define VV10_CASE(c) \
     case c:          \
@@ -1198,6 +1205,33 @@ hipError_t launch_contract_persistent_wide(const BatchMol *mols, const BatchItem
                                            hipStream_t stream) {
     k_zero_counter<<<1, 1, 0, stream>>>(counter);
     k_contract_persistent_wide<<<n_blocks, 512, 0, stream>>>(mols, items, n_items, counter);
+    return hipGetLastError();
+}
+int persistent_grid_blocks_per_cu(vv10_precision prec) {
+    int nb = 0;
+    hipError_t e;
+    if (prec == VV10_FP64)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_grid_persistent<VV10_FP64>, 64, 0);
+    else if (prec == VV10_MIXED_FP32)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_grid_persistent<VV10_MIXED_FP32>, 64, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_grid_persistent<VV10_MIXED_BF16X3>, 64, 0);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return nb;
+}
+hipError_t launch_grid_persistent(vv10_precision prec, const BatchMol *mols,
+                                  const BatchItem *items, int32_t n_items, int32_t *counter,
+                                  int n_blocks, hipStream_t stream) {
+    k_zero_counter<<<1, 1, 0, stream>>>(counter);
+    if (prec == VV10_FP64)
+        k_grid_persistent<VV10_FP64><<<n_blocks, 64, 0, stream>>>(mols, items, n_items, counter);
+    else if (prec == VV10_MIXED_FP32)
+        k_grid_persistent<VV10_MIXED_FP32><<<n_blocks, 64, 0, stream>>>(mols, items, n_items, counter);
+    else
+        k_grid_persistent<VV10_MIXED_BF16X3><<<n_blocks, 64, 0, stream>>>(mols, items, n_items, counter);
     return hipGetLastError();
 }
 hipError_t launch_contract_persistent(vv10_precision prec, const BatchMol *mols,

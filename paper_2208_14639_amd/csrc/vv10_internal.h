@@ -174,11 +174,10 @@ struct BatchMol {
     const double4 *Pd;     // FP64 point data (the self pair)
     double *Z, *Dpart, *Igrp;   // grid-pass outputs, as the plan's workspace holds them
 };
-// One unit of work of the persistent kernel, whose workgroups have W =
-// persistent_waves(prec) waves: with split >= 0 a contraction item
-// (molecule, column group grp, j split, i tile itile of 16 W points); with
-// split = -1 a grid item (molecule, atom group grp, grid-pass tiles itile ..
-// itile + W - 1, one per wave).
+// One unit of work of a persistent kernel: with split >= 0 a contraction
+// item (molecule, column group grp, j split, i tile itile of 16 W points,
+// where W = persistent_waves(prec), or 8 for the wide kernel); with
+// split = -1 a grid item (molecule, atom group grp, grid-pass tile itile).
 struct BatchItem {
     int32_t mol, grp, split, itile;
 };
@@ -191,6 +190,12 @@ hipError_t launch_contract_persistent(vv10_precision prec, const BatchMol *mols,
 // their contraction items in a second persistent kernel of eight waves
 // (i tiles of 128 points), the standalone kernel's form for these counts.
 constexpr int kWideMinNcb = 8;
+// The grid items (one grid tile of one molecule and atom group each) run in
+// a persistent kernel of their own, one wave per workgroup.
+int persistent_grid_blocks_per_cu(vv10_precision prec);
+hipError_t launch_grid_persistent(vv10_precision prec, const BatchMol *mols,
+                                  const BatchItem *items, int32_t n_items, int32_t *counter,
+                                  int n_blocks, hipStream_t stream);
 int persistent_wide_blocks_per_cu();
 hipError_t launch_contract_persistent_wide(const BatchMol *mols, const BatchItem *items,
                                            int32_t n_items, int32_t *counter, int n_blocks,
