@@ -65,11 +65,48 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def code_text(src):
+    """C/C++/HIP source without its comments and with runs of white space
+    collapsed: an edit of a comment leaves it unchanged, any edit of the code
+    changes it (string and character literals are kept as written)."""
+    out, code, i, n = [], [], 0, len(src)
+
+    def flush():
+        out.extend("".join(code).split())
+        code.clear()
+
+    while i < n:
+        c = src[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            flush()
+            out.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            j = src.find("\n", i)
+            code.append(" ")
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            code.append(" ")
+            i = n if j < 0 else j + 2
+        else:
+            code.append(c)
+            i += 1
+    flush()
+    return " ".join(out)
+
+
 def source_sha(rels):
+    """Hash of the code (not the comments) of the source files that a
+    counter record was taken from."""
     h = hashlib.sha256()
     for rel in rels:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
+            h.update(code_text(f.read()).encode())
+        h.update(b"\0")
     return h.hexdigest()[:16]
 
 

@@ -740,13 +740,13 @@ auto dispatch_ncb(int ncb, F &&f) -> decltype(f(std::integral_constant<int, 1>{}
 }
 
 // ---------------------------------------------------------------------------
-// Persistent batched kernel: a fixed grid of workgroups pulls work items from
-// an integer counter.  A contraction item is (molecule, i tile, column group,
-// j split); a grid item is a group of grid-pass tiles of one molecule for one
-// atom group, one tile per wave (the grid-position intermediates and the pair
-// integrals).  The host lists the grid items first, then the contraction
-// items, each kind largest first.  Every item writes its own output slab, so
-// the results do not depend on which workgroup ran which item.
+// Persistent batched kernels: a fixed grid of workgroups pulls work items
+// from an integer counter, one list and counter per kernel, each list
+// largest first.  A contraction item is (molecule, i tile, column group,
+// j split); a grid item is one grid-pass tile of one molecule for one atom
+// group (the grid-position intermediates and the pair integrals).  Every
+// item writes its own output slab, so the results do not depend on which
+// workgroup ran which item.
 // ---------------------------------------------------------------------------
 template <int PREC>
 struct PersistentTraits;
