@@ -813,13 +813,23 @@ def main():
 
     t_con = stage_ms["contract"] * 1e-3
     mfma_key = {"fp64": "mfma_f64", "fp32": "mfma_f32", "bf16x3": "mfma_bf16"}[args.prec]
-    achieved = FLOPS_PER_PAIR_PERT * pair_pert / t_con / 1e12
-    # the weighted workload runs the same main contraction launch on the same grid
-    traffic = measured_traffic("contract", base if weighted else args.workload, args.prec)
-    roofline = dict(bound="mfma", kernel=f"k_contract_{args.prec}", achieved=achieved,
-                    peak=PEAKS_TFLOPS[mfma_key], unit="TFLOP/s",
+    # split-BF16 with moving weights and at most four 16-column blocks: the
+    # library runs the main and the weight contraction as one kernel (the
+    # contraction stage), and the weight stage is the weight packing alone
+    fused_w = weighted and args.prec == "bf16x3" and args.screen == 0 and (P + 15) // 16 <= 4
+    flops_con = FLOPS_PER_PAIR_PERT + (FLOPS_PER_PAIR_PERT_W if fused_w else 0)
+    achieved = flops_con * pair_pert / t_con / 1e12
+    # the weighted workload runs the same main contraction launch on the same
+    # grid, unless the two contractions are fused (no counter record for that)
+    traffic = None if fused_w else measured_traffic("contract", base if weighted else args.workload,
+                                                    args.prec)
+    roofline = dict(bound="mfma", kernel="k_contract_bf16x3_w" if fused_w else f"k_contract_{args.prec}",
+                    achieved=achieved, peak=PEAKS_TFLOPS[mfma_key], unit="TFLOP/s",
                     frac=achieved / PEAKS_TFLOPS[mfma_key], traffic=traffic)
-    rec = counter_record("contract", base if weighted else args.workload, args.prec)
+    if fused_w:
+        roofline["flops_per_pair_pert"] = flops_con
+    rec = None if fused_w else counter_record("contract", base if weighted else args.workload,
+                                              args.prec)
     if rec is not None and "valu_issue_busy" in rec:
         # what limits the kernel, from the committed counter summary of the same launch
         roofline["issue"] = {"valu_issue_busy": rec["valu_issue_busy"], "mfma_busy": rec["mfma_busy"],
@@ -871,12 +881,18 @@ def main():
                               "pairs_per_s": float(n) * n / (e_ms * 1e-3),
                               "roofline": pair_pass_roofline(p, "k_pair", e_ms, args.prec)}
     if weighted:
-        t_w = stage_ms["weights"] * 1e-3
-        aw = FLOPS_PER_PAIR_PERT_W * pair_pert / t_w / 1e12
         out["config"]["weights"] = "becke"
-        out["weights_kernel"] = dict(bound="mfma", kernel=f"k_wcontract_{args.prec}", achieved=aw,
-                                     peak=PEAKS_TFLOPS[mfma_key], unit="TFLOP/s",
-                                     frac=aw / PEAKS_TFLOPS[mfma_key], stage_ms=stage_ms["weights"])
+        if fused_w:
+            # the weight rows are contracted inside `roofline`'s kernel
+            out["weights_kernel"] = dict(fused_with="k_contract_bf16x3_w",
+                                         packing_ms=stage_ms["weights"])
+        else:
+            t_w = stage_ms["weights"] * 1e-3
+            aw = FLOPS_PER_PAIR_PERT_W * pair_pert / t_w / 1e12
+            out["weights_kernel"] = dict(bound="mfma", kernel=f"k_wcontract_{args.prec}",
+                                         achieved=aw, peak=PEAKS_TFLOPS[mfma_key],
+                                         unit="TFLOP/s", frac=aw / PEAKS_TFLOPS[mfma_key],
+                                         stage_ms=stage_ms["weights"])
 
     if args.shells:
         out["config"]["point_order"] = "radial shells"
