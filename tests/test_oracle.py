@@ -155,6 +155,46 @@ def test_brute_force_energy_tiny():
     assert abs(e - tot) < 1e-14 * abs(tot)
 
 
+def test_energy_invariances():
+    """Section II.A energy on 40 random points: unchanged (to rounding) by a
+    rigid rotation and translation of all points, by a permutation of the
+    points with their data, and by splitting one point into two coincident
+    points of half its weight.  The last holds only if the double sum is
+    bilinear in the weights and keeps the self pair j = i (the two halves
+    pair with each other at R = 0 exactly as the whole point pairs with
+    itself); a sum that left the self pair out, or weighted a pair by w_i
+    alone, fails it."""
+    rng = np.random.default_rng(7)
+    n = 40
+    coords = rng.normal(scale=2.0, size=(n, 3))
+    w = rng.uniform(0.05, 1.0, n)
+    rho = rng.uniform(0.01, 3.0, n)
+    gam = rng.uniform(0.0, 2.0, n)
+    e0, _, _ = oracle.energy_potential(coords, w, rho, gam, B6, C01)
+    # rotation (QR of a random matrix) and translation
+    q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    e1, _, _ = oracle.energy_potential(coords @ q.T + np.array([1.5, -0.7, 3.2]), w, rho, gam,
+                                       B6, C01)
+    assert abs(e1 - e0) < 1e-13 * abs(e0)
+    perm = rng.permutation(n)
+    e2, _, _ = oracle.energy_potential(coords[perm], w[perm], rho[perm], gam[perm], B6, C01)
+    assert abs(e2 - e0) < 1e-13 * abs(e0)
+    k = 11
+    c3 = np.vstack([coords, coords[k:k + 1]])
+    w3 = np.concatenate([w, [0.5 * w[k]]])
+    w3[k] *= 0.5
+    r3 = np.concatenate([rho, [rho[k]]])
+    g3 = np.concatenate([gam, [gam[k]]])
+    e3, _, _ = oracle.energy_potential(c3, w3, r3, g3, B6, C01)
+    assert abs(e3 - e0) < 1e-13 * abs(e0)
+    # and the split is not an identity of any weighting: doubling one
+    # point's weight changes the energy
+    w4 = w.copy()
+    w4[k] *= 2.0
+    e4, _, _ = oracle.energy_potential(coords, w4, rho, gam, B6, C01)
+    assert abs(e4 - e0) > 1e-6 * abs(e0)
+
+
 # --------------------------------------------------------------------------
 # Potential and second-derivative matrices (Sections II.A, II.B)
 # --------------------------------------------------------------------------
