@@ -434,6 +434,35 @@ __device__ __forceinline__ void tile_bf16x3(int64_t npad, int64_t jlen, int32_t 
             }
         }
     };
+    // Screened form: X of a block through registers (loaded before the
+    // block's MFMAs, stored to the other buffer after them).  Its pair
+    // arithmetic sits between the column blocks' MFMA groups and waits for
+    // point data there; with X loads straight into LDS pending, the compiler
+    // makes that wait a full one (it treats the load counter as unordered),
+    // which also waited for the next block's X (screened 20-water
+    // contraction 52.5 ms that way, 44.9 ms through registers).
+    bf16x8 rh[PER], rl[PER];
+    auto load_x = [&](int64_t blk) {
+        const int64_t base = ((blk / 16) * Pp + col0) * 4;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = tid + NT * k;
+            if (e < UNITS) {
+                rh[k] = Xhi[base + e];
+                rl[k] = Xlo[base + e];
+            }
+        }
+    };
+    auto store_x = [&](int b) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = tid + NT * k;
+            if (e < UNITS) {
+                sH[b][e] = rh[k];
+                sL[b][e] = rl[k];
+            }
+        }
+    };
     // point data of this lane's 4 j of a block: j = blk + 4 g + jj
     float4 n0[4], n1[4];
     auto load_pts = [&](int64_t blk) {
@@ -537,7 +566,12 @@ __device__ __forceinline__ void tile_bf16x3(int64_t npad, int64_t jlen, int32_t 
         }
     } else {
     load_pts(jbeg);
-    dma_x(jbeg, 0);
+    if constexpr (SCR) {
+        load_x(jbeg);
+        store_x(0);
+    } else {
+        dma_x(jbeg, 0);
+    }
     Aops cur = form_A(a0, a1, n0, n1);
     load_pts(jbeg + 16);
     __builtin_amdgcn_s_waitcnt(0);   // this wave's LDS loads are done
@@ -549,7 +583,10 @@ __device__ __forceinline__ void tile_bf16x3(int64_t npad, int64_t jlen, int32_t 
         // cleared; K_pq, K_qp, K_qq vanish there (R = 0)
         if (j0 == ibase) mask_self(cur, m, g);
         const bool more = j0 + 16 < jend;
-        if (more) dma_x(j0 + 16, buf ^ 1);   // every wave finished reading it
+        if (more) {
+            if constexpr (SCR) load_x(j0 + 16);
+            else dma_x(j0 + 16, buf ^ 1);   // every wave finished reading it
+        }
         const bf16x8 *hp = sH[buf] + m * 4 + g;
         const bf16x8 *lp = sL[buf] + m * 4 + g;
         Aops nxt;
@@ -605,6 +642,9 @@ __device__ __forceinline__ void tile_bf16x3(int64_t npad, int64_t jlen, int32_t 
             load_pts(j0 + 32);
         }
         cur = nxt;
+        if constexpr (SCR) {
+            if (more) store_x(buf ^ 1);
+        }
         if ((j0 + 16 - jbeg) % kFp32Run == 0 && more) flush();
         __builtin_amdgcn_s_waitcnt(0);   // this wave's LDS loads of the next block
         __syncthreads();
@@ -646,12 +686,16 @@ __global__ __launch_bounds__(256, 2) void k_contract_f32(int64_t npad, int64_t j
 // and eight waves share each staged X block in 32-point stages (one barrier
 // per two MFMA blocks: 56.5 -> 53.0 ms on the 20-water grid); with fewer,
 // four waves in 16-point stages keep three to four waves per SIMD (the
-// 32-point stages' registers would drop it to two).
-template <int NCB>
-constexpr int bf16_waves() { return NCB >= kWideMinNcb ? 8 : 4; }
+// 32-point stages' registers would drop it to two).  The screened kernels
+// skip MFMA blocks behind branches in 16-point stages: four waves, so that
+// two workgroups share a CU and their waves do not wait at one barrier (with
+// eight waves the screened 20-water contraction took 55.1 ms against 49.4
+// unscreened).
+template <int NCB, bool SCR = false>
+constexpr int bf16_waves() { return !SCR && NCB >= kWideMinNcb ? 8 : 4; }
 
 template <int NCB, bool SCR>
-__global__ __launch_bounds__(64 * bf16_waves<NCB>(), 8 / bf16_waves<NCB>()) void k_contract_bf16x3(int64_t npad, int64_t jlen, int32_t Pp,
+__global__ __launch_bounds__(64 * (bf16_waves<NCB, SCR>()), 8 / (bf16_waves<NCB, SCR>())) void k_contract_bf16x3(int64_t npad, int64_t jlen, int32_t Pp,
                                                             const float4 *__restrict__ P0,
                                                             const float4 *__restrict__ P1,
                                                             const bf16x8 *__restrict__ Xhi,
@@ -660,8 +704,8 @@ __global__ __launch_bounds__(64 * bf16_waves<NCB>(), 8 / bf16_waves<NCB>()) void
                                                             const uint32_t *__restrict__ mask) {
     __shared__ __attribute__((aligned(16))) char smem[smem_bf16x3<NCB>()];
     // the second stage buffer of the eight-wave form (a one-byte dummy otherwise)
-    __shared__ __attribute__((aligned(16))) char smem2[bf16_waves<NCB>() == 8 ? smem_bf16x3<NCB>() : 1];
-    tile_bf16x3<NCB, SCR, bf16_waves<NCB>()>(npad, jlen, Pp, P0, P1, Xhi, Xlo, Yout,
+    __shared__ __attribute__((aligned(16))) char smem2[bf16_waves<NCB, SCR>() == 8 ? smem_bf16x3<NCB>() : 1];
+    tile_bf16x3<NCB, SCR, bf16_waves<NCB, SCR>()>(npad, jlen, Pp, P0, P1, Xhi, Xlo, Yout,
                                              blockIdx.x, blockIdx.y, blockIdx.z, smem, mask,
                                              smem2);
 }
@@ -684,7 +728,7 @@ hipError_t run_mode(vv10_plan *p, const Workspace &ws) {
     } else {
         const bf16x8 *xh = static_cast<const bf16x8 *>(ws.X);
         const bf16x8 *xl = xh + (size_t)p->npad * ws.Pp * 2 / 8;
-        constexpr int W = bf16_waves<NCB>();
+        constexpr int W = bf16_waves<NCB, SCR>();
         dim3 gridb((unsigned)(p->npad / (16 * W)), (unsigned)ws.ngroups, (unsigned)ws.jsplit);
         k_contract_bf16x3<NCB, SCR><<<gridb, 64 * W, 0, p->stream>>>(
             p->npad, ws.jlen, ws.Pp, p->P0f, p->P1f, xh, xl, static_cast<double *>(ws.Ypart), mask);
