@@ -813,9 +813,11 @@ struct PersistentTraits<VV10_MIXED_BF16X3> {
     // when every column count shared one register allocation and was slower
     // on the 64-cluster batch (2.95 s per launch against 2.86 s); molecules
     // with kWideMinNcb or more blocks per group run it in a kernel of their
-    // own (k_contract_persistent_wide), the rest and the grid items here
-    static constexpr int kMaxNcb = 12;
-    static constexpr int kSmem = smem_bf16x3<12>();
+    // own (k_contract_persistent_wide), so this one serves the narrower
+    // counts only, whose smaller register allocation leaves room for more
+    // waves per SIMD
+    static constexpr int kMaxNcb = kWideMinNcb - 1;
+    static constexpr int kSmem = smem_bf16x3<kWideMinNcb - 1>();
     static constexpr int kWaves = 4;
 };
 
