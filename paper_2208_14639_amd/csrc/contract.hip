@@ -439,8 +439,9 @@ __device__ __forceinline__ void tile_bf16x3(int64_t npad, int64_t jlen, int32_t 
     // arithmetic sits between the column blocks' MFMA groups and waits for
     // point data there; with X loads straight into LDS pending, the compiler
     // makes that wait a full one (it treats the load counter as unordered),
-    // which also waited for the next block's X (screened 20-water
-    // contraction 52.5 ms that way, 44.9 ms through registers).
+    // which also waited for the next block's X (measured with this form at
+    // twelve column blocks on the 20-water grid: 52.5 ms that way, 44.9 ms
+    // through registers).
     bf16x8 rh[PER], rl[PER];
     auto load_x = [&](int64_t blk) {
         const int64_t base = ((blk / 16) * Pp + col0) * 4;
@@ -473,7 +474,7 @@ __device__ __forceinline__ void tile_bf16x3(int64_t npad, int64_t jlen, int32_t 
             n1[jj] = P1[jq + jj];
         }
     };
-    if constexpr (!SCR && WAVES == 8) {
+    if constexpr (WAVES == 8) {
         // Stages of 32 points: the X of two 16-point blocks is staged at
         // once and the two blocks' MFMAs run between one pair of barriers.
         // The A operands alternate between two register sets, each formed
@@ -521,9 +522,14 @@ __device__ __forceinline__ void tile_bf16x3(int64_t npad, int64_t jlen, int32_t 
                 }
             }
         };
-        auto mfmas = [&](const Aops &A, const bf16x8 *hp, const bf16x8 *lp) {
+        // screened: a column block whose mask bit is clear skips its MFMAs
+        // (the mask word of the 16-point block at jb)
+        auto mfmas = [&](const Aops &A, const bf16x8 *hp, const bf16x8 *lp, int64_t jb) {
+            uint32_t mw = ~0u;
+            if constexpr (SCR) mw = mask[(jb >> 4) * ((Pp >> 4) / NCB) + grp];
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) {
+                if (SCR && !((mw >> cb) & 1u)) continue;
                 const bf16x8 bh = hp[cb * 64], bl = lp[cb * 64];
                 accp[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.ph, bh, accp[cb], 0, 0, 0);
                 accq[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.qh, bh, accq[cb], 0, 0, 0);
@@ -548,11 +554,11 @@ __device__ __forceinline__ void tile_bf16x3(int64_t npad, int64_t jlen, int32_t 
             if (j0 == ibase) mask_self(cur, m, g);
             Aops alt = form_A(a0, a1, n0, n1);      // points j0 + 16 ..
             load_pts(j0 + 32);
-            mfmas(cur, Hc + m * 4 + g, Lc + m * 4 + g);
+            mfmas(cur, Hc + m * 4 + g, Lc + m * 4 + g, j0);
             if (j0 + 16 == ibase) mask_self(alt, m, g);
             cur = form_A(a0, a1, n0, n1);           // points j0 + 32 ..
             load_pts(j0 + 48);
-            mfmas(alt, Hc + UNITS + m * 4 + g, Lc + UNITS + m * 4 + g);
+            mfmas(alt, Hc + UNITS + m * 4 + g, Lc + UNITS + m * 4 + g, j0 + 16);
             __builtin_amdgcn_s_waitcnt(0);   // this wave's LDS loads of the next stage
             __syncthreads();
         };
@@ -686,16 +692,15 @@ __global__ __launch_bounds__(256, 2) void k_contract_f32(int64_t npad, int64_t j
 // and eight waves share each staged X block in 32-point stages (one barrier
 // per two MFMA blocks: 56.5 -> 53.0 ms on the 20-water grid); with fewer,
 // four waves in 16-point stages keep three to four waves per SIMD (the
-// 32-point stages' registers would drop it to two).  The screened kernels
-// skip MFMA blocks behind branches in 16-point stages: four waves, so that
-// two workgroups share a CU and their waves do not wait at one barrier (with
-// eight waves the screened 20-water contraction took 55.1 ms against 49.4
-// unscreened).
-template <int NCB, bool SCR = false>
-constexpr int bf16_waves() { return !SCR && NCB >= kWideMinNcb ? 8 : 4; }
+// 32-point stages' registers would drop it to two).  Screened, the
+// eight-wave form skips a column block's MFMAs behind a branch (its MFMA and
+// VALU work do not overlap anyway: screened 20-water contraction 37.3 ms,
+// against 45.0 in the four-wave screened form and 49-50 unscreened).
+template <int NCB>
+constexpr int bf16_waves() { return NCB >= kWideMinNcb ? 8 : 4; }
 
 template <int NCB, bool SCR>
-__global__ __launch_bounds__(64 * (bf16_waves<NCB, SCR>()), 8 / (bf16_waves<NCB, SCR>())) void k_contract_bf16x3(int64_t npad, int64_t jlen, int32_t Pp,
+__global__ __launch_bounds__(64 * bf16_waves<NCB>(), 8 / bf16_waves<NCB>()) void k_contract_bf16x3(int64_t npad, int64_t jlen, int32_t Pp,
                                                             const float4 *__restrict__ P0,
                                                             const float4 *__restrict__ P1,
                                                             const bf16x8 *__restrict__ Xhi,
@@ -704,8 +709,8 @@ __global__ __launch_bounds__(64 * (bf16_waves<NCB, SCR>()), 8 / (bf16_waves<NCB,
                                                             const uint32_t *__restrict__ mask) {
     __shared__ __attribute__((aligned(16))) char smem[smem_bf16x3<NCB>()];
     // the second stage buffer of the eight-wave form (a one-byte dummy otherwise)
-    __shared__ __attribute__((aligned(16))) char smem2[bf16_waves<NCB, SCR>() == 8 ? smem_bf16x3<NCB>() : 1];
-    tile_bf16x3<NCB, SCR, bf16_waves<NCB, SCR>()>(npad, jlen, Pp, P0, P1, Xhi, Xlo, Yout,
+    __shared__ __attribute__((aligned(16))) char smem2[bf16_waves<NCB>() == 8 ? smem_bf16x3<NCB>() : 1];
+    tile_bf16x3<NCB, SCR, bf16_waves<NCB>()>(npad, jlen, Pp, P0, P1, Xhi, Xlo, Yout,
                                              blockIdx.x, blockIdx.y, blockIdx.z, smem, mask,
                                              smem2);
 }
@@ -728,7 +733,7 @@ hipError_t run_mode(vv10_plan *p, const Workspace &ws) {
     } else {
         const bf16x8 *xh = static_cast<const bf16x8 *>(ws.X);
         const bf16x8 *xl = xh + (size_t)p->npad * ws.Pp * 2 / 8;
-        constexpr int W = bf16_waves<NCB, SCR>();
+        constexpr int W = bf16_waves<NCB>();
         dim3 gridb((unsigned)(p->npad / (16 * W)), (unsigned)ws.ngroups, (unsigned)ws.jsplit);
         k_contract_bf16x3<NCB, SCR><<<gridb, 64 * W, 0, p->stream>>>(
             p->npad, ws.jlen, ws.Pp, p->P0f, p->P1f, xh, xl, static_cast<double *>(ws.Ypart), mask);
