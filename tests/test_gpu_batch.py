@@ -94,25 +94,27 @@ def test_batch_mixed_bounds_vs_oracle(torch):
         assert relerr(e[m], e0) <= 1e-6
 
 
-@pytest.mark.parametrize("tiles", [None, [(3, 0), (1, 0), (1, 0), (2, 0)]])
-def test_batch_wide_items(torch, tiles):
-    """Split-BF16 molecules of eight or more column blocks (14, 17 and 21
-    waters: 8, 10 and 12 blocks) run their contraction items in the
-    eight-wave persistent kernel, a 2-water one in the four-wave kernel with
-    the grid items: every Hessian equals the single path's bitwise (the
-    standalone kernel runs the same eight-wave form), and the largest is
-    within the bounds of the oracle (Section II.B E^{AB})."""
+@pytest.mark.parametrize("prec,tiles", [("bf16x3", None), ("bf16x3", [(3, 0), (1, 0), (1, 0), (2, 0)]),
+                                        ("fp32", None), ("fp64", None)])
+def test_batch_wide_items(torch, prec, tiles):
+    """Molecules of eight or more column blocks (14, 17 and 21 waters: 8, 10
+    and 12 blocks) beside a 2-water one.  Split-BF16 runs the wide ones'
+    contraction items in the eight-wave persistent kernel and the small
+    one's in the four-wave kernel; FP32 runs all of them in its four-wave
+    kernel at up to twelve blocks, FP64 in two column groups above eight.
+    Every Hessian equals the single path's bitwise (the same tile functions),
+    and the largest is within the bounds of the oracle (Section II.B E^{AB})."""
     from paper_2208_14639_amd import vv10
     probs = [inputs.make_problem(14, 40, 901), inputs.make_problem(2, 150, 902),
              inputs.make_problem(21, 30, 903), inputs.make_problem(17, 30, 904)]
-    with vv10.Batch(probs, prec="bf16x3", tiles=tiles) as b:
+    with vv10.Batch(probs, prec=prec, tiles=tiles) as b:
         e, blocks = b.run()
         torch.cuda.synchronize()
         n_items, n_wg = b.info()
         _say("wide batch: items", n_items, "workgroups", n_wg)
         Hb = [h.cpu().numpy() for h in blocks]
     for m, p in enumerate(probs):
-        with vv10.Plan(p, prec="bf16x3", tiles=None if tiles is None else tiles[m]) as pl:
+        with vv10.Plan(p, prec=prec, tiles=None if tiles is None else tiles[m]) as pl:
             H = pl.hessian_terms(p.rho_x, p.grad_rho_x)["hess"].cpu().numpy()
             torch.cuda.synchronize()
         assert np.array_equal(H, Hb[m]), (m, normwise(Hb[m], H))
@@ -120,7 +122,10 @@ def test_batch_wide_items(torch, tiles):
     g, gx = oracle.problem_inputs(p)
     H0, _ = oracle.hessian_terms(p.atom_of, p.n_atom, p.coords, p.weights, p.rho, g, p.b, p.C,
                                  p.rho_x, gx)
-    assert np.max(np.abs(Hb[2] - H0)) <= 1e-5
+    if prec == "fp64":
+        assert normwise(Hb[2], H0) < 1e-10
+    else:
+        assert np.max(np.abs(Hb[2] - H0)) <= 1e-5
 
 
 def test_graph_replays_with_eager_work_between(torch):
