@@ -17,8 +17,9 @@ TOL64 = 1e-10
 RESP_NORM = {"fp32": 1e-5, "bf16x3": 5e-5}
 
 # (n_water, n_pa, seed, n_t): tiny; ragged points and columns; the dimer
-# workload; n_t = 200 spans two column groups in every mode
-CASES = [(1, 8, 11, 1), (2, 37, 5, 7), (2, 700, 1001, 18), (1, 200, 21, 200)]
+# workload; n_t = 150 is one group of ten 16-column blocks (the eight-wave
+# split-BF16 form), n_t = 200 spans two column groups in every mode
+CASES = [(1, 8, 11, 1), (2, 37, 5, 7), (2, 700, 1001, 18), (1, 150, 23, 150), (1, 200, 21, 200)]
 
 
 def _say(*a):
