@@ -23,6 +23,10 @@ FOCK_NORM = {"fp32": 1e-5, "bf16x3": 5e-5}
 # dimer with a ragged tail (N = 222); several 64-point tiles and 32-point
 # j blocks (N = 900); the dimer workload size (N = 4200)
 CASES = [(1, 8, 11), (2, 37, 5), (2, 150, 21), (2, 700, 1001)]
+# wide column groups: 14 waters (P = 126: the main split-BF16 contraction in
+# its eight-wave form, the weight rows in one group of eight blocks) and 21
+# waters (P = 189: the weight rows in two groups of six), 30-40 points per atom
+WIDE = [(14, 40, 514), (21, 30, 521)]
 
 
 def _say(*a):
@@ -66,7 +70,7 @@ def _run(torch, p, prec, w_x):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
-@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("case", CASES + WIDE)
 def test_weighted_terms_vs_oracle(torch, case, prec):
     _say("weighted terms", prec, case)
     p = becke(*case)
