@@ -15,6 +15,9 @@ pytestmark = pytest.mark.gpu
 TOL64 = 1e-10
 FOCK_NORM = {"fp32": 1e-5, "bf16x3": 5e-5}
 CASES = [(1, 8, 11), (2, 37, 5), (2, 700, 1001)]
+# wide column groups: eight (14 waters, the eight-wave split-BF16 form) and
+# twelve 16-column blocks (21 waters), 30-40 points per atom
+WIDE = [(14, 40, 614), (21, 30, 621)]
 
 
 def _say(*a):
@@ -37,7 +40,7 @@ def oracle_fock(n_water, n_pa, seed):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
-@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("case", CASES + WIDE)
 def test_fock_terms_vs_oracle(torch, case, prec):
     from paper_2208_14639_amd import vv10
     _say("fock terms", prec, case)
