@@ -33,3 +33,17 @@ def test_counter_records_name_existing_sources():
             assert os.path.isfile(os.path.join(ROOT, rel)), (key, rel)
         assert os.path.isfile(os.path.join(ROOT, rec["profile"])), key
         assert rec["bytes_per_launch"] > rec["algorithmic_bytes"] > 0, key
+
+
+def test_more_than_one_gpu_is_refused():
+    """The engine runs on one GPU: asking bench.py for more exits with a
+    message (before any GPU work), also under a launcher's WORLD_SIZE."""
+    import subprocess
+    env = dict(os.environ)
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120, env=env)
+    assert r.returncode == 2 and "one GPU" in r.stderr, (r.returncode, r.stderr)
+    env["WORLD_SIZE"] = "4"
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py")],
+                       capture_output=True, text=True, timeout=120, env=env)
+    assert r.returncode == 2 and "one GPU" in r.stderr, (r.returncode, r.stderr)
